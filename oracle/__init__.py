@@ -1,0 +1,23 @@
+"""Plain FP64 CPU oracle for the photoacoustic k-space solver.
+
+TEST INFRASTRUCTURE ONLY.  This package is the independent reference the GPU
+library is checked against: slow, unfused, written from the paper's
+equations.  Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+CPU-baseline leg may import it.  It shares no code with the GPU library and
+imports nothing from it.
+
+Modules
+-------
+kspace    forward operator H and its exact transpose (sections II-A, III)
+prox      FGP dual solver of the bound-constrained TV prox (section IV)
+transfer  restriction / prolongation (section V) and FP64 reductions
+
+Parity status: every function is pinned by tests in ``tests/test_oracle_*.py``
+against closed forms, invariants, brute force or library routines, except
+the PML's profile and placement and heterogeneous lossy propagation, which
+are pinned only structurally (transpose, linearity, lossless limit).
+"""
+from . import kspace, prox, transfer  # noqa: F401
+from .kspace import make_plan, forward, adjoint  # noqa: F401
+from .prox import tv_prox  # noqa: F401
+from .transfer import restrict, prolong, dot  # noqa: F401
