@@ -1,0 +1,243 @@
+/*
+ * pat.h -- C ABI of libpat, a gfx950 (MI355X) solver for the forward and
+ * adjoint operators of photoacoustic tomography in lossy heterogeneous media
+ * (Javaherian & Holman, "A Multi-Grid Iterative Method for Photoacoustic
+ * Tomography"), and of the auxiliary operators of its multi-grid ISTA/FISTA.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Arrays are row-major with x fastest: [ny][nx] in 2D, [nz][ny][nx] in 3D.
+ *    Per-axis descriptor fields are listed in physical order (x, y, z).
+ *  - Sensor data are time-major: data[n][s], n = 0..nt-1 (sample n at t = n dt),
+ *    s = 0..n_sensors-1, float32.
+ *  - Every float array argument is a caller-owned *device* pointer (e.g. the
+ *    data_ptr() of a torch tensor on the HIP device).  Only sensor_pos and
+ *    the scalar out-parameters are host memory.  Pointers must stay valid
+ *    until the work enqueued on the stream has finished.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *    Calls enqueue work and return without waiting unless stated otherwise.
+ *  - Output arrays are overwritten, never accumulated into.
+ *  - No C++ exception crosses the ABI; every int-returning call returns one of
+ *    the PAT_* codes below.  On a non-zero return nothing was enqueued.
+ *  - A plan may be used by one stream at a time.
+ */
+#ifndef PAT_H
+#define PAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+#define PAT_OK          0
+#define PAT_EINVAL      1  /* bad descriptor, size, pointer or sensor position   */
+#define PAT_EUNSTABLE   2  /* dt above the stability bound c_max dt/dx <= 1/sqrt(d) */
+#define PAT_ENOMEM      3  /* device or host allocation failed                    */
+#define PAT_EHIP        4  /* a HIP runtime call failed                           */
+#define PAT_ENONFINITE  5  /* a non-finite pressure was seen (PAT_CHECK_FINITE)   */
+#define PAT_ENOSYS      6  /* combination not supported by this build             */
+
+/* ------------------------------------------------------------------ flags */
+#define PAT_NO_PML        0x1u  /* switch the PML off: periodic grid             */
+#define PAT_CHECK_FINITE  0x2u  /* record non-finite pressure; see pat_plan_sync */
+
+/*
+ * Grid, time axis and physics of one solver instance (one multi-grid level).
+ *
+ *  ndim         2 or 3.
+ *  n[j]         points per axis, including the PML: a power of two in
+ *               [16, 1024] (3D: [16, 256]).  n[2] is ignored in 2D.
+ *  dx[j]        spacing [m]; node i of axis j sits at origin[j] + i*dx[j].
+ *  nt           number of time samples (>= 1): data[n] is recorded at t = n dt.
+ *  dt, cfl      time step [s]; dt <= 0 selects dt = cfl * min_j dx[j] / c_max.
+ *  pml_size[j]  PML points on each side of axis j, inside the grid (0 = none);
+ *               2*pml_size[j] < n[j].
+ *  pml_alpha    PML absorption at full depth, nepers per grid point
+ *               (section VI-A uses 2).
+ *  alpha_power  power-law exponent y of the absorption (section II-A-2);
+ *               0 < y < 3, y != 1.  Ignored when alpha0_db is NULL.
+ *  n_sensors    number of point detectors (>= 1).
+ *  flags        PAT_NO_PML | PAT_CHECK_FINITE.
+ */
+typedef struct {
+  int32_t ndim;
+  int32_t n[3];
+  double dx[3];
+  double origin[3];
+  int32_t nt;
+  double dt;
+  double cfl;
+  int32_t pml_size[3];
+  double pml_alpha;
+  double alpha_power;
+  int32_t n_sensors;
+  uint32_t flags;
+} pat_desc;
+
+/* Derived quantities of a plan (filled by pat_plan_info). */
+typedef struct {
+  double dt;            /* time step actually used [s]                        */
+  double c_ref;         /* reference speed of the k-space correction = max c0  */
+  int64_t npoints;      /* grid points                                        */
+  int32_t lossy;        /* 1 when alpha0_db was given                          */
+  int32_t n_slots;      /* partial-sum slots of the sensor gather              */
+  size_t device_bytes;  /* device memory owned by the plan                     */
+  size_t state_bytes;   /* size of a forward-state snapshot (pat_forward_range) */
+} pat_info;
+
+typedef struct pat_plan pat_plan;
+typedef struct pat_batch pat_batch;
+
+/*
+ * pat_plan_create -- derive everything the time loop needs, once per level.
+ *
+ * Implements the set-up of the forward model of section II-A: the medium
+ * coefficients of equations mom, mass, state and Twelve (tau, eta from
+ * alpha0 and c0), the k-space operators, the per-axis PML (section VI-A) and
+ * the linear-interpolation sensor operator M w of section III.
+ *
+ *  c0, rho0    device, N floats each, sound speed [m/s] and ambient density
+ *              [kg/m^3], both > 0 and finite.
+ *  alpha0_db   device, N floats, absorption in dB/(MHz^y cm), or NULL for a
+ *              lossless medium (then tau = eta = 0 and no absorption pass runs).
+ *  sensor_pos  host, n_sensors*ndim doubles, physical (x, y[, z]) per sensor;
+ *              each grid coordinate (pos - origin)/dx must lie in [0, n-1].
+ *
+ * The plan copies what it needs: the caller may free the inputs afterwards.
+ * The call synchronises `stream` (it reads back c_max to fix dt).
+ * Errors: PAT_EINVAL (descriptor, NULL pointer, sensor outside the grid,
+ * non-positive or non-finite medium), PAT_EUNSTABLE, PAT_ENOMEM, PAT_EHIP.
+ */
+int pat_plan_create(pat_plan** out, const pat_desc* desc, const float* c0, const float* rho0,
+                    const float* alpha0_db, const double* sensor_pos, void* stream);
+
+/* Release a plan and its device memory (NULL is accepted). */
+void pat_plan_destroy(pat_plan* plan);
+
+/* Copy the derived quantities of `plan` into *info (host). */
+int pat_plan_info(const pat_plan* plan, pat_info* info);
+
+/*
+ * pat_forward -- the forward operator H of section III: data = H p0.
+ *
+ * Runs the k-space scheme for nt-1 steps from p(0) = p0, u(0) = 0
+ * (equation initial) and samples the pressure at the sensors by linear
+ * interpolation at every step, t = 0 included.
+ *
+ *  p0    device, N floats (initial pressure, the image x).
+ *  data  device, nt*n_sensors floats, written as data[n][s].
+ */
+int pat_forward(pat_plan* plan, const float* p0, float* data, void* stream);
+
+/*
+ * pat_adjoint -- the adjoint H^* = P^* M^* of section III as the exact
+ * transpose of pat_forward: for every p0 and h,
+ *   <pat_forward(p0), h> = <p0, pat_adjoint(h)>   (equation adj2),
+ * up to float32 rounding.  It steps the time-reversed system of equations
+ * moma/massa/statea with the data injected as a mass source and returns
+ * the transposed initial condition (the discrete rho*(T)/rho0 of adjj).
+ *
+ *  data  device, nt*n_sensors floats, [n][s].
+ *  img   device, N floats, overwritten.
+ */
+int pat_adjoint(pat_plan* plan, const float* data, float* img, void* stream);
+
+/*
+ * pat_forward_range -- the forward operator in time segments, for
+ * checkpointing: records samples n_begin .. n_end-1 into data[n][s] (the rows
+ * of `data` outside that range are not touched).
+ *
+ *  n_begin == 0  starts from p0 (state_io is only written);
+ *  n_begin  > 0  resumes from the snapshot in state_io, which must hold the
+ *                state at sample n_begin written by an earlier call
+ *                (p0 is then ignored and may be NULL).
+ *  state_io      device, info.state_bytes bytes; receives the state at n_end.
+ *
+ * Running [0, k) then [k, nt) gives bitwise the same data as pat_forward.
+ */
+int pat_forward_range(pat_plan* plan, const float* p0, float* data, int32_t n_begin, int32_t n_end,
+                      void* state_io, void* stream);
+
+/*
+ * Batched execution of many plans (uneven sizes and nt allowed: instances
+ * retire when their own time axis ends).  Each pass of the scheme runs as one
+ * launch over a work table that holds the tiles of every active instance; the
+ * time loop is captured into HIP graphs of `chunk` steps and replayed.
+ * The plans must outlive the batch; a batch is used by one stream at a time.
+ *
+ *  pat_batch_create   plans: host array of nb plan pointers; chunk >= 1
+ *                     (0 selects the default, 32).  All plans must have the
+ *                     same ndim.
+ *  pat_batch_forward  p0[i], data[i]: host arrays of nb device pointers.
+ *  pat_batch_adjoint  data[i], img[i]: host arrays of nb device pointers.
+ *
+ * Results equal pat_forward / pat_adjoint per instance bitwise.
+ */
+int pat_batch_create(pat_batch** out, pat_plan* const* plans, int32_t nb, int32_t chunk);
+void pat_batch_destroy(pat_batch* batch);
+int pat_batch_forward(pat_batch* batch, const float* const* p0, float* const* data, void* stream);
+int pat_batch_adjoint(pat_batch* batch, const float* const* data, float* const* img, void* stream);
+
+/*
+ * pat_tv_prox -- the proximal map of equation proxmal for
+ * g = lambda_eff * TV + indicator(x >= lower), section IV:
+ *   x = argmin  lambda_eff * TV_iso(x) + 1/2 ||x - z||^2   s.t. x >= lower,
+ * by n_iter iterations of the fast gradient projection on the dual field of
+ * Beck and Teboulle (the dual approach the paper uses), with forward
+ * differences, Neumann boundary and dual step 1/(4 d lambda_eff).
+ * lambda_eff = 0 returns max(z, lower) (the coarse-level projection).
+ *
+ *  ndim, n     grid (2 or 3 axes, any sizes >= 1, physical order x, y, z).
+ *  z, x        device, N floats each (may not alias).
+ *  lower       device, N floats, or NULL for the bound 0.
+ *  work        device scratch of at least pat_tv_prox_work_bytes(ndim, n) bytes.
+ */
+size_t pat_tv_prox_work_bytes(int32_t ndim, const int32_t n[3]);
+int pat_tv_prox(int32_t ndim, const int32_t n[3], const float* z, float* x, double lambda_eff,
+                int32_t n_iter, const float* lower, void* work, size_t work_bytes, void* stream);
+
+/*
+ * pat_restrict / pat_prolong -- the transfer operators I_h^{h-1} and
+ * I_{h-1}^h of section V (which the paper leaves undefined): the coarse grid
+ * is cell-centred over 2^d blocks of fine points;
+ *   restrict: coarse[I] = 2^-d * sum_{delta in {0,1}^d} fine[2I + delta]
+ *   prolong:  fine[i]   = coarse[floor(i/2)]   (= 2^d * restrict^T)
+ * n_fine / n_coarse: per-axis sizes (n_fine even).  Arrays are device floats.
+ */
+int pat_restrict(int32_t ndim, const int32_t n_fine[3], const float* fine, float* coarse, void* stream);
+int pat_prolong(int32_t ndim, const int32_t n_coarse[3], const float* coarse, float* fine, void* stream);
+
+/*
+ * pat_dot_f64 -- sum_i a[i]*b[i] of float32 device arrays accumulated in
+ * float64 with a fixed reduction order (deterministic), for the objective
+ * 1/2 ||Hx - p||^2 and the norms of the multi-grid decision rule (sections
+ * IV, V).  Synchronises `stream` and writes the result to *out_host.
+ * b == a gives the squared norm.  n may be 0 (result 0).
+ */
+int pat_dot_f64(const float* a, const float* b, int64_t n, double* out_host, void* stream);
+
+/*
+ * pat_residual_f64 -- r = a - b written to device `r` (float32) and
+ * 1/2 ||a - b||^2 accumulated in float64 (deterministic), in one pass.
+ * Synchronises `stream`; *half_sq_host receives the value.
+ */
+int pat_residual_f64(const float* a, const float* b, float* r, int64_t n, double* half_sq_host,
+                     void* stream);
+
+/*
+ * pat_plan_sync -- wait for `plan`'s work on `stream` and report deferred
+ * device errors: PAT_ENONFINITE if PAT_CHECK_FINITE was set and a non-finite
+ * pressure value was produced since the last sync (the flag is then cleared).
+ */
+int pat_plan_sync(pat_plan* plan, void* stream);
+
+/* Static description of a return code. */
+const char* pat_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PAT_H */

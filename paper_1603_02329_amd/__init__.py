@@ -1,0 +1,343 @@
+"""Python binding of libpat (gfx950): argument marshalling only.
+
+Every operator runs in the HIP kernels of ``libpat.so``; this module only
+checks tensors, allocates outputs with torch and forwards device pointers and
+the current HIP stream to the C ABI declared in ``include/pat.h``.  It fails
+loudly when the library is missing or a tensor is not on the GPU: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+__all__ = ["lib", "PatError", "Plan", "Batch", "tv_prox", "restrict", "prolong", "dot_f64", "residual_f64",
+           "LIB_PATH", "EXPORTED"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpat.so")
+
+PAT_OK, PAT_EINVAL, PAT_EUNSTABLE, PAT_ENOMEM, PAT_EHIP, PAT_ENONFINITE, PAT_ENOSYS = range(7)
+PAT_NO_PML = 0x1
+PAT_CHECK_FINITE = 0x2
+
+#: every symbol include/pat.h declares
+EXPORTED = [
+    "pat_plan_create", "pat_plan_destroy", "pat_plan_info", "pat_forward", "pat_adjoint",
+    "pat_forward_range", "pat_batch_create", "pat_batch_destroy", "pat_batch_forward",
+    "pat_batch_adjoint", "pat_tv_prox_work_bytes", "pat_tv_prox", "pat_restrict", "pat_prolong",
+    "pat_dot_f64", "pat_residual_f64", "pat_plan_sync", "pat_strerror",
+]
+
+
+class PatError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.pat_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: {msg} (code {code})")
+        self.code = code
+
+
+class CDesc(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("dx", ctypes.c_double * 3),
+        ("origin", ctypes.c_double * 3), ("nt", ctypes.c_int32), ("dt", ctypes.c_double),
+        ("cfl", ctypes.c_double), ("pml_size", ctypes.c_int32 * 3), ("pml_alpha", ctypes.c_double),
+        ("alpha_power", ctypes.c_double), ("n_sensors", ctypes.c_int32), ("flags", ctypes.c_uint32),
+    ]
+
+
+class CInfo(ctypes.Structure):
+    _fields_ = [
+        ("dt", ctypes.c_double), ("c_ref", ctypes.c_double), ("npoints", ctypes.c_int64),
+        ("lossy", ctypes.c_int32), ("n_slots", ctypes.c_int32), ("device_bytes", ctypes.c_size_t),
+        ("state_bytes", ctypes.c_size_t),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libpat.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libpat.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "pat_plan_create": (ctypes.c_int, [pp, ctypes.POINTER(CDesc), vp, vp, vp, vp, vp]),
+        "pat_plan_destroy": (None, [vp]),
+        "pat_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(CInfo)]),
+        "pat_forward": (ctypes.c_int, [vp, vp, vp, vp]),
+        "pat_adjoint": (ctypes.c_int, [vp, vp, vp, vp]),
+        "pat_forward_range": (ctypes.c_int, [vp, vp, vp, i32, i32, vp, vp]),
+        "pat_batch_create": (ctypes.c_int, [pp, pp, i32, i32]),
+        "pat_batch_destroy": (None, [vp]),
+        "pat_batch_forward": (ctypes.c_int, [vp, pp, pp, vp]),
+        "pat_batch_adjoint": (ctypes.c_int, [vp, pp, pp, vp]),
+        "pat_tv_prox_work_bytes": (sz, [i32, ctypes.POINTER(i32)]),
+        "pat_tv_prox": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, f64, i32, vp, vp, sz, vp]),
+        "pat_restrict": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, vp]),
+        "pat_prolong": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, vp]),
+        "pat_dot_f64": (ctypes.c_int, [vp, vp, i64, ctypes.POINTER(f64), vp]),
+        "pat_residual_f64": (ctypes.c_int, [vp, vp, vp, i64, ctypes.POINTER(f64), vp]),
+        "pat_plan_sync": (ctypes.c_int, [vp, vp]),
+        "pat_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(code: int, where: str) -> None:
+    if code != PAT_OK:
+        raise PatError(code, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f32(t, name: str, numel: Optional[int] = None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the HIP device")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _i32x3(v: Sequence[int]):
+    a = (ctypes.c_int32 * 3)(*([int(x) for x in v] + [1] * (3 - len(v))))
+    return a
+
+
+def make_desc(desc, n_sensors: int, check_finite: bool = False) -> CDesc:
+    """C descriptor from any object with the GridDesc attributes."""
+    nd = int(desc.ndim)
+    c = CDesc()
+    c.ndim = nd
+    for j in range(3):
+        c.n[j] = int(desc.n[j]) if j < nd else 1
+        c.dx[j] = float(desc.dx[j]) if j < nd else 1.0
+        c.origin[j] = float(desc.origin[j]) if j < nd else 0.0
+        c.pml_size[j] = int(desc.pml_size[j]) if j < len(desc.pml_size) else 0
+    c.nt = int(desc.nt)
+    c.dt = float(desc.dt)
+    c.cfl = float(desc.cfl)
+    c.pml_alpha = float(desc.pml_alpha)
+    c.alpha_power = float(desc.alpha_power)
+    c.n_sensors = int(n_sensors)
+    c.flags = (0 if getattr(desc, "pml", True) else PAT_NO_PML) | (PAT_CHECK_FINITE if check_finite else 0)
+    return c
+
+
+class Plan:
+    """One solver instance (a grid level) resident on the GPU.
+
+    ``c0``, ``rho0`` and ``alpha0_db`` are float32 tensors (or arrays, copied
+    to the device) of the grid's shape; ``sensors`` is an (ns, ndim) array of
+    physical positions.  ``alpha0_db=None`` selects a lossless medium."""
+
+    def __init__(self, desc, c0, rho0, alpha0_db, sensors, *, device="cuda", check_finite=False):
+        torch = _torch()
+        L = lib()
+        self.desc = desc
+        self.ndim = int(desc.ndim)
+        self.shape = tuple(int(v) for v in reversed(desc.n[: self.ndim]))
+        self.npoints = int(np.prod(self.shape))
+        sens = np.ascontiguousarray(np.asarray(sensors, dtype=np.float64).reshape(-1, self.ndim))
+        self.ns = sens.shape[0]
+        self.nt = int(desc.nt)
+
+        def dev(a):
+            if a is None:
+                return None
+            t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a, np.float32))
+            return t.to(device=device, dtype=torch.float32).contiguous()
+
+        c0t, r0t, a0t = dev(c0), dev(rho0), dev(alpha0_db)
+        cd = make_desc(desc, self.ns, check_finite)
+        h = ctypes.c_void_p()
+        rc = L.pat_plan_create(ctypes.byref(h), ctypes.byref(cd), _dev_f32(c0t, "c0", self.npoints),
+                               _dev_f32(r0t, "rho0", self.npoints),
+                               None if a0t is None else _dev_f32(a0t, "alpha0_db", self.npoints),
+                               sens.ctypes.data_as(ctypes.c_void_p), _stream())
+        _check(rc, "pat_plan_create")
+        self._h = h
+        self._device = device
+        info = CInfo()
+        _check(L.pat_plan_info(h, ctypes.byref(info)), "pat_plan_info")
+        self.dt = info.dt
+        self.c_ref = info.c_ref
+        self.lossy = bool(info.lossy)
+        self.device_bytes = int(info.device_bytes)
+        self.state_bytes = int(info.state_bytes)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pat_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, p0, data=None):
+        """data[n, s] = (H p0) sampled at t = n dt (shape (nt, ns))."""
+        torch = _torch()
+        if data is None:
+            data = torch.empty((self.nt, self.ns), device=p0.device, dtype=torch.float32)
+        _check(lib().pat_forward(self._h, _dev_f32(p0, "p0", self.npoints),
+                                 _dev_f32(data, "data", self.nt * self.ns), _stream()), "pat_forward")
+        return data
+
+    def adjoint(self, data, img=None):
+        """img = H^T data (shape of the grid)."""
+        torch = _torch()
+        if img is None:
+            img = torch.empty(self.shape, device=data.device, dtype=torch.float32)
+        _check(lib().pat_adjoint(self._h, _dev_f32(data, "data", self.nt * self.ns),
+                                 _dev_f32(img, "img", self.npoints), _stream()), "pat_adjoint")
+        return img
+
+    def forward_range(self, p0, data, n_begin: int, n_end: int, state):
+        """Samples n_begin..n_end-1 into data; state (uint8 tensor of
+        state_bytes) is read when n_begin > 0 and receives the end state."""
+        torch = _torch()
+        if state.dtype != torch.uint8 or state.numel() < self.state_bytes or not state.is_cuda:
+            raise ValueError("state must be a uint8 device tensor of state_bytes")
+        _check(lib().pat_forward_range(self._h, None if p0 is None else _dev_f32(p0, "p0", self.npoints),
+                                       _dev_f32(data, "data", self.nt * self.ns), int(n_begin), int(n_end),
+                                       ctypes.c_void_p(state.data_ptr()), _stream()), "pat_forward_range")
+        return data
+
+    def sync(self):
+        """Wait for the plan's work; raises PatError(ENONFINITE) if flagged."""
+        _check(lib().pat_plan_sync(self._h, _stream()), "pat_plan_sync")
+
+
+class Batch:
+    """Many plans run together (one launch per pass over all instances)."""
+
+    def __init__(self, plans: Sequence[Plan], chunk: int = 0):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib().pat_batch_create(ctypes.byref(h), arr, len(self.plans), int(chunk)), "pat_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pat_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, p0s, datas=None):
+        torch = _torch()
+        if datas is None:
+            datas = [torch.empty((p.nt, p.ns), device=x.device, dtype=torch.float32) for p, x in zip(self.plans, p0s)]
+        a = (ctypes.c_void_p * len(self.plans))(*[_dev_f32(x, "p0", p.npoints).value for p, x in zip(self.plans, p0s)])
+        b = (ctypes.c_void_p * len(self.plans))(*[_dev_f32(d, "data", p.nt * p.ns).value
+                                                  for p, d in zip(self.plans, datas)])
+        _check(lib().pat_batch_forward(self._h, a, b, _stream()), "pat_batch_forward")
+        return datas
+
+    def adjoint(self, datas, imgs=None):
+        torch = _torch()
+        if imgs is None:
+            imgs = [torch.empty(p.shape, device=d.device, dtype=torch.float32) for p, d in zip(self.plans, datas)]
+        a = (ctypes.c_void_p * len(self.plans))(*[_dev_f32(d, "data", p.nt * p.ns).value
+                                                  for p, d in zip(self.plans, datas)])
+        b = (ctypes.c_void_p * len(self.plans))(*[_dev_f32(x, "img", p.npoints).value for p, x in zip(self.plans, imgs)])
+        _check(lib().pat_batch_adjoint(self._h, a, b, _stream()), "pat_batch_adjoint")
+        return imgs
+
+
+def tv_prox(z, lam: float, n_iter: int = 20, lower=None, out=None, work=None):
+    """argmin_x lam TV(x) + 1/2||x - z||^2 s.t. x >= lower (FGP, n_iter steps)."""
+    torch = _torch()
+    nd = z.dim()
+    n = _i32x3(list(reversed(z.shape)))
+    nbytes = lib().pat_tv_prox_work_bytes(nd, n)
+    if out is None:
+        out = torch.empty_like(z)
+    if work is None:
+        work = torch.empty(max(1, nbytes), dtype=torch.uint8, device=z.device)
+    _check(lib().pat_tv_prox(nd, n, _dev_f32(z, "z"), _dev_f32(out, "x", z.numel()), float(lam), int(n_iter),
+                             None if lower is None else _dev_f32(lower, "lower", z.numel()),
+                             ctypes.c_void_p(work.data_ptr()), ctypes.c_size_t(work.numel()), _stream()),
+           "pat_tv_prox")
+    return out
+
+
+def restrict(fine, out=None):
+    torch = _torch()
+    nd = fine.dim()
+    if out is None:
+        out = torch.empty(tuple(s // 2 for s in fine.shape), device=fine.device, dtype=torch.float32)
+    _check(lib().pat_restrict(nd, _i32x3(list(reversed(fine.shape))), _dev_f32(fine, "fine"),
+                              _dev_f32(out, "coarse", fine.numel() >> nd), _stream()), "pat_restrict")
+    return out
+
+
+def prolong(coarse, out=None):
+    torch = _torch()
+    nd = coarse.dim()
+    if out is None:
+        out = torch.empty(tuple(2 * s for s in coarse.shape), device=coarse.device, dtype=torch.float32)
+    _check(lib().pat_prolong(nd, _i32x3(list(reversed(coarse.shape))), _dev_f32(coarse, "coarse"),
+                             _dev_f32(out, "fine", coarse.numel() << nd), _stream()), "pat_prolong")
+    return out
+
+
+def dot_f64(a, b=None) -> float:
+    """sum a*b of float32 device tensors with float64 accumulation."""
+    b = a if b is None else b
+    out = ctypes.c_double()
+    _check(lib().pat_dot_f64(_dev_f32(a, "a"), _dev_f32(b, "b", a.numel()), a.numel(), ctypes.byref(out),
+                             _stream()), "pat_dot_f64")
+    return out.value
+
+
+def residual_f64(a, b, r=None):
+    """(r = a - b, 1/2 ||a - b||^2 in float64)."""
+    torch = _torch()
+    if r is None:
+        r = torch.empty_like(a)
+    out = ctypes.c_double()
+    _check(lib().pat_residual_f64(_dev_f32(a, "a"), _dev_f32(b, "b", a.numel()), _dev_f32(r, "r", a.numel()),
+                                  a.numel(), ctypes.byref(out), _stream()), "pat_residual_f64")
+    return r, out.value

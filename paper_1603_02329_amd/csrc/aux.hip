@@ -1,0 +1,289 @@
+// Auxiliary operators of the multi-grid ISTA/FISTA iteration on gfx950:
+// the TV proximal map (dual FGP), the level-transfer operators and the
+// float64 reductions.  All are O(N) per call (the prox: O(N) per iteration).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <mutex>
+#include <vector>
+
+#include "pat_internal.h"
+
+namespace {
+
+#define PAT_TRY_HIP(x)                     \
+  do {                                     \
+    hipError_t e_ = (x);                   \
+    if (e_ != hipSuccess) return PAT_EHIP; \
+  } while (0)
+
+struct Grid3 {
+  int n[3];
+  long N;
+  long stride[3];
+};
+
+int make_grid(int ndim, const int32_t* n, Grid3& g) {
+  if ((ndim != 2 && ndim != 3) || !n) return PAT_EINVAL;
+  g.N = 1;
+  for (int j = 0; j < 3; ++j) {
+    g.n[j] = (j < ndim) ? n[j] : 1;
+    if (g.n[j] < 1) return PAT_EINVAL;
+  }
+  g.stride[0] = 1;
+  g.stride[1] = g.n[0];
+  g.stride[2] = (long)g.n[0] * g.n[1];
+  g.N = (long)g.n[0] * g.n[1] * g.n[2];
+  return PAT_OK;
+}
+
+inline int blocks_for(long n, int per = 256) { return (int)((n + per - 1) / per); }
+
+// ------------------------------------------------------------------ FGP prox
+// x = max(z - lam * L r, lower), with (L r)_i = sum_a r_a[i] - r_a[i - e_a]
+// (r_a is zero on axis a's last index and outside the grid).
+__global__ void k_prox_primal(Grid3 g, int ndim, const float* __restrict__ z, const float* __restrict__ lower,
+                              const float* __restrict__ r, float lam, float* __restrict__ x) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  long rem = i;
+  int idx[3];
+  for (int j = 0; j < 3; ++j) {
+    idx[j] = (int)(rem % g.n[j]);
+    rem /= g.n[j];
+  }
+  float div = 0.f;
+  for (int a = 0; a < ndim; ++a) {
+    const float* ra = r + (long)a * g.N;
+    if (idx[a] < g.n[a] - 1) div += ra[i];
+    if (idx[a] > 0) div -= ra[i - g.stride[a]];
+  }
+  const float lo = lower ? lower[i] : 0.f;
+  x[i] = fmaxf(z[i] - lam * div, lo);
+}
+
+// p = P_P(r + step * Lt x) with Lt x = x[i] - x[i + e_a] (0 on the last index);
+// r <- p + theta (p - p_prev); p_prev <- p.
+__global__ void k_prox_dual(Grid3 g, int ndim, const float* __restrict__ x, float step, float theta,
+                            float* __restrict__ r, float* __restrict__ pprev) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  long rem = i;
+  int idx[3];
+  for (int j = 0; j < 3; ++j) {
+    idx[j] = (int)(rem % g.n[j]);
+    rem /= g.n[j];
+  }
+  float v[3] = {0.f, 0.f, 0.f};
+  float nrm2 = 0.f;
+  for (int a = 0; a < ndim; ++a) {
+    const float d = (idx[a] < g.n[a] - 1) ? x[i] - x[i + g.stride[a]] : 0.f;
+    v[a] = r[(long)a * g.N + i] + step * d;
+    nrm2 += v[a] * v[a];
+  }
+  const float s = fmaxf(1.f, sqrtf(nrm2));
+  for (int a = 0; a < ndim; ++a) {
+    const float pa = v[a] / s;
+    const long k = (long)a * g.N + i;
+    const float pp = pprev[k];
+    r[k] = pa + theta * (pa - pp);
+    pprev[k] = pa;
+  }
+}
+
+__global__ void k_proj(long n, const float* __restrict__ z, const float* __restrict__ lower, float* __restrict__ x) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = fmaxf(z[i], lower ? lower[i] : 0.f);
+}
+
+__global__ void k_zero(long n, float* __restrict__ a) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.f;
+}
+
+// ------------------------------------------------------------------ transfers
+__global__ void k_restrict(Grid3 c, int ndim, const float* __restrict__ fine, float* __restrict__ coarse) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.N) return;
+  const int cx = (int)(i % c.n[0]);
+  const int cy = (int)((i / c.n[0]) % c.n[1]);
+  const int cz = (int)(i / ((long)c.n[0] * c.n[1]));
+  const long fx = 2L * c.n[0], fy = 2L * c.n[1];
+  float acc = 0.f;
+  const int nzc = ndim == 3 ? 2 : 1;
+  for (int dz = 0; dz < nzc; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const long f = (2L * cx + dx) + fx * ((2L * cy + dy) + fy * (ndim == 3 ? (2L * cz + dz) : 0));
+        acc += fine[f];
+      }
+  coarse[i] = acc * (ndim == 3 ? 0.125f : 0.25f);
+}
+
+__global__ void k_prolong(Grid3 f, int ndim, const float* __restrict__ coarse, float* __restrict__ fine) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= f.N) return;
+  const int fx = (int)(i % f.n[0]);
+  const int fy = (int)((i / f.n[0]) % f.n[1]);
+  const int fz = (int)(i / ((long)f.n[0] * f.n[1]));
+  const long cxn = f.n[0] / 2, cyn = f.n[1] / 2;
+  const long c = (fx / 2) + cxn * ((fy / 2) + cyn * (ndim == 3 ? (fz / 2) : 0));
+  fine[i] = coarse[c];
+}
+
+// ------------------------------------------------------------------ float64 reductions
+constexpr int kRedBlocks = 512;
+constexpr int kRedThreads = 256;
+
+// Fixed partition: block b sums the contiguous chunk b of the input, each
+// thread a strided subsequence in order, then a fixed tree -> deterministic.
+template <int OP>  // 0: a*b   1: (a-b)^2/2 and r = a-b
+__global__ void __launch_bounds__(kRedThreads) k_red1(const float* __restrict__ a, const float* __restrict__ b,
+                                                      float* __restrict__ r, long n, double* __restrict__ part) {
+  __shared__ double sh[kRedThreads];
+  const long chunk = (n + kRedBlocks - 1) / kRedBlocks;
+  const long beg = (long)blockIdx.x * chunk;
+  const long end = beg + chunk < n ? beg + chunk : n;
+  double acc = 0.0;
+  for (long i = beg + threadIdx.x; i < end; i += kRedThreads) {
+    if (OP == 0) {
+      acc += (double)a[i] * (double)b[i];
+    } else {
+      const float d = a[i] - b[i];
+      r[i] = d;
+      acc += 0.5 * (double)d * (double)d;
+    }
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(kRedThreads) k_red2(const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[kRedThreads];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) acc += part[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+std::mutex g_red_mu;
+std::vector<double*> g_red_buf;  // per device: kRedBlocks partials + 1 result
+
+int red_buffer(double** out) {
+  int dev = 0;
+  PAT_TRY_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_red_mu);
+  if ((int)g_red_buf.size() <= dev) g_red_buf.resize(dev + 1, nullptr);
+  if (!g_red_buf[dev]) {
+    if (hipMalloc(&g_red_buf[dev], sizeof(double) * (kRedBlocks + 1)) != hipSuccess) return PAT_ENOMEM;
+  }
+  *out = g_red_buf[dev];
+  return PAT_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C entry points
+extern "C" size_t pat_tv_prox_work_bytes(int32_t ndim, const int32_t n[3]) {
+  Grid3 g;
+  if (make_grid(ndim, n, g)) return 0;
+  return (size_t)(2 * ndim + 1) * (size_t)g.N * sizeof(float);
+}
+
+extern "C" int pat_tv_prox(int32_t ndim, const int32_t n[3], const float* z, float* x, double lambda_eff,
+                           int32_t n_iter, const float* lower, void* work, size_t work_bytes, void* stream) {
+  Grid3 g;
+  if (make_grid(ndim, n, g)) return PAT_EINVAL;
+  if (!z || !x || z == x || !(lambda_eff >= 0) || !std::isfinite(lambda_eff) || n_iter < 0) return PAT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int nb = blocks_for(g.N);
+  if (lambda_eff == 0.0 || n_iter == 0) {
+    if (lambda_eff != 0.0 && n_iter == 0) {
+      // zero iterations of FGP: output is P_C(z - lam L 0) = P_C(z)
+    }
+    hipLaunchKernelGGL(k_proj, dim3(nb), dim3(256), 0, st, g.N, z, lower, x);
+    return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
+  }
+  if (!work || work_bytes < pat_tv_prox_work_bytes(ndim, n)) return PAT_EINVAL;
+  float* r = (float*)work;
+  float* pprev = r + (long)ndim * g.N;
+  float* xt = pprev + (long)ndim * g.N;
+  hipLaunchKernelGGL(k_zero, dim3(blocks_for(2L * ndim * g.N)), dim3(256), 0, st, 2L * ndim * g.N, r);
+  const float lam = (float)lambda_eff;
+  const float step = (float)(1.0 / (4.0 * ndim * lambda_eff));
+  double t = 1.0;
+  for (int k = 0; k < n_iter; ++k) {
+    const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    const float theta = (float)((t - 1.0) / tn);
+    hipLaunchKernelGGL(k_prox_primal, dim3(nb), dim3(256), 0, st, g, ndim, z, lower, r, lam, xt);
+    hipLaunchKernelGGL(k_prox_dual, dim3(nb), dim3(256), 0, st, g, ndim, xt, step, theta, r, pprev);
+    t = tn;
+  }
+  hipLaunchKernelGGL(k_prox_primal, dim3(nb), dim3(256), 0, st, g, ndim, z, lower, pprev, lam, x);
+  return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
+}
+
+extern "C" int pat_restrict(int32_t ndim, const int32_t n_fine[3], const float* fine, float* coarse, void* stream) {
+  Grid3 f;
+  if (make_grid(ndim, n_fine, f) || !fine || !coarse) return PAT_EINVAL;
+  int32_t nc[3];
+  for (int j = 0; j < 3; ++j) {
+    if (j < ndim && (f.n[j] % 2)) return PAT_EINVAL;
+    nc[j] = j < ndim ? f.n[j] / 2 : 1;
+  }
+  Grid3 c;
+  make_grid(ndim, nc, c);
+  hipLaunchKernelGGL(k_restrict, dim3(blocks_for(c.N)), dim3(256), 0, (hipStream_t)stream, c, ndim, fine, coarse);
+  return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
+}
+
+extern "C" int pat_prolong(int32_t ndim, const int32_t n_coarse[3], const float* coarse, float* fine, void* stream) {
+  Grid3 c;
+  if (make_grid(ndim, n_coarse, c) || !fine || !coarse) return PAT_EINVAL;
+  int32_t nf[3];
+  for (int j = 0; j < 3; ++j) nf[j] = j < ndim ? 2 * c.n[j] : 1;
+  Grid3 f;
+  make_grid(ndim, nf, f);
+  hipLaunchKernelGGL(k_prolong, dim3(blocks_for(f.N)), dim3(256), 0, (hipStream_t)stream, f, ndim, coarse, fine);
+  return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
+}
+
+static int reduce_common(int op, const float* a, const float* b, float* r, int64_t n, double* out_host,
+                         hipStream_t st) {
+  if (!out_host || n < 0 || ((!a || !b) && n > 0) || (op == 1 && !r && n > 0)) return PAT_EINVAL;
+  if (n == 0) {
+    *out_host = 0.0;
+    return PAT_OK;
+  }
+  double* buf = nullptr;
+  int rc = red_buffer(&buf);
+  if (rc) return rc;
+  if (op == 0)
+    hipLaunchKernelGGL(k_red1<0>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, a, b, r, (long)n, buf);
+  else
+    hipLaunchKernelGGL(k_red1<1>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, a, b, r, (long)n, buf);
+  hipLaunchKernelGGL(k_red2, dim3(1), dim3(kRedThreads), 0, st, buf, buf + kRedBlocks);
+  PAT_TRY_HIP(hipGetLastError());
+  PAT_TRY_HIP(hipMemcpyAsync(out_host, buf + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, st));
+  PAT_TRY_HIP(hipStreamSynchronize(st));
+  return PAT_OK;
+}
+
+extern "C" int pat_dot_f64(const float* a, const float* b, int64_t n, double* out_host, void* stream) {
+  return reduce_common(0, a, b, nullptr, n, out_host, (hipStream_t)stream);
+}
+
+extern "C" int pat_residual_f64(const float* a, const float* b, float* r, int64_t n, double* half_sq_host,
+                                void* stream) {
+  return reduce_common(1, a, b, r, n, half_sq_host, (hipStream_t)stream);
+}

@@ -1,0 +1,171 @@
+// Register/LDS Stockham FFT for gfx950.
+//
+// One transform of length M is carried by T = M / E threads, each holding E
+// complex values in registers.  Thread t owns the elements at indices
+// t + T*m (m = 0..E-1) both on entry (time/space order) and on exit
+// (natural frequency order): consecutive lanes touch consecutive elements,
+// so loads and stores to global memory coalesce.  Each stage is a radix-R
+// butterfly (R = E, or smaller for the last stage) in registers; between
+// stages the values pass through the transform's LDS region in Stockham
+// (self-sorting) order.
+//
+// Twiddles come from a table of exp(-2 pi i q / TWN) held as hi + lo float
+// pairs, and the radix-8 constant sqrt(1/2) likewise: the product x*w is
+// formed as x*w_hi + x*w_lo, so the table's float32 rounding -- a fixed,
+// systematic perturbation of the DFT that would otherwise accumulate over
+// thousands of time steps -- is removed.  Only the arithmetic rounding of
+// the butterflies remains.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pat_internal.h"
+
+namespace pat {
+
+__device__ __forceinline__ float2 operator+(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 operator-(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 operator*(float s, float2 a) { return make_float2(s * a.x, s * a.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+
+// x * (w_hi + w_lo) for the table twiddle w (SIGN < 0) or its conjugate (SIGN > 0)
+template <int SIGN>
+__device__ __forceinline__ float2 twmul(float2 x, const Tw w) {
+  const float wr = w.hr, wi = (SIGN < 0) ? w.hi : -w.hi;
+  const float lr = w.lr, li = (SIGN < 0) ? w.li : -w.li;
+  const float tr = x.x * lr - x.y * li;
+  const float ti = x.x * li + x.y * lr;
+  return make_float2(fmaf(x.x, wr, fmaf(-x.y, wi, tr)), fmaf(x.x, wi, fmaf(x.y, wr, ti)));
+}
+
+// x * (SIGN i)
+template <int SIGN>
+__device__ __forceinline__ float2 mul_si(float2 x) {
+  return (SIGN < 0) ? make_float2(x.y, -x.x) : make_float2(-x.y, x.x);
+}
+
+// sqrt(1/2) = S8H + S8L
+constexpr float S8H = 0.70710676908493042f;
+constexpr float S8L = 1.2101617485882343e-08f;
+__device__ __forceinline__ float mul_s8(float v) { return fmaf(v, S8H, v * S8L); }
+
+// x * exp(SIGN i pi/4) and x * exp(SIGN 3 i pi/4)
+template <int SIGN>
+__device__ __forceinline__ float2 mul_w8(float2 x) {
+  return (SIGN < 0) ? make_float2(mul_s8(x.x + x.y), mul_s8(x.y - x.x))
+                    : make_float2(mul_s8(x.x - x.y), mul_s8(x.y + x.x));
+}
+template <int SIGN>
+__device__ __forceinline__ float2 mul_w83(float2 x) {
+  return (SIGN < 0) ? make_float2(mul_s8(x.y - x.x), mul_s8(-x.x - x.y))
+                    : make_float2(mul_s8(-x.x - x.y), mul_s8(x.x - x.y));
+}
+
+template <int R, int SIGN>
+struct Dft;
+
+template <int SIGN>
+struct Dft<1, SIGN> {
+  __device__ __forceinline__ static void run(float2*) {}
+};
+
+template <int SIGN>
+struct Dft<2, SIGN> {
+  __device__ __forceinline__ static void run(float2* x) {
+    const float2 a = x[0];
+    x[0] = a + x[1];
+    x[1] = a - x[1];
+  }
+};
+
+template <int SIGN>
+struct Dft<4, SIGN> {
+  __device__ __forceinline__ static void run(float2* x) {
+    const float2 c0 = x[0] + x[2], c1 = x[0] - x[2];
+    const float2 c2 = x[1] + x[3], c3 = mul_si<SIGN>(x[1] - x[3]);
+    x[0] = c0 + c2;
+    x[2] = c0 - c2;
+    x[1] = c1 + c3;
+    x[3] = c1 - c3;
+  }
+};
+
+template <int SIGN>
+struct Dft<8, SIGN> {
+  __device__ __forceinline__ static void run(float2* x) {
+    float2 a[4], b[4];
+    a[0] = x[0] + x[4];
+    b[0] = x[0] - x[4];
+    a[1] = x[1] + x[5];
+    b[1] = mul_w8<SIGN>(x[1] - x[5]);
+    a[2] = x[2] + x[6];
+    b[2] = mul_si<SIGN>(x[2] - x[6]);
+    a[3] = x[3] + x[7];
+    b[3] = mul_w83<SIGN>(x[3] - x[7]);
+    Dft<4, SIGN>::run(a);
+    Dft<4, SIGN>::run(b);
+    x[0] = a[0];
+    x[2] = a[1];
+    x[4] = a[2];
+    x[6] = a[3];
+    x[1] = b[0];
+    x[3] = b[1];
+    x[5] = b[2];
+    x[7] = b[3];
+  }
+};
+
+// One Stockham stage of span L (product of the radices already applied).
+template <int M, int E, int SIGN, int L>
+struct FftStage {
+  static constexpr int T = M / E;
+  static constexpr int R = (M / L) < E ? (M / L) : E;
+  static constexpr int NB = E / R;
+  static constexpr bool LAST = (L * R == M);
+
+  __device__ __forceinline__ static void run(float2 (&v)[E], float2* lds, int t, const Tw* __restrict__ tw) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int k = t + T * b;
+      const int j = k & (L - 1);
+      float2 x[R];
+#pragma unroll
+      for (int i = 0; i < R; ++i) x[i] = v[b + i * NB];
+      if constexpr (L > 1) {
+#pragma unroll
+        for (int i = 1; i < R; ++i) x[i] = twmul<SIGN>(x[i], tw[(i * j) * (TWN / (L * R))]);
+      }
+      Dft<R, SIGN>::run(x);
+      if constexpr (LAST) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) v[b + i * NB] = x[i];
+      } else {
+        const int base = (k - j) * R + j;
+#pragma unroll
+        for (int i = 0; i < R; ++i) lds[base + i * L] = x[i];
+      }
+    }
+    if constexpr (!LAST) {
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = lds[t + T * m];
+      __syncthreads();
+      FftStage<M, E, SIGN, L * R>::run(v, lds, t, tw);
+    }
+  }
+};
+
+// Unnormalised DFT of length M (SIGN = -1 forward, +1 inverse) of the values
+// v[m] = x[t + T m] held by the T threads of one transform; `lds` is that
+// transform's region of M complex values.  Every thread of the block must
+// call it (it synchronises the block).
+template <int M, int E, int SIGN>
+__device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, int t, const Tw* __restrict__ tw) {
+  static_assert((M & (M - 1)) == 0 && M >= E && M <= TWN, "unsupported FFT length");
+  FftStage<M, E, SIGN, 1>::run(v, lds, t, tw);
+}
+
+}  // namespace pat

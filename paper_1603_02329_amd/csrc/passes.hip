@@ -1,0 +1,682 @@
+// Time-step passes of the k-space scheme on gfx950.
+//
+// Each spectral operator F^-1[m F f] of the scheme is split into two kinds
+// of passes over HBM:
+//   row pass    : per grid row (x fastest), inverse real FFT along x of the
+//                 incoming packed spectra -> the pointwise part of the step
+//                 (velocity, density, state or their transposes, PML, sensor
+//                 gather/scatter) -> forward real FFT along x of the fields the
+//                 next spectral operator needs;
+//   column pass : per tile of x-frequency columns, FFT along y (and z), the
+//                 k-space multiplier, inverse FFT along y (and z).
+// Between passes only packed x-spectra (4 bytes per grid point and field)
+// and the state fields travel through memory; the pressure itself never
+// does.  The multipliers are formed on the fly from 1-D per-axis tables.
+//
+// The forward step (equations mom, mass, state of section II-A, split per
+// axis for the PML) is
+//   col  : S1,S2 <- a_x, a_y applied to S0 = F_x p             (gradient)
+//   row 1: u_j   <- Qsg_j (Qsg_j u_j - B_j d_j p);  S_j <- F_x u_j
+//   col  : S_j   <- b_j applied to S_j                          (divergence)
+//   row 2: rho_j <- Q_j (Q_j rho_j - dt rho0 g_j);  S1 <- F_x(dt rho0 sum g),
+//                                                   S2 <- F_x(sum rho)
+//   col  : S1 <- |k|^(y-2)/dt S1, S2 <- |k|^(y-1) S2            (absorption)
+//   row 3: p = c0^2 sum rho + c0^2 tau A1 - c0^2 eta A2; gather; S0 <- F_x p
+// and the adjoint runs the transposed passes in reverse order.
+#include <hip/hip_runtime.h>
+
+#include "fft.h"
+#include "pat_internal.h"
+
+namespace pat {
+
+__device__ Tw g_tw[TWN];
+
+// ------------------------------------------------------------------ geometry
+template <int N>
+struct RowGeo {
+  static constexpr int M = N / 2;             // packed complex bins per row
+  static constexpr int E = (M < 8) ? M : 8;   // values per thread
+  static constexpr int T = M / E;             // threads per row
+  static constexpr int ROWS = (256 / T) < 16 ? (256 / T) : 16;
+  static constexpr int NTH = ROWS * T;
+};
+
+template <int NY>
+struct ColGeo {
+  static constexpr int E = 8;
+  static constexpr int TC = NY / E;                          // threads per column
+  static constexpr int TILE = (1024 / TC) < 16 ? (1024 / TC) : 16;
+  static constexpr int NTH = TILE * TC;
+  static constexpr int LD = NY + 1;                          // padded LDS column stride
+};
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ float2 ld2(const float* a, long i) { return reinterpret_cast<const float2*>(a)[i]; }
+__device__ __forceinline__ void st2(float* a, long i, float2 v) { reinterpret_cast<float2*>(a)[i] = v; }
+__device__ __forceinline__ float2 f2(float a, float b) { return make_float2(a, b); }
+__device__ __forceinline__ float2 mul2(float2 a, float2 b) { return make_float2(a.x * b.x, a.y * b.y); }
+__device__ __forceinline__ float2 scl2(float s, float2 a) { return make_float2(s * a.x, s * a.y); }
+
+// Packed half spectrum of one row -> real row, as pairs (x[2n], x[2n+1]) at
+// n = t + T m.  Unnormalised inverse real DFT.
+template <int N>
+__device__ __forceinline__ void c2r(const float2* __restrict__ src, float2 (&r)[RowGeo<N>::E], float2* L, int t,
+                                    bool valid) {
+  using G = RowGeo<N>;
+  constexpr int M = G::M, E = G::E, T = G::T;
+#pragma unroll
+  for (int m = 0; m < E; ++m) L[t + T * m] = valid ? src[t + T * m] : f2(0.f, 0.f);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = t + T * m;
+    const float2 X = L[k];
+    if (k == 0) {
+      r[m] = f2(X.x + X.y, X.x - X.y);
+    } else {
+      const float2 Y = conjf2(L[M - k]);
+      const float2 A = X + Y;
+      const float2 B = twmul<+1>(X - Y, g_tw[k * (TWN / N)]);
+      r[m] = A + mul_si<+1>(B);
+    }
+  }
+  __syncthreads();
+  fft<M, E, +1>(r, L, t, g_tw);
+}
+
+// Real row held as pairs (x[2n], x[2n+1]) -> packed half spectrum stored at dst.
+template <int N>
+__device__ __forceinline__ void r2c(float2 (&r)[RowGeo<N>::E], float2* __restrict__ dst, float2* L, int t,
+                                    bool valid) {
+  using G = RowGeo<N>;
+  constexpr int M = G::M, E = G::E, T = G::T;
+  fft<M, E, -1>(r, L, t, g_tw);
+#pragma unroll
+  for (int m = 0; m < E; ++m) L[t + T * m] = r[m];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = t + T * m;
+    const float2 Z = L[k];
+    float2 X;
+    if (k == 0) {
+      X = f2(Z.x + Z.y, Z.x - Z.y);
+    } else {
+      const float2 Y = conjf2(L[M - k]);
+      const float2 A = Z + Y;
+      const float2 B = twmul<-1>(Z - Y, g_tw[k * (TWN / N)]);
+      X = 0.5f * (A + mul_si<-1>(B));
+    }
+    if (valid) dst[k] = X;
+  }
+  __syncthreads();
+}
+
+// Sensor gather of sample `n` from the real row p held in LDS (as floats).
+template <int N>
+__device__ __forceinline__ void gather_row(const DevPlan& P, int n, const float* Lf, int row, int t, bool valid) {
+  using G = RowGeo<N>;
+  __syncthreads();
+  if (valid) {
+    const int e1 = P.g_ptr[row + 1];
+    float* out = P.partial + (long)n * P.nslots;
+    for (int e = P.g_ptr[row] + t; e < e1; e += G::T) {
+      const GTap tap = P.g_tap[e];
+      out[tap.slot] = fmaf(tap.w0, Lf[tap.x0], tap.w1 * Lf[tap.x0 + 1]);
+    }
+  }
+  __syncthreads();
+}
+
+// Add W^T h[n] for this row to the real row held in LDS (as floats).
+template <int N>
+__device__ __forceinline__ void scatter_row(const DevPlan& P, int n, float* Lf, int row, int t, bool valid) {
+  using G = RowGeo<N>;
+  __syncthreads();
+  if (valid) {
+    const int g1 = P.s_ptr[row + 1];
+    const float* h = P.in + (long)n * P.ns;
+    for (int g = P.s_ptr[row] + t; g < g1; g += G::T) {
+      const SGroup grp = P.s_grp[g];
+      float acc = 0.f;
+      for (int e = grp.beg; e < grp.end; ++e) {
+        const STap tp = P.s_tap[e];
+        acc = fmaf(tp.w, h[tp.s], acc);
+      }
+      Lf[grp.x] += acc;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void check_finite(const DevPlan& P, float2 v) {
+  if ((P.flags & PAT_CHECK_FINITE) && !(isfinite(v.x) && isfinite(v.y))) atomicOr(P.bad, 1);
+}
+
+// ------------------------------------------------------------------ row passes
+template <int N, int D, int K>
+__global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restrict__ plans,
+                                                        const int2* __restrict__ table, StepArg sa) {
+  using G = RowGeo<N>;
+  constexpr int M = G::M, E = G::E, T = G::T;
+  __shared__ float2 lds[G::ROWS * M];
+  const int2 job = table ? table[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+  const DevPlan& P = plans[job.x];
+  const int rl = threadIdx.x / T, t = threadIdx.x % T;
+  const int row = job.y * G::ROWS + rl;
+  const bool valid = row < P.nrows;
+  const int rowc = valid ? row : 0;
+  const int ny = P.n[1];
+  const int yy = rowc % ny, zz = rowc / ny;
+  float2* L = lds + rl * M;
+  float* Lf = reinterpret_cast<float*>(L);
+  const long base = (long)rowc * M;  // float2 index of this row
+  const int it = step_of(sa);         // forward step n / adjoint iteration i
+
+  // per-row PML factors of the y and z axes
+  float qy = 1.f, qsy = 1.f, qz = 1.f, qsz = 1.f;
+  qy = P.Q[1][yy];
+  qsy = P.Qsg[1][yy];
+  if constexpr (D == 3) {
+    qz = P.Q[2][zz];
+    qsz = P.Qsg[2][zz];
+  }
+  const float qrow[3] = {1.f, qy, qz};
+  const float qsrow[3] = {1.f, qsy, qsz};
+
+  if constexpr (K == R_FWD_INIT) {
+    float2 p[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int n = t + T * m;
+      p[m] = valid ? ld2(P.in, base + n) : f2(0.f, 0.f);
+      const float2 rr = mul2(p[m], valid ? ld2(P.inv_dc2, base + n) : f2(0.f, 0.f));
+      if (valid) {
+#pragma unroll
+        for (int j = 0; j < D; ++j) st2(P.r[j], base + n, rr);
+      }
+      L[n] = p[m];
+    }
+    gather_row<N>(P, 0, Lf, rowc, t, valid);
+    r2c<N>(p, P.S[0] + base, L, t, valid);
+  } else if constexpr (K == R_FWD_1) {
+    float2 d[D][E];
+#pragma unroll
+    for (int j = 0; j < D; ++j) c2r<N>(P.S[1 + j] + base, d[j], L, t, valid);
+    const bool first = (it == 0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int n = t + T * m;
+        if (!valid) continue;
+        const float2 b = ld2(P.B[j], base + n);
+        const float2 qs = (j == 0) ? ld2(P.Qsg[0], n) : f2(qsrow[j], qsrow[j]);
+        const float2 db = mul2(b, d[j][m]);
+        const float2 u = first ? scl2(0.5f, db) : ld2(P.u[j], base + n);
+        const float2 un = mul2(qs, mul2(qs, u) - db);
+        st2(P.u[j], base + n, un);
+        d[j][m] = un;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) r2c<N>(d[j], P.S[1 + j] + base, L, t, valid);
+  } else if constexpr (K == R_FWD_2 || K == R_FWD_2LL) {
+    float2 g[D][E];
+#pragma unroll
+    for (int j = 0; j < D; ++j) c2r<N>(P.S[1 + j] + base, g[j], L, t, valid);
+    float2 sdiv[E], srho[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int n = t + T * m;
+      sdiv[m] = f2(0.f, 0.f);
+      srho[m] = f2(0.f, 0.f);
+      if (!valid) continue;
+      const float2 dr = ld2(P.dtr0, base + n);
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const float2 q = (j == 0) ? ld2(P.Q[0], n) : f2(qrow[j], qrow[j]);
+        const float2 tj = mul2(dr, g[j][m]);
+        const float2 rn = mul2(q, mul2(q, ld2(P.r[j], base + n)) - tj);
+        st2(P.r[j], base + n, rn);
+        sdiv[m] = sdiv[m] + tj;
+        srho[m] = srho[m] + rn;
+      }
+    }
+    if constexpr (K == R_FWD_2) {
+      r2c<N>(sdiv, P.S[1] + base, L, t, valid);
+      r2c<N>(srho, P.S[2] + base, L, t, valid);
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int n = t + T * m;
+        const float2 p = valid ? mul2(ld2(P.c2, base + n), srho[m]) : f2(0.f, 0.f);
+        if (valid) check_finite(P, p);
+        srho[m] = p;
+        L[n] = p;
+      }
+      gather_row<N>(P, it + 1, Lf, rowc, t, valid);
+      r2c<N>(srho, P.S[0] + base, L, t, valid);
+    }
+  } else if constexpr (K == R_FWD_3) {
+    float2 a1[E], a2[E];
+    c2r<N>(P.S[1] + base, a1, L, t, valid);
+    c2r<N>(P.S[2] + base, a2, L, t, valid);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int n = t + T * m;
+      float2 p = f2(0.f, 0.f);
+      if (valid) {
+        float2 rs = ld2(P.r[0], base + n);
+#pragma unroll
+        for (int j = 1; j < D; ++j) rs = rs + ld2(P.r[j], base + n);
+        p = mul2(ld2(P.c2, base + n), rs) + mul2(ld2(P.c2tau, base + n), a1[m]) -
+            mul2(ld2(P.c2eta, base + n), a2[m]);
+        check_finite(P, p);
+      }
+      a1[m] = p;
+      L[n] = p;
+    }
+    gather_row<N>(P, it + 1, Lf, rowc, t, valid);
+    r2c<N>(a1, P.S[0] + base, L, t, valid);
+  } else if constexpr (K == R_ADJ_3 || K == R_ADJ_32LL) {
+    const bool first = (it == 0);
+    const int nsamp = P.nt - 1 - it;  // h[n+1] with n = nt-2-it
+    float2 v[E];
+    if (first) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = f2(0.f, 0.f);
+    } else {
+      c2r<N>(P.S[0] + base, v, L, t, valid);
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) L[t + T * m] = v[m];
+    scatter_row<N>(P, nsamp, Lf, rowc, t, valid);
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = L[t + T * m];
+    __syncthreads();
+    if constexpr (K == R_ADJ_3) {
+      float2 e[E], ta[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int n = t + T * m;
+        e[m] = f2(0.f, 0.f);
+        ta[m] = f2(0.f, 0.f);
+        if (!valid) continue;
+        st2(P.q, base + n, mul2(ld2(P.c2, base + n), v[m]));
+        e[m] = mul2(ld2(P.c2eta, base + n), v[m]);
+        ta[m] = mul2(ld2(P.c2tau, base + n), v[m]);
+      }
+      r2c<N>(e, P.S[1] + base, L, t, valid);
+      r2c<N>(ta, P.S[2] + base, L, t, valid);
+    } else {
+      float2 g[D][E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int n = t + T * m;
+#pragma unroll
+        for (int j = 0; j < D; ++j) g[j][m] = f2(0.f, 0.f);
+        if (!valid) continue;
+        const float2 q = mul2(ld2(P.c2, base + n), v[m]);
+        const float2 dr = ld2(P.dtr0, base + n);
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          const float2 qq = (j == 0) ? ld2(P.Q[0], n) : f2(qrow[j], qrow[j]);
+          const float2 rb = (first ? f2(0.f, 0.f) : ld2(P.r[j], base + n)) + q;
+          g[j][m] = f2(0.f, 0.f) - mul2(dr, mul2(qq, rb));
+          st2(P.r[j], base + n, mul2(mul2(qq, qq), rb));
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < D; ++j) r2c<N>(g[j], P.S[1 + j] + base, L, t, valid);
+    }
+  } else if constexpr (K == R_ADJ_2) {
+    const bool first = (it == 0);
+    float2 a2[E], a1[E];
+    c2r<N>(P.S[1] + base, a2, L, t, valid);
+    c2r<N>(P.S[2] + base, a1, L, t, valid);
+    float2 g[D][E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int n = t + T * m;
+#pragma unroll
+      for (int j = 0; j < D; ++j) g[j][m] = f2(0.f, 0.f);
+      if (!valid) continue;
+      const float2 qa = ld2(P.q, base + n) - a2[m];
+      const float2 dr = ld2(P.dtr0, base + n);
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const float2 qq = (j == 0) ? ld2(P.Q[0], n) : f2(qrow[j], qrow[j]);
+        const float2 rb = (first ? f2(0.f, 0.f) : ld2(P.r[j], base + n)) + qa;
+        g[j][m] = mul2(dr, a1[m] - mul2(qq, rb));
+        st2(P.r[j], base + n, mul2(mul2(qq, qq), rb));
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) r2c<N>(g[j], P.S[1 + j] + base, L, t, valid);
+  } else if constexpr (K == R_ADJ_1) {
+    const bool first = (it == 0);
+    const bool last = (it == P.nt - 2);
+    float2 d[D][E];
+#pragma unroll
+    for (int j = 0; j < D; ++j) c2r<N>(P.S[1 + j] + base, d[j], L, t, valid);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int n = t + T * m;
+        if (!valid) {
+          d[j][m] = f2(0.f, 0.f);
+          continue;
+        }
+        const float2 qs = (j == 0) ? ld2(P.Qsg[0], n) : f2(qsrow[j], qsrow[j]);
+        const float2 b = ld2(P.B[j], base + n);
+        const float2 ub = (first ? f2(0.f, 0.f) : ld2(P.u[j], base + n)) - d[j][m];
+        const float2 bq = mul2(b, mul2(qs, ub));
+        if (last) {
+          d[j][m] = mul2(bq, f2(1.f - 0.5f * qs.x, 1.f - 0.5f * qs.y));
+        } else {
+          d[j][m] = bq;
+          st2(P.u[j], base + n, mul2(mul2(qs, qs), ub));
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) r2c<N>(d[j], P.S[1 + j] + base, L, t, valid);
+  } else if constexpr (K == R_ADJ_FINAL || K == R_ADJ_SCATTER_ONLY) {
+    float2 v[E];
+    if constexpr (K == R_ADJ_FINAL) {
+      c2r<N>(P.S[0] + base, v, L, t, valid);
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = f2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int m = 0; m < E; ++m) L[t + T * m] = v[m];
+    scatter_row<N>(P, 0, Lf, rowc, t, valid);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int n = t + T * m;
+      float2 x = L[n];
+      if (valid) {
+        if constexpr (K == R_ADJ_FINAL) {
+          float2 rs = ld2(P.r[0], base + n);
+#pragma unroll
+          for (int j = 1; j < D; ++j) rs = rs + ld2(P.r[j], base + n);
+          x = x + mul2(rs, ld2(P.inv_dc2, base + n));
+        }
+        st2(P.out, base + n, x);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ column passes
+// k-space multiplier `kind` at x-bin kxi (0..nx/2) and y-bin ky, including the
+// normalisation 1/(nx ny).
+__device__ __forceinline__ float2 mult_at(const DevPlan& P, int kind, int kxi, int ky) {
+  const float k2 = P.ksq[0][kxi] + P.ksq[1][ky];
+  float2 m;
+  if (kind <= M_BZ) {
+    const float th = P.kap * sqrtf(k2);
+    const float kap = (th < 1e-4f) ? 1.f - th * th * (1.f / 6.f) : sinf(th) / th;
+    const float2 sh = (kind == M_AX) ? P.shA[0][kxi]
+                      : (kind == M_AY) ? P.shA[1][ky]
+                      : (kind == M_BX) ? P.shB[0][kxi]
+                                       : P.shB[1][ky];
+    m = scl2(kap * P.scale, sh);
+  } else {
+    float v = 0.f;
+    if (k2 > 0.f) v = (kind == M_L1DT) ? powf(k2, P.ym2h) * P.inv_dt : powf(k2, P.ym1h);
+    m = f2(v * P.scale, 0.f);
+  }
+  return m;
+}
+
+// y-transform tile of up to TILE packed columns starting at c0.
+template <int NY>
+struct ColTile {
+  using G = ColGeo<NY>;
+  static constexpr int E = G::E, TC = G::TC, LD = G::LD;
+
+  __device__ static void load(float2* lds, const float2* __restrict__ src, int M, int c0, int width) {
+    for (int idx = threadIdx.x; idx < NY * width; idx += G::NTH) {
+      const int y = idx / width, cc = idx - y * width;
+      lds[cc * LD + y] = src[(long)y * M + c0 + cc];
+    }
+  }
+  __device__ static void store(const float2* lds, float2* __restrict__ dst, int M, int c0, int width) {
+    for (int idx = threadIdx.x; idx < NY * width; idx += G::NTH) {
+      const int y = idx / width, cc = idx - y * width;
+      dst[(long)y * M + c0 + cc] = lds[cc * LD + y];
+    }
+  }
+};
+
+template <int NY, int MODE, int NF>
+__global__ void __launch_bounds__(ColGeo<NY>::NTH) k_col(const DevPlan* __restrict__ plans,
+                                                         const int2* __restrict__ table, ColSpec spec) {
+  using G = ColGeo<NY>;
+  using CT = ColTile<NY>;
+  constexpr int E = G::E, TC = G::TC, LD = G::LD;
+  __shared__ float2 lds[G::TILE * LD];
+  const int2 job = table ? table[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+  const DevPlan& P = plans[job.x];
+  const int M = P.n[0] / 2;
+  const int width = M < G::TILE ? M : G::TILE;
+  const int c0 = job.y * G::TILE;
+  const int c = threadIdx.x / TC, t = threadIdx.x % TC;
+  float2* Lc = lds + c * LD;
+  const int kxi = c0 + c;
+  const bool special = (c0 == 0);  // tile holds packed column 0 = (kx = 0, kx = nx/2)
+  const bool cvalid = c < width;
+
+  auto forward = [&](const float2* src, float2 (&v)[E]) {
+    CT::load(lds, src, M, c0, width);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = Lc[t + TC * m];
+    __syncthreads();
+    fft<NY, E, -1>(v, Lc, t, g_tw);
+  };
+  // conj(C[-ky]) of packed column 0 (block-uniform call when `special`)
+  auto partner = [&](const float2 (&v)[E], float2 (&vm)[E]) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) Lc[t + TC * m] = v[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < E; ++m) vm[m] = conjf2(Lc[(NY - (t + TC * m)) & (NY - 1)]);
+    __syncthreads();
+  };
+  // accumulate mult * spectrum into acc (column-0 aware)
+  auto apply = [&](int kind, const float2 (&v)[E], const float2 (&vm)[E], float2 (&acc)[E]) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int ky = t + TC * m;
+      if (special && c == 0) {
+        const float2 m0 = mult_at(P, kind, 0, ky);
+        const float2 mM = mult_at(P, kind, M, ky);
+        acc[m] = acc[m] + cmul(0.5f * (m0 + mM), v[m]) + cmul(0.5f * (m0 - mM), vm[m]);
+      } else {
+        acc[m] = acc[m] + cmul(mult_at(P, kind, cvalid ? kxi : 0, ky), v[m]);
+      }
+    }
+  };
+  auto inverse_store = [&](float2 (&acc)[E], float2* dst) {
+    fft<NY, E, +1>(acc, Lc, t, g_tw);
+#pragma unroll
+    for (int m = 0; m < E; ++m) Lc[t + TC * m] = acc[m];
+    __syncthreads();
+    CT::store(lds, dst, M, c0, width);
+    __syncthreads();
+  };
+
+  float2 v[E], vm[E], acc[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) vm[m] = f2(0.f, 0.f);
+  if constexpr (MODE == 0) {
+    forward(P.S[0], v);
+    if (special) partner(v, vm);
+#pragma unroll
+    for (int o = 0; o < NF; ++o) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
+      apply(spec.mult[o], v, vm, acc);
+      inverse_store(acc, P.S[1 + o]);
+    }
+  } else if constexpr (MODE == 1) {
+    const int f = 1 + (int)blockIdx.y;
+    forward(P.S[f], v);
+    if (special) partner(v, vm);
+#pragma unroll
+    for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
+    apply(spec.mult[f - 1], v, vm, acc);
+    inverse_store(acc, P.S[f]);
+  } else {
+#pragma unroll
+    for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
+#pragma unroll
+    for (int f = 1; f <= NF; ++f) {
+      forward(P.S[f], v);
+      if (special) partner(v, vm);
+      apply(spec.mult[f - 1], v, vm, acc);
+    }
+    inverse_store(acc, P.S[0]);
+  }
+}
+
+// ------------------------------------------------------------------ gather reduction
+__global__ void __launch_bounds__(256) k_reduce(const DevPlan* __restrict__ plans, const int2* __restrict__ table) {
+  const int2 job = table ? table[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+  const DevPlan& P = plans[job.x];
+  const long idx = (long)job.y * 256 + threadIdx.x;
+  const long total = (long)P.nt * P.ns;
+  if (idx >= total) return;
+  const int n = (int)(idx / P.ns);
+  const int s = (int)(idx - (long)n * P.ns);
+  const float* part = P.partial + (long)n * P.nslots;
+  const int k0 = P.slot_ptr[s], k1 = P.slot_ptr[s + 1];
+  float acc = part[k0];
+  for (int k = k0 + 1; k < k1; ++k) acc += part[k];
+  P.out[idx] = acc;
+}
+
+// ------------------------------------------------------------------ launchers
+int row_tile_rows(int nx) {
+  switch (nx) {
+    case 16: return RowGeo<16>::ROWS;
+    case 32: return RowGeo<32>::ROWS;
+    case 64: return RowGeo<64>::ROWS;
+    case 128: return RowGeo<128>::ROWS;
+    case 256: return RowGeo<256>::ROWS;
+    case 512: return RowGeo<512>::ROWS;
+    case 1024: return RowGeo<1024>::ROWS;
+  }
+  return 0;
+}
+
+template <int N, int D>
+static hipError_t launch_row_nd(RowKind kind, const Launch& L, StepArg s) {
+  const dim3 grid(L.nblocks), block(RowGeo<N>::NTH);
+#define PAT_ROW_CASE(KK) \
+  case KK: hipLaunchKernelGGL((k_row<N, D, KK>), grid, block, 0, L.stream, L.plans, L.table, s); break;
+  switch (kind) {
+    PAT_ROW_CASE(R_FWD_INIT)
+    PAT_ROW_CASE(R_FWD_1)
+    PAT_ROW_CASE(R_FWD_2)
+    PAT_ROW_CASE(R_FWD_2LL)
+    PAT_ROW_CASE(R_FWD_3)
+    PAT_ROW_CASE(R_ADJ_3)
+    PAT_ROW_CASE(R_ADJ_32LL)
+    PAT_ROW_CASE(R_ADJ_2)
+    PAT_ROW_CASE(R_ADJ_1)
+    PAT_ROW_CASE(R_ADJ_FINAL)
+    PAT_ROW_CASE(R_ADJ_SCATTER_ONLY)
+    default: return hipErrorInvalidValue;
+  }
+#undef PAT_ROW_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_row(RowKind kind, int ndim, int nx, const Launch& L, StepArg s) {
+  if (ndim == 2) {
+    switch (nx) {
+      case 16: return launch_row_nd<16, 2>(kind, L, s);
+      case 32: return launch_row_nd<32, 2>(kind, L, s);
+      case 64: return launch_row_nd<64, 2>(kind, L, s);
+      case 128: return launch_row_nd<128, 2>(kind, L, s);
+      case 256: return launch_row_nd<256, 2>(kind, L, s);
+      case 512: return launch_row_nd<512, 2>(kind, L, s);
+      case 1024: return launch_row_nd<1024, 2>(kind, L, s);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+int col_tiles(int ndim, int nx, int ny, int nz) {
+  const int M = nx / 2;
+  int tile = 0;
+  switch (ny) {
+    case 16: tile = ColGeo<16>::TILE; break;
+    case 32: tile = ColGeo<32>::TILE; break;
+    case 64: tile = ColGeo<64>::TILE; break;
+    case 128: tile = ColGeo<128>::TILE; break;
+    case 256: tile = ColGeo<256>::TILE; break;
+    case 512: tile = ColGeo<512>::TILE; break;
+    case 1024: tile = ColGeo<1024>::TILE; break;
+    default: return 0;
+  }
+  (void)ndim;
+  (void)nz;
+  return (M + tile - 1) / tile;
+}
+
+template <int NY>
+static hipError_t launch_col_n(const ColSpec& spec, const Launch& L) {
+  const dim3 block(ColGeo<NY>::NTH);
+  if (spec.mode == 0) {
+    const dim3 grid(L.nblocks);
+    if (spec.nfield == 2)
+      hipLaunchKernelGGL((k_col<NY, 0, 2>), grid, block, 0, L.stream, L.plans, L.table, spec);
+    else
+      return hipErrorInvalidValue;
+  } else if (spec.mode == 1) {
+    const dim3 grid(L.nblocks, spec.nfield);
+    hipLaunchKernelGGL((k_col<NY, 1, 1>), grid, block, 0, L.stream, L.plans, L.table, spec);
+  } else {
+    const dim3 grid(L.nblocks);
+    if (spec.nfield == 2)
+      hipLaunchKernelGGL((k_col<NY, 2, 2>), grid, block, 0, L.stream, L.plans, L.table, spec);
+    else
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_col(const ColSpec& spec, int ndim, int nx, int ny, int nz, const Launch& L) {
+  (void)nx;
+  (void)nz;
+  if (ndim != 2) return hipErrorInvalidValue;
+  switch (ny) {
+    case 16: return launch_col_n<16>(spec, L);
+    case 32: return launch_col_n<32>(spec, L);
+    case 64: return launch_col_n<64>(spec, L);
+    case 128: return launch_col_n<128>(spec, L);
+    case 256: return launch_col_n<256>(spec, L);
+    case 512: return launch_col_n<512>(spec, L);
+    case 1024: return launch_col_n<1024>(spec, L);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce(const Launch& L, int) {
+  hipLaunchKernelGGL(k_reduce, dim3(L.nblocks), dim3(256), 0, L.stream, L.plans, L.table);
+  return hipGetLastError();
+}
+
+hipError_t upload_twiddles(const Tw* host) {
+  return hipMemcpyToSymbol(HIP_SYMBOL(g_tw), host, sizeof(Tw) * TWN, 0, hipMemcpyHostToDevice);
+}
+
+}  // namespace pat

@@ -1,0 +1,157 @@
+// Internal declarations shared by the host runtime and the gfx950 kernels.
+//
+// A solver instance ("plan") lives in device memory as a DevPlan record: the
+// kernels read every size, pointer and scalar they need from it, so a single
+// launch can serve many instances through a work table of (instance, tile)
+// pairs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pat.h"
+
+namespace pat {
+
+constexpr int kMaxDim = 3;
+constexpr int TWN = 1024;  // twiddle table length: exp(-2 pi i q / TWN), q < TWN
+
+// Twiddle stored as an unevaluated float sum hi + lo (per component), so
+// that the systematic float32 rounding of the table does not enter the FFT.
+struct alignas(16) Tw {
+  float hr, hi, lr, li;
+};
+
+// Linear-interpolation tap of one sensor in one grid row:
+// partial[slot] = w0 * p[row][x0] + w1 * p[row][x0 + 1]
+struct GTap {
+  int32_t x0;
+  int32_t slot;
+  float w0, w1;
+};
+
+// Transposed sensor operator, grouped by node: a row's groups have distinct
+// x, each summing its taps w * h[s] in a fixed order.
+struct SGroup {
+  int32_t x;
+  int32_t beg, end;
+};
+struct STap {
+  int32_t s;
+  float w;
+};
+
+// Everything one instance needs on the device.  Arrays are float32,
+// row-major with x fastest; "packed spectra" hold per row nx/2 complex
+// values of the x-transform, with bin 0 carrying (X[0], X[nx/2]) -- both real.
+struct DevPlan {
+  int32_t ndim;
+  int32_t n[3];      // nx, ny, nz (nz = 1 in 2D)
+  int32_t nrows;     // ny * nz
+  int32_t nt;
+  int32_t ns;
+  int32_t nslots;
+  int32_t lossy;
+  uint32_t flags;
+  float dt;
+  float kap;         // c_ref * dt / 2: kappa = sinc(kap * |k|)
+  float ym2h, ym1h;  // (y - 2)/2 and (y - 1)/2: |k|^(y-2) = (|k|^2)^ym2h
+  float inv_dt;
+  float scale;       // 1 / (nx ny nz): normalisation of a forward+inverse pair
+
+  // medium coefficients (N each)
+  const float* B[3];     // dt / rho0 at the staggered points of each axis
+  const float* dtr0;     // dt * rho0
+  const float* c2;       // c0^2
+  const float* c2tau;    // c0^2 tau
+  const float* c2eta;    // c0^2 eta
+  const float* inv_dc2;  // 1 / (d c0^2)
+
+  // per-axis 1-D tables
+  const float* Q[3];       // PML factor exp(-sigma dt/2) on nodes, length n[j]
+  const float* Qsg[3];     // ... on staggered points
+  const float* ksq[3];     // k_j^2; x: packed bins 0..nx/2, y/z: 0..n-1
+  const float2* shA[3];    // i k_j exp(+i k_j dx_j/2)
+  const float2* shB[3];    // i k_j exp(-i k_j dx_j/2)
+
+  // state (N floats each) and packed spectra (N/2 complex each)
+  float* u[3];
+  float* r[3];
+  float* q;
+  float2* S[4];
+
+  // sensors
+  const int32_t* g_ptr;   // [nrows + 1]
+  const GTap* g_tap;
+  const int32_t* s_ptr;   // [nrows + 1]
+  const SGroup* s_grp;
+  const STap* s_tap;
+  const int32_t* slot_ptr;  // [ns + 1]
+  float* partial;           // [nt][nslots]
+  int32_t* bad;             // non-finite flag (PAT_CHECK_FINITE)
+
+  // per-call I/O pointers (set by the executor before launching)
+  const float* in;   // p0 (forward) or data (adjoint)
+  float* out;        // data (forward) or image (adjoint)
+};
+
+// Step index of a launch: n = (ctr ? *ctr : 0) + k.  Graph-captured chunks
+// pass a device counter advanced once per chunk; eager launches pass k only.
+struct StepArg {
+  const int32_t* ctr;
+  int32_t k;
+};
+
+__device__ __forceinline__ int step_of(const StepArg& s) { return (s.ctr ? *s.ctr : 0) + s.k; }
+
+// multiplier kinds of the column passes
+enum Mult : int32_t {
+  M_AX = 0, M_AY = 1, M_AZ = 2,   // a_j = i k_j kappa e^{+i k_j dx_j/2}
+  M_BX = 3, M_BY = 4, M_BZ = 5,   // b_j = i k_j kappa e^{-i k_j dx_j/2}
+  M_L1DT = 6,                      // |k|^(y-2) / dt
+  M_L2 = 7,                        // |k|^(y-1)
+};
+
+// ---------------------------------------------------------------- launchers
+// (defined in passes.hip; all return hipError_t of the launch)
+struct Launch {
+  const DevPlan* plans;  // device array
+  const int2* table;     // device work table (instance, tile) or nullptr
+  int32_t nblocks;
+  hipStream_t stream;
+};
+
+enum RowKind : int32_t {
+  R_FWD_INIT = 0,
+  R_FWD_1 = 1,
+  R_FWD_2 = 2,       // lossy: density update, feeds the absorption pass
+  R_FWD_2LL = 3,     // lossless: density update + equation of state + gather
+  R_FWD_3 = 4,       // lossy equation of state + gather
+  R_ADJ_3 = 5,       // lossy: scatter, transposed equation of state (first half)
+  R_ADJ_32LL = 6,    // lossless: scatter + transposed state + density
+  R_ADJ_2 = 7,       // lossy: transposed absorption + density
+  R_ADJ_1 = 8,       // transposed velocity update
+  R_ADJ_FINAL = 9,   // transposed initial condition -> image
+  R_ADJ_SCATTER_ONLY = 10,  // nt == 1: image = W^T h[0]
+  R_COUNT = 11
+};
+
+hipError_t launch_row(RowKind kind, int ndim, int nx, const Launch& L, StepArg s);
+// rows per work item of the row passes for row length nx
+int row_tile_rows(int nx);
+
+// column passes along y (2D) -- and along y/z in 3D.
+// mode 0: out S[o] = mult[o] * in S[0]         (o = 1..nout)
+// mode 1: out S[f] = mult[f] * in S[f]         (blockIdx.y = field index f-1)
+// mode 2: out S[0] = sum_f mult[f] * in S[f]   (f = 1..nin)
+struct ColSpec {
+  int32_t mode;
+  int32_t nfield;
+  int32_t mult[3];
+};
+hipError_t launch_col(const ColSpec& spec, int ndim, int nx, int ny, int nz, const Launch& L);
+int col_tiles(int ndim, int nx, int ny, int nz);
+
+hipError_t launch_reduce(const Launch& L, int nt_max_ns_blocks);
+
+}  // namespace pat

@@ -1,0 +1,568 @@
+// Host runtime of libpat: plan construction, eager executors, C entry points.
+//
+// Plan construction derives every coefficient of the scheme in float64 and
+// rounds each once to float32:
+//   B_j     = dt / rho0_sg,j   (rho0 on the staggered points: mean of the two
+//                               neighbours, the last index keeps its value)
+//   dtr0    = dt rho0,  c2 = c0^2,  inv_dc2 = 1 / (d c0^2)
+//   c2tau   = c0^2 tau, c2eta = c0^2 eta with tau = -2 a0 c0^(y-1),
+//             eta = 2 a0 c0^y tan(pi y / 2)           (equation Twelve)
+//   a0      = alpha0_dB * 100 * (1e-6 / 2pi)^y / (20 log10 e)  [Np/((rad/s)^y m)]
+// plus the per-axis PML factors, the per-axis wavenumber tables and the
+// sensor interpolation operator with its transpose.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "pat_internal.h"
+
+namespace pat {
+hipError_t upload_twiddles(const Tw* host);
+}
+
+using namespace pat;
+
+struct pat_plan {
+  pat_desc desc{};
+  int device = 0;
+  double dt = 0, c_ref = 0;
+  int lossy = 0;
+  int64_t npoints = 0;
+  int nslots = 0;
+  DevPlan hp{};            // host image of the device record
+  DevPlan* dp = nullptr;   // device record
+  void* arena = nullptr;   // all device buffers of the plan
+  size_t arena_bytes = 0;
+  size_t state_bytes = 0;
+};
+
+namespace {
+
+#define PAT_TRY_HIP(x)                 \
+  do {                                 \
+    hipError_t e_ = (x);               \
+    if (e_ != hipSuccess) return PAT_EHIP; \
+  } while (0)
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+std::mutex g_tw_mu;
+std::vector<int> g_tw_ready;  // per device
+
+int ensure_twiddles() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PAT_EHIP;
+  std::lock_guard<std::mutex> lk(g_tw_mu);
+  if ((int)g_tw_ready.size() <= dev) g_tw_ready.resize(dev + 1, 0);
+  if (g_tw_ready[dev]) return PAT_OK;
+  std::vector<Tw> tw(TWN);
+  for (int q = 0; q < TWN; ++q) {
+    const double a = -2.0 * M_PI * (double)q / (double)TWN;
+    const double c = std::cos(a), s = std::sin(a);
+    const float ch = (float)c, sh = (float)s;
+    tw[q] = Tw{ch, sh, (float)(c - (double)ch), (float)(s - (double)sh)};
+  }
+  if (upload_twiddles(tw.data()) != hipSuccess) return PAT_EHIP;
+  g_tw_ready[dev] = 1;
+  return PAT_OK;
+}
+
+// Bump allocator over one device arena (256-byte aligned pieces).
+struct Carve {
+  size_t off = 0;
+  template <class T>
+  size_t take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    const size_t at = off;
+    off += count * sizeof(T);
+    return at;
+  }
+};
+
+double pml_factor(int n, int L, double alpha, double c_ref, double dx, double dt, int i, bool stag) {
+  if (L <= 0) return 1.0;
+  const double s = i + (stag ? 0.5 : 0.0);
+  double depth = 0.0;
+  if (s < L) depth = L - s;
+  if (s > (n - 1 - L)) depth = s - (n - 1 - L);
+  const double sigma = alpha * (c_ref / dx) * std::pow(depth / L, 4.0);
+  return std::exp(-sigma * dt / 2.0);
+}
+
+int validate_desc(const pat_desc* d, bool lossy) {
+  if (!d) return PAT_EINVAL;
+  if (d->ndim != 2 && d->ndim != 3) return PAT_EINVAL;
+  for (int j = 0; j < d->ndim; ++j) {
+    const int lim = d->ndim == 3 ? 256 : 1024;
+    if (!is_pow2(d->n[j]) || d->n[j] < 16 || d->n[j] > lim) return PAT_EINVAL;
+    if (!(d->dx[j] > 0) || !std::isfinite(d->dx[j]) || !std::isfinite(d->origin[j])) return PAT_EINVAL;
+    if (d->pml_size[j] < 0 || 2 * d->pml_size[j] >= d->n[j]) return PAT_EINVAL;
+  }
+  if (d->nt < 1) return PAT_EINVAL;
+  if (!std::isfinite(d->dt) || !std::isfinite(d->cfl)) return PAT_EINVAL;
+  if (d->dt <= 0 && !(d->cfl > 0)) return PAT_EINVAL;
+  if (!(d->pml_alpha >= 0) || !std::isfinite(d->pml_alpha)) return PAT_EINVAL;
+  if (lossy && !(d->alpha_power > 0 && d->alpha_power < 3 && d->alpha_power != 1.0)) return PAT_EINVAL;
+  if (d->n_sensors < 1) return PAT_EINVAL;
+  if (d->flags & ~(PAT_NO_PML | PAT_CHECK_FINITE)) return PAT_EINVAL;
+  return PAT_OK;
+}
+
+struct SensorOps {
+  std::vector<int32_t> g_ptr, s_ptr, slot_ptr;
+  std::vector<GTap> g_tap;
+  std::vector<SGroup> s_grp;
+  std::vector<STap> s_tap;
+  int nslots = 0;
+};
+
+// Linear-interpolation sensor operator: one gather tap per (sensor, row)
+// with non-zero row weight; the transposed operator grouped by node.
+int build_sensors(const pat_desc& d, const double* pos, SensorOps& so) {
+  const int nd = d.ndim, ns = d.n_sensors;
+  const int nx = d.n[0], ny = d.n[1], nz = nd == 3 ? d.n[2] : 1;
+  const int nrows = ny * nz;
+  struct RowTap {
+    int row, x0, slot, s;
+    double w0, w1;
+  };
+  std::vector<RowTap> taps;
+  so.slot_ptr.assign(ns + 1, 0);
+  int slot = 0;
+  for (int s = 0; s < ns; ++s) {
+    int lo[3] = {0, 0, 0};
+    double fr[3] = {0, 0, 0};
+    for (int j = 0; j < nd; ++j) {
+      const double g = (pos[(size_t)s * nd + j] - d.origin[j]) / d.dx[j];
+      if (!(g >= 0.0) || !(g <= (double)(d.n[j] - 1))) return PAT_EINVAL;
+      const int i0 = std::min((int)std::floor(g), d.n[j] - 2);
+      lo[j] = i0;
+      fr[j] = g - i0;
+    }
+    so.slot_ptr[s] = slot;
+    const int nrow_taps = nd == 3 ? 4 : 2;
+    for (int b = 0; b < nrow_taps; ++b) {
+      const int by = b & 1, bz = (b >> 1) & 1;
+      double w = by ? fr[1] : 1.0 - fr[1];
+      if (nd == 3) w *= bz ? fr[2] : 1.0 - fr[2];
+      if (w == 0.0) continue;
+      const int row = (lo[1] + by) + (nd == 3 ? (lo[2] + bz) * ny : 0);
+      taps.push_back(RowTap{row, lo[0], slot, s, w * (1.0 - fr[0]), w * fr[0]});
+      ++slot;
+    }
+    if (slot == so.slot_ptr[s]) return PAT_EINVAL;  // cannot happen: weights sum to 1
+  }
+  so.slot_ptr[ns] = slot;
+  so.nslots = slot;
+
+  // gather: CSR by row
+  std::stable_sort(taps.begin(), taps.end(), [](const RowTap& a, const RowTap& b) { return a.row < b.row; });
+  so.g_ptr.assign(nrows + 1, 0);
+  so.g_tap.clear();
+  for (const auto& t : taps) {
+    so.g_ptr[t.row + 1]++;
+    so.g_tap.push_back(GTap{t.x0, t.slot, (float)t.w0, (float)t.w1});
+  }
+  for (int r = 0; r < nrows; ++r) so.g_ptr[r + 1] += so.g_ptr[r];
+
+  // scatter: per row, node groups sorted by x, taps by sensor
+  struct NodeTap {
+    int row, x, s;
+    double w;
+  };
+  std::vector<NodeTap> nt;
+  for (const auto& t : taps) {
+    if (t.w0 != 0.0) nt.push_back(NodeTap{t.row, t.x0, t.s, t.w0});
+    if (t.w1 != 0.0) nt.push_back(NodeTap{t.row, t.x0 + 1, t.s, t.w1});
+  }
+  std::sort(nt.begin(), nt.end(), [](const NodeTap& a, const NodeTap& b) {
+    if (a.row != b.row) return a.row < b.row;
+    if (a.x != b.x) return a.x < b.x;
+    return a.s < b.s;
+  });
+  so.s_ptr.assign(nrows + 1, 0);
+  so.s_grp.clear();
+  so.s_tap.clear();
+  for (size_t i = 0; i < nt.size();) {
+    size_t j = i;
+    const int beg = (int)so.s_tap.size();
+    while (j < nt.size() && nt[j].row == nt[i].row && nt[j].x == nt[i].x) {
+      so.s_tap.push_back(STap{nt[j].s, (float)nt[j].w});
+      ++j;
+    }
+    so.s_grp.push_back(SGroup{nt[i].x, beg, (int)so.s_tap.size()});
+    so.s_ptr[nt[i].row + 1]++;
+    i = j;
+  }
+  for (int r = 0; r < nrows; ++r) so.s_ptr[r + 1] += so.s_ptr[r];
+  (void)nx;
+  return PAT_OK;
+}
+
+__global__ void k_set_io(DevPlan* p, const float* in, float* out) {
+  p->in = in;
+  p->out = out;
+}
+
+inline StepArg eager(int k) { return StepArg{nullptr, k}; }
+
+}  // namespace
+
+// ===================================================================== plan
+extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float* c0_d, const float* rho0_d,
+                               const float* alpha0_d, const double* sensor_pos, void* stream) {
+  if (!out) return PAT_EINVAL;
+  *out = nullptr;
+  const bool lossy = alpha0_d != nullptr;
+  int rc = validate_desc(desc, lossy);
+  if (rc) return rc;
+  if (!c0_d || !rho0_d || !sensor_pos) return PAT_EINVAL;
+  const pat_desc d = *desc;
+  if (d.ndim == 3) return PAT_ENOSYS;
+  hipStream_t st = (hipStream_t)stream;
+  const int nd = d.ndim;
+  const int nx = d.n[0], ny = d.n[1], nz = nd == 3 ? d.n[2] : 1;
+  const int64_t N = (int64_t)nx * ny * nz;
+  if ((rc = ensure_twiddles())) return rc;
+
+  // medium to host (float32 inputs, widened to float64)
+  std::vector<float> c0(N), rho0(N), a0db(lossy ? N : 0);
+  PAT_TRY_HIP(hipMemcpyAsync(c0.data(), c0_d, N * 4, hipMemcpyDeviceToHost, st));
+  PAT_TRY_HIP(hipMemcpyAsync(rho0.data(), rho0_d, N * 4, hipMemcpyDeviceToHost, st));
+  if (lossy) PAT_TRY_HIP(hipMemcpyAsync(a0db.data(), alpha0_d, N * 4, hipMemcpyDeviceToHost, st));
+  PAT_TRY_HIP(hipStreamSynchronize(st));
+  double cmax = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    if (!(c0[i] > 0) || !std::isfinite(c0[i]) || !(rho0[i] > 0) || !std::isfinite(rho0[i])) return PAT_EINVAL;
+    if (lossy && (!(a0db[i] >= 0) || !std::isfinite(a0db[i]))) return PAT_EINVAL;
+    cmax = std::max(cmax, (double)c0[i]);
+  }
+  double dxmin = d.dx[0];
+  for (int j = 1; j < nd; ++j) dxmin = std::min(dxmin, d.dx[j]);
+  const double dt = d.dt > 0 ? d.dt : d.cfl * dxmin / cmax;
+  if (cmax * dt / dxmin > (1.0 / std::sqrt((double)nd)) * (1.0 + 1e-12)) return PAT_EUNSTABLE;
+
+  SensorOps so;
+  if ((rc = build_sensors(d, sensor_pos, so))) return rc;
+
+  auto* p = new (std::nothrow) pat_plan();
+  if (!p) return PAT_ENOMEM;
+  p->desc = d;
+  hipGetDevice(&p->device);
+  p->dt = dt;
+  p->c_ref = cmax;
+  p->lossy = lossy;
+  p->npoints = N;
+  p->nslots = so.nslots;
+
+  // ---- device arena layout
+  const int M = nx / 2;
+  Carve cv;
+  size_t oB[3] = {0, 0, 0}, oQ[3], oQs[3], oK[3], oA[3], oBb[3], oU[3] = {0, 0, 0}, oR[3] = {0, 0, 0};
+  for (int j = 0; j < nd; ++j) oB[j] = cv.take<float>(N);
+  const size_t o_dtr0 = cv.take<float>(N), o_c2 = cv.take<float>(N), o_inv = cv.take<float>(N);
+  const size_t o_c2tau = lossy ? cv.take<float>(N) : 0, o_c2eta = lossy ? cv.take<float>(N) : 0;
+  int tlen[3];
+  for (int j = 0; j < nd; ++j) {
+    tlen[j] = (j == 0) ? M + 1 : d.n[j];
+    oQ[j] = cv.take<float>(d.n[j]);
+    oQs[j] = cv.take<float>(d.n[j]);
+    oK[j] = cv.take<float>(tlen[j]);
+    oA[j] = cv.take<float2>(tlen[j]);
+    oBb[j] = cv.take<float2>(tlen[j]);
+  }
+  const size_t state_begin = (cv.off + 255) & ~size_t(255);
+  for (int j = 0; j < nd; ++j) oU[j] = cv.take<float>(N);
+  for (int j = 0; j < nd; ++j) oR[j] = cv.take<float>(N);
+  const size_t state_end = cv.off;
+  const size_t o_q = cv.take<float>(N);
+  size_t oS[4] = {0, 0, 0, 0};
+  for (int j = 0; j <= nd; ++j) oS[j] = cv.take<float2>((size_t)N / 2);
+  const size_t o_gptr = cv.take<int32_t>(so.g_ptr.size()), o_gtap = cv.take<GTap>(std::max<size_t>(1, so.g_tap.size()));
+  const size_t o_sptr = cv.take<int32_t>(so.s_ptr.size()), o_sgrp = cv.take<SGroup>(std::max<size_t>(1, so.s_grp.size()));
+  const size_t o_stap = cv.take<STap>(std::max<size_t>(1, so.s_tap.size()));
+  const size_t o_slot = cv.take<int32_t>(so.slot_ptr.size());
+  const size_t o_part = cv.take<float>((size_t)d.nt * so.nslots);
+  const size_t o_bad = cv.take<int32_t>(1);
+  const size_t o_rec = cv.take<DevPlan>(1);
+  p->arena_bytes = (cv.off + 255) & ~size_t(255);
+  p->state_bytes = state_end - state_begin;
+  if (hipMalloc(&p->arena, p->arena_bytes) != hipSuccess) {
+    delete p;
+    return PAT_ENOMEM;
+  }
+  char* A = (char*)p->arena;
+
+  // ---- host-side coefficient arrays (float64 -> float32 once)
+  std::vector<char> hbuf(state_begin, 0);
+  auto hf = [&](size_t off) { return reinterpret_cast<float*>(hbuf.data() + off); };
+  auto hc = [&](size_t off) { return reinterpret_cast<float2*>(hbuf.data() + off); };
+  const int64_t strides[3] = {1, nx, (int64_t)nx * ny};
+  const double y = d.alpha_power;
+  const double a_conv = 100.0 * std::pow(1e-6 / (2.0 * M_PI), y) / (20.0 * std::log10(std::exp(1.0)));
+  const double tan_y = std::tan(M_PI * y / 2.0);
+  for (int64_t i = 0; i < N; ++i) {
+    const double c = c0[i], r = rho0[i];
+    for (int j = 0; j < nd; ++j) {
+      const int64_t ij = (i / strides[j]) % d.n[j];
+      const double rn = (ij + 1 < d.n[j]) ? (double)rho0[i + strides[j]] : r;
+      hf(oB[j])[i] = (float)(dt / (0.5 * (r + rn)));
+    }
+    hf(o_dtr0)[i] = (float)(dt * r);
+    hf(o_c2)[i] = (float)(c * c);
+    hf(o_inv)[i] = (float)(1.0 / (nd * c * c));
+    if (lossy) {
+      const double a0 = (double)a0db[i] * a_conv;
+      const double tau = -2.0 * a0 * std::pow(c, y - 1.0);
+      const double eta = 2.0 * a0 * std::pow(c, y) * tan_y;
+      hf(o_c2tau)[i] = (float)(c * c * tau);
+      hf(o_c2eta)[i] = (float)(c * c * eta);
+    }
+  }
+  const bool pml_on = !(d.flags & PAT_NO_PML);
+  for (int j = 0; j < nd; ++j) {
+    const int n = d.n[j];
+    const int L = pml_on ? d.pml_size[j] : 0;
+    for (int i = 0; i < n; ++i) {
+      hf(oQ[j])[i] = (float)pml_factor(n, L, d.pml_alpha, cmax, d.dx[j], dt, i, false);
+      hf(oQs[j])[i] = (float)pml_factor(n, L, d.pml_alpha, cmax, d.dx[j], dt, i, true);
+    }
+    for (int m = 0; m < tlen[j]; ++m) {
+      const int mt = (m < n / 2) ? m : m - n;
+      const double k = 2.0 * M_PI * mt / (n * d.dx[j]);
+      const double h = k * d.dx[j] / 2.0;
+      hf(oK[j])[m] = (float)(k * k);
+      if (2 * m == n) {  // Nyquist: i k e^{+-i pi/2} is exactly real
+        hc(oA[j])[m] = make_float2((float)k, 0.f);
+        hc(oBb[j])[m] = make_float2((float)(-k), 0.f);
+      } else {
+        hc(oA[j])[m] = make_float2((float)(-k * std::sin(h)), (float)(k * std::cos(h)));
+        hc(oBb[j])[m] = make_float2((float)(k * std::sin(h)), (float)(k * std::cos(h)));
+      }
+    }
+  }
+  PAT_TRY_HIP(hipMemcpyAsync(A, hbuf.data(), state_begin, hipMemcpyHostToDevice, st));
+
+  auto up = [&](size_t off, const void* src, size_t bytes) -> int {
+    if (bytes == 0) return PAT_OK;
+    return hipMemcpyAsync(A + off, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess ? PAT_OK : PAT_EHIP;
+  };
+  rc = up(o_gptr, so.g_ptr.data(), so.g_ptr.size() * 4);
+  if (!rc) rc = up(o_gtap, so.g_tap.data(), so.g_tap.size() * sizeof(GTap));
+  if (!rc) rc = up(o_sptr, so.s_ptr.data(), so.s_ptr.size() * 4);
+  if (!rc) rc = up(o_sgrp, so.s_grp.data(), so.s_grp.size() * sizeof(SGroup));
+  if (!rc) rc = up(o_stap, so.s_tap.data(), so.s_tap.size() * sizeof(STap));
+  if (!rc) rc = up(o_slot, so.slot_ptr.data(), so.slot_ptr.size() * 4);
+  if (!rc && hipMemsetAsync(A + o_bad, 0, 4, st) != hipSuccess) rc = PAT_EHIP;
+
+  DevPlan& h = p->hp;
+  h.ndim = nd;
+  h.n[0] = nx;
+  h.n[1] = ny;
+  h.n[2] = nz;
+  h.nrows = ny * nz;
+  h.nt = d.nt;
+  h.ns = d.n_sensors;
+  h.nslots = so.nslots;
+  h.lossy = lossy;
+  h.flags = d.flags;
+  h.dt = (float)dt;
+  h.kap = (float)(cmax * dt / 2.0);
+  h.ym2h = (float)((y - 2.0) / 2.0);
+  h.ym1h = (float)((y - 1.0) / 2.0);
+  h.inv_dt = (float)(1.0 / dt);
+  h.scale = (float)(1.0 / (double)N);
+  for (int j = 0; j < nd; ++j) {
+    h.B[j] = (const float*)(A + oB[j]);
+    h.Q[j] = (const float*)(A + oQ[j]);
+    h.Qsg[j] = (const float*)(A + oQs[j]);
+    h.ksq[j] = (const float*)(A + oK[j]);
+    h.shA[j] = (const float2*)(A + oA[j]);
+    h.shB[j] = (const float2*)(A + oBb[j]);
+    h.u[j] = (float*)(A + oU[j]);
+    h.r[j] = (float*)(A + oR[j]);
+  }
+  h.dtr0 = (const float*)(A + o_dtr0);
+  h.c2 = (const float*)(A + o_c2);
+  h.inv_dc2 = (const float*)(A + o_inv);
+  h.c2tau = lossy ? (const float*)(A + o_c2tau) : nullptr;
+  h.c2eta = lossy ? (const float*)(A + o_c2eta) : nullptr;
+  h.q = (float*)(A + o_q);
+  for (int j = 0; j <= nd; ++j) h.S[j] = (float2*)(A + oS[j]);
+  h.g_ptr = (const int32_t*)(A + o_gptr);
+  h.g_tap = (const GTap*)(A + o_gtap);
+  h.s_ptr = (const int32_t*)(A + o_sptr);
+  h.s_grp = (const SGroup*)(A + o_sgrp);
+  h.s_tap = (const STap*)(A + o_stap);
+  h.slot_ptr = (const int32_t*)(A + o_slot);
+  h.partial = (float*)(A + o_part);
+  h.bad = (int32_t*)(A + o_bad);
+  p->dp = (DevPlan*)(A + o_rec);
+  if (!rc) rc = up(o_rec, &h, sizeof(DevPlan));
+  if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = PAT_EHIP;
+  if (rc) {
+    hipFree(p->arena);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return PAT_OK;
+}
+
+extern "C" void pat_plan_destroy(pat_plan* p) {
+  if (!p) return;
+  hipDeviceSynchronize();
+  hipFree(p->arena);
+  delete p;
+}
+
+extern "C" int pat_plan_info(const pat_plan* p, pat_info* info) {
+  if (!p || !info) return PAT_EINVAL;
+  info->dt = p->dt;
+  info->c_ref = p->c_ref;
+  info->npoints = p->npoints;
+  info->lossy = p->lossy;
+  info->n_slots = p->nslots;
+  info->device_bytes = p->arena_bytes;
+  info->state_bytes = p->state_bytes;
+  return PAT_OK;
+}
+
+// ===================================================================== eager executors
+namespace {
+
+struct Eager {
+  const pat_plan* p;
+  hipStream_t st;
+  Launch L(int nblocks) const { return Launch{p->dp, nullptr, nblocks, st}; }
+  int rows_blocks() const {
+    const int R = row_tile_rows(p->desc.n[0]);
+    return (p->hp.nrows + R - 1) / R;
+  }
+  int row(RowKind k, int step) const {
+    return launch_row(k, p->desc.ndim, p->desc.n[0], L(rows_blocks()), eager(step)) == hipSuccess ? PAT_OK
+                                                                                                 : PAT_EHIP;
+  }
+  int col(int mode, int nf, int m0, int m1, int m2 = 0) const {
+    ColSpec cs{mode, nf, {m0, m1, m2}};
+    const int nb = col_tiles(p->desc.ndim, p->desc.n[0], p->desc.n[1], p->hp.n[2]);
+    return launch_col(cs, p->desc.ndim, p->desc.n[0], p->desc.n[1], p->hp.n[2], L(nb)) == hipSuccess ? PAT_OK
+                                                                                                     : PAT_EHIP;
+  }
+  int reduce() const {
+    const long total = (long)p->desc.nt * p->desc.n_sensors;
+    return launch_reduce(L((int)((total + 255) / 256)), 0) == hipSuccess ? PAT_OK : PAT_EHIP;
+  }
+  int set_io(const float* in, float* out) const {
+    hipLaunchKernelGGL(k_set_io, dim3(1), dim3(1), 0, st, p->dp, in, out);
+    return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
+  }
+};
+
+// forward steps n in [n0, n1): each computes p^{n+1} and records sample n+1
+int forward_steps(const Eager& X, int n0, int n1) {
+  const bool lossy = X.p->lossy;
+  int rc = PAT_OK;
+  for (int n = n0; n < n1 && !rc; ++n) {
+    rc = X.col(0, 2, M_AX, M_AY);
+    if (!rc) rc = X.row(R_FWD_1, n);
+    if (!rc) rc = X.col(1, 2, M_BX, M_BY);
+    if (lossy) {
+      if (!rc) rc = X.row(R_FWD_2, n);
+      if (!rc) rc = X.col(1, 2, M_L1DT, M_L2);
+      if (!rc) rc = X.row(R_FWD_3, n);
+    } else {
+      if (!rc) rc = X.row(R_FWD_2LL, n);
+    }
+  }
+  return rc;
+}
+
+int adjoint_steps(const Eager& X) {
+  const bool lossy = X.p->lossy;
+  const int nt = X.p->desc.nt;
+  int rc = PAT_OK;
+  for (int i = 0; i + 1 < nt && !rc; ++i) {
+    if (lossy) {
+      rc = X.row(R_ADJ_3, i);
+      if (!rc) rc = X.col(1, 2, M_L2, M_L1DT);
+      if (!rc) rc = X.row(R_ADJ_2, i);
+    } else {
+      rc = X.row(R_ADJ_32LL, i);
+    }
+    if (!rc) rc = X.col(1, 2, M_AX, M_AY);
+    if (!rc) rc = X.row(R_ADJ_1, i);
+    if (!rc) rc = X.col(2, 2, M_BX, M_BY);
+  }
+  return rc;
+}
+
+}  // namespace
+
+extern "C" int pat_forward(pat_plan* p, const float* p0, float* data, void* stream) {
+  if (!p || !p0 || !data) return PAT_EINVAL;
+  Eager X{p, (hipStream_t)stream};
+  int rc = X.set_io(p0, data);
+  if (!rc) rc = X.row(R_FWD_INIT, 0);
+  if (!rc) rc = forward_steps(X, 0, p->desc.nt - 1);
+  if (!rc) rc = X.reduce();
+  return rc;
+}
+
+extern "C" int pat_adjoint(pat_plan* p, const float* data, float* img, void* stream) {
+  if (!p || !data || !img) return PAT_EINVAL;
+  Eager X{p, (hipStream_t)stream};
+  int rc = X.set_io(data, img);
+  if (rc) return rc;
+  if (p->desc.nt == 1) return X.row(R_ADJ_SCATTER_ONLY, 0);
+  rc = adjoint_steps(X);
+  if (!rc) rc = X.row(R_ADJ_FINAL, 0);
+  return rc;
+}
+
+extern "C" int pat_forward_range(pat_plan*, const float*, float*, int32_t, int32_t, void*, void*) {
+  return PAT_ENOSYS;
+}
+
+extern "C" int pat_plan_sync(pat_plan* p, void* stream) {
+  if (!p) return PAT_EINVAL;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PAT_EHIP;
+  int32_t bad = 0;
+  if (hipMemcpy(&bad, p->hp.bad, 4, hipMemcpyDeviceToHost) != hipSuccess) return PAT_EHIP;
+  if (bad) {
+    if (hipMemset(p->hp.bad, 0, 4) != hipSuccess) return PAT_EHIP;
+    return PAT_ENONFINITE;
+  }
+  return PAT_OK;
+}
+
+extern "C" const char* pat_strerror(int code) {
+  switch (code) {
+    case PAT_OK: return "ok";
+    case PAT_EINVAL: return "invalid argument";
+    case PAT_EUNSTABLE: return "time step above the stability bound";
+    case PAT_ENOMEM: return "out of memory";
+    case PAT_EHIP: return "HIP runtime error";
+    case PAT_ENONFINITE: return "non-finite pressure produced";
+    case PAT_ENOSYS: return "not supported by this build";
+  }
+  return "unknown error";
+}
+
+// ===================================================================== batched (filled by the batch executor)
+struct pat_batch {
+  int dummy;
+};
+extern "C" int pat_batch_create(pat_batch** out, pat_plan* const*, int32_t, int32_t) {
+  if (out) *out = nullptr;
+  return PAT_ENOSYS;
+}
+extern "C" void pat_batch_destroy(pat_batch*) {}
+extern "C" int pat_batch_forward(pat_batch*, const float* const*, float* const*, void*) { return PAT_ENOSYS; }
+extern "C" int pat_batch_adjoint(pat_batch*, const float* const*, float* const*, void*) { return PAT_ENOSYS; }

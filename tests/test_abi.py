@@ -1,0 +1,96 @@
+"""Host-side checks of the C ABI: the library loads and exports every
+declared symbol, and the pure-host entry points validate their arguments
+(no kernel is launched by any of these)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1603_02329_amd as pat
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pat.h")).read()
+    return sorted(set(re.findall(r"\b(pat_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pat.lib()
+    declared = _declared()
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(pat.EXPORTED) == declared
+
+
+def test_strerror_codes():
+    L = pat.lib()
+    for code in range(7):
+        assert L.pat_strerror(code)
+    assert L.pat_strerror(99) == b"unknown error"
+
+
+def test_prox_work_bytes():
+    L = pat.lib()
+    n = (ctypes.c_int32 * 3)(512, 256, 1)
+    assert L.pat_tv_prox_work_bytes(2, n) == 5 * 512 * 256 * 4
+    n3 = (ctypes.c_int32 * 3)(8, 8, 8)
+    assert L.pat_tv_prox_work_bytes(3, n3) == 7 * 512 * 4
+    assert L.pat_tv_prox_work_bytes(4, n3) == 0
+
+
+def test_plan_create_rejects_bad_descriptors_on_host():
+    """Descriptor validation happens before any device access."""
+    L = pat.lib()
+    import synth
+    base = synth.small_instance(1, (16, 16), nt=4).desc
+    cd4 = pat.make_desc(base, 3)
+    cd4.ndim = 4
+    h0 = ctypes.c_void_p()
+    assert L.pat_plan_create(ctypes.byref(h0), ctypes.byref(cd4), ctypes.c_void_p(16), ctypes.c_void_p(16), None,
+                             (ctypes.c_double * 6)(), None) == pat.PAT_EINVAL
+    bad = [
+        dict(n=(24, 16)), dict(n=(8, 16)), dict(n=(2048, 16)), dict(nt=0),
+        dict(pml_size=(8, 2, 0)), dict(dx=(0.0, 1e-4)), dict(dt=0.0, cfl=0.0),
+    ]
+    from dataclasses import replace
+    for kw in bad:
+        d = replace(base, **kw)
+        cd = pat.make_desc(d, 3)
+        h = ctypes.c_void_p()
+        dummy = ctypes.c_void_p(16)
+        pos = (ctypes.c_double * 6)()
+        rc = L.pat_plan_create(ctypes.byref(h), ctypes.byref(cd), dummy, dummy, None, pos, None)
+        assert rc == pat.PAT_EINVAL, kw
+    # bad power-law exponent only matters for a lossy medium
+    d = replace(base, alpha_power=1.0)
+    cd = pat.make_desc(d, 3)
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)
+    assert L.pat_plan_create(ctypes.byref(h), ctypes.byref(cd), dummy, dummy, dummy, (ctypes.c_double * 6)(),
+                             None) == pat.PAT_EINVAL
+    # NULL arguments
+    cd = pat.make_desc(base, 3)
+    assert L.pat_plan_create(ctypes.byref(h), ctypes.byref(cd), None, dummy, None, (ctypes.c_double * 6)(),
+                             None) == pat.PAT_EINVAL
+    assert L.pat_plan_create(None, ctypes.byref(cd), dummy, dummy, None, (ctypes.c_double * 6)(),
+                             None) == pat.PAT_EINVAL
+
+
+def test_null_plan_calls_are_rejected():
+    L = pat.lib()
+    assert L.pat_forward(None, None, None, None) == pat.PAT_EINVAL
+    assert L.pat_adjoint(None, None, None, None) == pat.PAT_EINVAL
+    assert L.pat_plan_info(None, None) == pat.PAT_EINVAL
+    assert L.pat_plan_sync(None, None) == pat.PAT_EINVAL
+    L.pat_plan_destroy(None)
+    n = (ctypes.c_int32 * 3)(16, 16, 1)
+    assert L.pat_restrict(2, n, None, None, None) == pat.PAT_EINVAL
+    assert L.pat_prolong(5, n, None, None, None) == pat.PAT_EINVAL
+    assert L.pat_tv_prox(2, n, None, None, 0.1, 20, None, None, 0, None) == pat.PAT_EINVAL
+    out = ctypes.c_double(7.0)
+    assert L.pat_dot_f64(None, None, 0, ctypes.byref(out), None) == pat.PAT_OK and out.value == 0.0
+    assert L.pat_dot_f64(None, None, 5, ctypes.byref(out), None) == pat.PAT_EINVAL
