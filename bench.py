@@ -1,0 +1,213 @@
+"""Benchmark: forward+adjoint grid-point-steps per second on one MI355X.
+
+A step is one gradient-and-prox iteration over a whole batch of synthetic
+problems: the batched forward H x for every instance, the float32 residual
+with its float64 half squared norm (the least-squares objective), the
+batched adjoint H^T r (the gradient), then x <- prox(x - alpha grad) with 20
+FGP iterations of the TV prox.  Throughput counts 2 * N * N_t grid-point
+steps per instance (forward and adjoint), over the wall time of the step.
+
+Default workload: 48 uneven 2D instances, 16 each of 128^2 (N_t 600),
+256^2 (N_t 1200) and 512^2 (N_t 2400), heterogeneous lossy media.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "forward+adjoint grid-point-steps/s, batched vs plain FP32, at rel-L2 ≤1e-5"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name: str):
+    import synth
+    if name == "cfg4":
+        return synth.config4(), "48 x 2D lossy heterogeneous: 16x128^2/Nt600 + 16x256^2/Nt1200 + 16x512^2/Nt2400"
+    if name == "cfg2":
+        return [synth.config2()], "2D 256^2 lossy heterogeneous, Nt 1200, 256 sensors"
+    if name == "cfg3":
+        f, c = synth.config3()
+        return [f, c], "2D two-level: 512^2/Nt2400 + 256^2/Nt1200 lossy heterogeneous"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(insts, seconds_target=15.0):
+    """The FP64 oracle on a bounded sample: one instance of each grid size,
+    a shortened time axis, forward + adjoint."""
+    from dataclasses import replace
+
+    from oracle import kspace as K
+    cores = min(os.cpu_count() or 1, 16)
+    K.WORKERS = cores
+    seen = {}
+    for inst in insts:
+        seen.setdefault(inst.desc.n, inst)
+    sample = list(seen.values())
+    nts = 41
+    gps = 0.0
+    t_total = 0.0
+    for inst in sample:
+        d = replace(inst.desc, nt=nts)
+        op = K.make_plan(d, inst.c0, inst.rho0, inst.alpha0_db, inst.sensors)
+        t0 = time.perf_counter()
+        data = K.forward(op, inst.p0)
+        K.adjoint(op, data)
+        t_total += time.perf_counter() - t0
+        gps += 2.0 * inst.desc.npoints * nts
+    sizes = "+".join(f"{i.desc.n[0]}^2" for i in sample)
+    return {"value": gps / t_total, "unit": "grid-point-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle forward+adjoint of one instance per size ({sizes}) with N_t={nts} "
+                      f"instead of the full time axis; {t_total:.1f} s on {cores} threads (scipy.fft workers)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg4")
+    ap.add_argument("--chunk", type=int, default=32, help="graph chunk (steps per captured graph; 1 = eager)")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--time-pass", default="0:1", help="direction:pass_index timed with HIP events")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the solver runs each instance on a single device "
+              "(see DESIGN.md for how the path would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1603_02329_amd as pat
+    dev = torch.device("cuda:0")
+    insts, wl_name = workload(args.workload)
+    log(f"workload: {wl_name} ({len(insts)} instances)")
+    plans = [pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=dev) for i in insts]
+    x_true = [torch.from_numpy(i.p0).to(dev) for i in insts]
+    batch = pat.Batch(plans, chunk=args.chunk)
+    targets = [d.clone() for d in batch.forward(x_true)]
+    xs = [0.5 * x for x in x_true]
+    total_gps = sum(2.0 * p.npoints * p.nt for p in plans)
+    tvw = [torch.empty(max(1, pat.lib().pat_tv_prox_work_bytes(2, pat._i32x3(list(reversed(x.shape))))),
+                       dtype=torch.uint8, device=dev) for x in xs]
+    alpha = 1e-3
+    lam = 1e-3
+
+    def step(run_forward, run_adjoint):
+        datas = run_forward(xs)
+        res, loss = [], 0.0
+        for d, t in zip(datas, targets):
+            r, half = pat.residual_f64(d, t)
+            res.append(r)
+            loss += half
+        grads = run_adjoint(res)
+        for k, (x, g) in enumerate(zip(xs, grads)):
+            xs[k] = pat.tv_prox(x - alpha * g, alpha * lam, 20, work=tvw[k])
+        return loss
+
+    batched = (batch.forward, batch.adjoint)
+    plain = (lambda X: [p.forward(x) for p, x in zip(plans, X)],
+             lambda R: [p.adjoint(r) for p, r in zip(plans, R)])
+
+    def timed(fns, steps, warmup, label):
+        for _ in range(warmup):
+            step(*fns)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            step(*fns)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / steps
+        log(f"{label}: {ms:.1f} ms/step (host wall {wall / steps * 1e3:.1f} ms/step), "
+            f"{total_gps / (ms / 1e3) / 1e9:.2f} G gps/s")
+        return ms
+
+    # main timed region: batched executor; the selected pass is timed with
+    # HIP events on its stream when the batch runs eagerly (chunk 1)
+    tdir, tidx = (int(v) for v in args.time_pass.split(":"))
+    pat.timing_begin(tdir, tidx)
+    ms = timed(batched, args.steps, args.warmup, f"batched(chunk={args.chunk})")
+    k_ms, k_n, k_bytes = pat.timing_end()
+    if k_n == 0:
+        # graph-captured launches are not event-timed: time the same pass
+        # over the same batch with an eager (chunk 1) batch right after
+        b1 = pat.Batch(plans, chunk=1)
+        pat.timing_begin(tdir, tidx)
+        step(b1.forward, b1.adjoint)
+        torch.cuda.synchronize()
+        k_ms, k_n, k_bytes = pat.timing_end()
+        b1.close()
+        kernel_note = "eager batch run right after the timed region"
+    else:
+        kernel_note = "timed region"
+    plain_ms = None
+    if not args.no_plain:
+        plain_ms = timed(plain, 1, 0, "plain (one instance at a time, eager)")
+    value = total_gps / (ms / 1e3)
+    achieved = k_bytes / (k_ms / 1e3) / 1e9 if k_ms > 0 else 0.0
+    names = {(0, 0): "col gradient", (0, 1): "row velocity", (0, 2): "col divergence", (0, 3): "row density",
+             (0, 4): "col absorption", (0, 5): "row state+gather", (1, 0): "row adj-state+scatter",
+             (1, 1): "col adj-absorption", (1, 2): "row adj-density", (1, 3): "col adj-gradient",
+             (1, 4): "row adj-velocity", (1, 5): "col adj-divergence"}
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": wl_name,
+            "instances": len(plans),
+            "gps_per_step": total_gps,
+            "executor": f"batched, graph chunk {args.chunk}",
+            "plain_ms_per_step": plain_ms,
+            "batched_over_plain": (plain_ms / ms) if plain_ms else None,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": names.get((tdir, tidx), f"{tdir}:{tidx}"),
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "launches": k_n,
+            "avg_launch_us": (k_ms / k_n * 1e3) if k_n else None,
+            "measured_in": kernel_note,
+            "step_frac": value * 152.0 / (HBM_PEAK_GBS * 1e9),
+        },
+    }
+    if not args.no_cpu:
+        log("timing the FP64 oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(insts)
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

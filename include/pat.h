@@ -151,10 +151,12 @@ int pat_adjoint(pat_plan* plan, const float* data, float* img, void* stream);
  * of `data` outside that range are not touched).
  *
  *  n_begin == 0  starts from p0 (state_io is only written);
- *  n_begin  > 0  resumes from the snapshot in state_io, which must hold the
- *                state at sample n_begin written by an earlier call
+ *  n_begin  > 0  resumes from the snapshot in state_io, which must be the one
+ *                written by an earlier call that ended at n_end == n_begin
  *                (p0 is then ignored and may be NULL).
- *  state_io      device, info.state_bytes bytes; receives the state at n_end.
+ *  state_io      device, info.state_bytes bytes; on return it holds the
+ *                scheme's state after sample n_end-1 (velocities, split
+ *                densities and the x-spectrum of the pressure).
  *
  * Running [0, k) then [k, nt) gives bitwise the same data as pat_forward.
  */
@@ -233,6 +235,28 @@ int pat_residual_f64(const float* a, const float* b, float* r, int64_t n, double
  * pressure value was produced since the last sync (the flag is then cleared).
  */
 int pat_plan_sync(pat_plan* plan, void* stream);
+
+/*
+ * Diagnostics: HIP-event timing of one pass of the time step.
+ *
+ * pat_timing_begin selects pass `pass_index` (0-based position in the step's
+ * launch sequence) of direction 0 (forward) or 1 (adjoint); every later
+ * eager launch of that pass -- by pat_forward, pat_adjoint, pat_forward_range
+ * or a batch created with chunk = 1 -- is bracketed by HIP events on its
+ * stream.  pat_timing_end waits for those events and returns their summed
+ * duration [ms], the number of launches and the algorithmic bytes they moved
+ * (full-grid float32 arrays each pass must read and write, per grid point,
+ * times the points the launch covers).  Not thread-safe against concurrent
+ * begin/end calls; launches captured into graphs are not timed.
+ *
+ * Forward lossy 2D sequence: 0 gradient (column), 1 velocity (row),
+ * 2 divergence (column), 3 density (row), 4 absorption (column),
+ * 5 equation of state + sensors (row).  Adjoint lossy 2D: 0 transposed state
+ * (row), 1 absorption (column), 2 density (row), 3 gradient (column),
+ * 4 velocity (row), 5 divergence sum (column).
+ */
+int pat_timing_begin(int32_t direction, int32_t pass_index);
+int pat_timing_end(double* total_ms, int64_t* launches, double* alg_bytes);
 
 /* Static description of a return code. */
 const char* pat_strerror(int code);

@@ -28,7 +28,8 @@ EXPORTED = [
     "pat_plan_create", "pat_plan_destroy", "pat_plan_info", "pat_forward", "pat_adjoint",
     "pat_forward_range", "pat_batch_create", "pat_batch_destroy", "pat_batch_forward",
     "pat_batch_adjoint", "pat_tv_prox_work_bytes", "pat_tv_prox", "pat_restrict", "pat_prolong",
-    "pat_dot_f64", "pat_residual_f64", "pat_plan_sync", "pat_strerror",
+    "pat_dot_f64", "pat_residual_f64", "pat_plan_sync", "pat_strerror", "pat_timing_begin",
+    "pat_timing_end",
 ]
 
 
@@ -88,6 +89,8 @@ def lib() -> ctypes.CDLL:
         "pat_residual_f64": (ctypes.c_int, [vp, vp, vp, i64, ctypes.POINTER(f64), vp]),
         "pat_plan_sync": (ctypes.c_int, [vp, vp]),
         "pat_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "pat_timing_begin": (ctypes.c_int, [i32, i32]),
+        "pat_timing_end": (ctypes.c_int, [ctypes.POINTER(f64), ctypes.POINTER(i64), ctypes.POINTER(f64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -284,6 +287,18 @@ class Batch:
         b = (ctypes.c_void_p * len(self.plans))(*[_dev_f32(x, "img", p.npoints).value for p, x in zip(self.plans, imgs)])
         _check(lib().pat_batch_adjoint(self._h, a, b, _stream()), "pat_batch_adjoint")
         return imgs
+
+
+def timing_begin(direction: int, pass_index: int) -> None:
+    """Start HIP-event timing of one pass of the time step (see pat.h)."""
+    _check(lib().pat_timing_begin(int(direction), int(pass_index)), "pat_timing_begin")
+
+
+def timing_end():
+    """(total milliseconds, launches, algorithmic bytes) of the timed pass."""
+    ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+    _check(lib().pat_timing_end(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)), "pat_timing_end")
+    return ms.value, n.value, b.value
 
 
 def tv_prox(z, lam: float, n_iter: int = 20, lower=None, out=None, work=None):

@@ -1,0 +1,549 @@
+// Executors of the time loop: eager (one instance, launches on the caller's
+// stream) and batched (many instances, one launch per pass over a work table
+// of every instance of a size class, time loop captured into HIP graphs).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "pat_internal.h"
+
+namespace pat {
+
+// ------------------------------------------------------------------ pass sequences
+int step_ops(int dir, int lossy, PassOp* ops) {
+  int n = 0;
+  auto row = [&](RowKind k) { ops[n++] = PassOp{0, k, ColSpec{0, 0, {0, 0, 0}}}; };
+  auto col = [&](int mode, int nf, int a, int b) { ops[n++] = PassOp{1, R_COUNT, ColSpec{mode, nf, {a, b, 0}}}; };
+  if (dir == 0) {
+    col(0, 2, M_AX, M_AY);  // gradient of p at the staggered points
+    row(R_FWD_1);           // velocity update
+    col(1, 2, M_BX, M_BY);  // divergence components back on the nodes
+    if (lossy) {
+      row(R_FWD_2);             // density update
+      col(1, 2, M_L1DT, M_L2);  // fractional Laplacians
+      row(R_FWD_3);             // equation of state + sensors
+    } else {
+      row(R_FWD_2LL);  // density update + equation of state + sensors
+    }
+  } else {
+    if (lossy) {
+      row(R_ADJ_3);
+      col(1, 2, M_L2, M_L1DT);
+      row(R_ADJ_2);
+    } else {
+      row(R_ADJ_32LL);
+    }
+    col(1, 2, M_AX, M_AY);
+    row(R_ADJ_1);
+    col(2, 2, M_BX, M_BY);
+  }
+  return n;
+}
+
+double pass_bytes_per_point(const PassOp& op, int ndim, int lossy) {
+  (void)lossy;
+  const int d = ndim;
+  if (op.is_col) {
+    const int f = op.col.nfield;
+    // packed spectra: 4 bytes per grid point and field
+    if (op.col.mode == 0) return 4.0 * (1 + f);
+    if (op.col.mode == 1) return 8.0 * f;
+    return 4.0 * (f + 1);
+  }
+  switch (op.row) {
+    case R_FWD_INIT: return 4.0 * (d + 3);       // p0, 1/(d c0^2) -> rho_j, S0
+    case R_FWD_1: return 20.0 * d;               // S_j, u_j, B_j -> u_j, S_j
+    case R_FWD_2: return 4.0 * (3 * d + 3);      // S_j, rho_j, dt rho0 -> rho_j, S1, S2
+    case R_FWD_2LL: return 4.0 * (3 * d + 3);    // S_j, rho_j, dt rho0, c0^2 -> rho_j, S0
+    case R_FWD_3: return 4.0 * (d + 6);          // S1, S2, rho_j, c0^2, c0^2 tau, c0^2 eta -> S0
+    case R_ADJ_3: return 28.0;                   // S0, c0^2, c0^2 eta, c0^2 tau -> q, S1, S2
+    case R_ADJ_32LL: return 4.0 * (3 * d + 3);   // S0, c0^2, rho_j, dt rho0 -> rho_j, S_j
+    case R_ADJ_2: return 4.0 * (3 * d + 4);      // S1, S2, q, rho_j, dt rho0 -> rho_j, S_j
+    case R_ADJ_1: return 20.0 * d;               // S_j, u_j, B_j -> u_j, S_j
+    case R_ADJ_FINAL: return 4.0 * (d + 3);      // S0, rho_j, 1/(d c0^2) -> image
+    case R_ADJ_SCATTER_ONLY: return 4.0;
+    default: return 0.0;
+  }
+}
+
+namespace {
+
+// ------------------------------------------------------------------ event timing
+struct Timing {
+  int dir = -1, index = -1;
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  double bytes = 0;
+  long launches = 0;
+};
+std::mutex g_tmu;
+Timing g_timing;
+bool g_timing_on = false;
+
+struct TimeScope {
+  bool on = false;
+  hipStream_t st;
+  hipEvent_t e1 = nullptr;
+  TimeScope(int dir, int idx, hipStream_t s, double bytes) : st(s) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing_on || g_timing.dir != dir || g_timing.index != idx) return;
+    if (g_timing.used + 2 > g_timing.ev.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+      g_timing.ev.push_back(a);
+      g_timing.ev.push_back(b);
+    }
+    hipEvent_t e0 = g_timing.ev[g_timing.used];
+    e1 = g_timing.ev[g_timing.used + 1];
+    g_timing.used += 2;
+    g_timing.bytes += bytes;
+    g_timing.launches += 1;
+    hipEventRecord(e0, st);
+    on = true;
+  }
+  ~TimeScope() {
+    if (on) hipEventRecord(e1, st);
+  }
+};
+
+__global__ void k_set_io(DevPlan* p, const float* in, float* out) {
+  p->in = in;
+  p->out = out;
+}
+
+constexpr int kIoMax = 64;
+struct IoArgs {
+  const float* in[kIoMax];
+  float* out[kIoMax];
+};
+__global__ void k_set_io_many(DevPlan* recs, int nb, IoArgs a) {
+  const int i = threadIdx.x;
+  if (i < nb) {
+    recs[i].in = a.in[i];
+    recs[i].out = a.out[i];
+  }
+}
+__global__ void k_set_ctr(int32_t* c, int v) { *c = v; }
+__global__ void k_add_ctr(int32_t* c, int v) { *c += v; }
+
+// ------------------------------------------------------------------ runner
+// Launch geometry of one group of same-shape instances (one, for eager).
+struct Runner {
+  int ndim, nx, ny, nz, nt, lossy;
+  const DevPlan* recs;
+  const int2 *row_tab, *col_tab, *red_tab;
+  int row_n, col_n, red_n;
+  double points;  // grid points covered by one launch (all instances)
+
+  int op(int dir, int idx, const PassOp& o, StepArg sa, hipStream_t st, bool timed) const {
+    const double bytes = pass_bytes_per_point(o, ndim, lossy) * points;
+    if (timed) {
+      TimeScope ts(dir, idx, st, bytes);
+      return launch1(o, sa, st);
+    }
+    return launch1(o, sa, st);
+  }
+  int launch1(const PassOp& o, StepArg sa, hipStream_t st) const {
+    hipError_t e;
+    if (o.is_col)
+      e = launch_col(o.col, ndim, nx, ny, nz, Launch{recs, col_tab, col_n, st});
+    else
+      e = launch_row(o.row, ndim, nx, Launch{recs, row_tab, row_n, st}, sa);
+    return e == hipSuccess ? PAT_OK : PAT_EHIP;
+  }
+  int row(RowKind k, StepArg sa, hipStream_t st) const {
+    return launch_row(k, ndim, nx, Launch{recs, row_tab, row_n, st}, sa) == hipSuccess ? PAT_OK : PAT_EHIP;
+  }
+  int reduce(int n0, int n1, hipStream_t st, int blocks) const {
+    return launch_reduce(Launch{recs, red_tab, blocks, st}, n0, n1) == hipSuccess ? PAT_OK : PAT_EHIP;
+  }
+  // steps [s0, s1) of direction dir, eager
+  int steps(int dir, int s0, int s1, hipStream_t st) const {
+    PassOp ops[8];
+    const int nops = step_ops(dir, lossy, ops);
+    int rc = PAT_OK;
+    for (int s = s0; s < s1 && !rc; ++s)
+      for (int i = 0; i < nops && !rc; ++i) rc = op(dir, i, ops[i], StepArg{nullptr, s}, st, true);
+    return rc;
+  }
+};
+
+Runner eager_runner(const pat_plan* p) {
+  Runner r{};
+  r.ndim = p->desc.ndim;
+  r.nx = p->hp.n[0];
+  r.ny = p->hp.n[1];
+  r.nz = p->hp.n[2];
+  r.nt = p->desc.nt;
+  r.lossy = p->lossy;
+  r.recs = p->dp;
+  r.row_tab = r.col_tab = r.red_tab = nullptr;
+  const int R = row_tile_rows(r.nx);
+  r.row_n = (p->hp.nrows + R - 1) / R;
+  r.col_n = col_tiles(r.ndim, r.nx, r.ny, r.nz);
+  r.red_n = 0;
+  r.points = (double)p->npoints;
+  return r;
+}
+
+int set_io(const pat_plan* p, const float* in, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_set_io, dim3(1), dim3(1), 0, st, p->dp, in, out);
+  return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
+}
+
+int reduce_blocks(long nsamples, long ns) { return (int)((nsamples * ns + 255) / 256); }
+
+}  // namespace
+}  // namespace pat
+
+using namespace pat;
+
+// ===================================================================== eager entry points
+extern "C" int pat_forward(pat_plan* p, const float* p0, float* data, void* stream) {
+  if (!p || !p0 || !data) return PAT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const Runner R = eager_runner(p);
+  int rc = set_io(p, p0, data, st);
+  if (!rc) rc = R.row(R_FWD_INIT, StepArg{nullptr, 0}, st);
+  if (!rc) rc = R.steps(0, 0, p->desc.nt - 1, st);
+  if (!rc) rc = R.reduce(0, 0, st, reduce_blocks(p->desc.nt, p->desc.n_sensors));
+  return rc;
+}
+
+extern "C" int pat_adjoint(pat_plan* p, const float* data, float* img, void* stream) {
+  if (!p || !data || !img) return PAT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const Runner R = eager_runner(p);
+  int rc = set_io(p, data, img, st);
+  if (rc) return rc;
+  if (p->desc.nt == 1) return R.row(R_ADJ_SCATTER_ONLY, StepArg{nullptr, 0}, st);
+  rc = R.steps(1, 0, p->desc.nt - 1, st);
+  if (!rc) rc = R.row(R_ADJ_FINAL, StepArg{nullptr, 0}, st);
+  return rc;
+}
+
+extern "C" int pat_forward_range(pat_plan* p, const float* p0, float* data, int32_t n_begin, int32_t n_end,
+                                 void* state_io, void* stream) {
+  if (!p || !data || !state_io) return PAT_EINVAL;
+  const int nt = p->desc.nt;
+  if (n_begin < 0 || n_end <= n_begin || n_end > nt) return PAT_EINVAL;
+  if (n_begin == 0 && !p0) return PAT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const Runner R = eager_runner(p);
+  void* state = (void*)p->hp.u[0];
+  int rc = set_io(p, p0, data, st);
+  if (rc) return rc;
+  int s0;
+  if (n_begin == 0) {
+    rc = R.row(R_FWD_INIT, StepArg{nullptr, 0}, st);
+    s0 = 0;
+  } else {
+    if (hipMemcpyAsync(state, state_io, p->state_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return PAT_EHIP;
+    s0 = n_begin - 1;
+  }
+  // step n records sample n + 1: samples n_begin..n_end-1 need steps s0..n_end-2
+  if (!rc) rc = R.steps(0, s0, n_end - 1, st);
+  if (!rc) rc = R.reduce(n_begin, n_end, st, reduce_blocks(n_end - n_begin, p->desc.n_sensors));
+  if (!rc && hipMemcpyAsync(state_io, state, p->state_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+    rc = PAT_EHIP;
+  return rc;
+}
+
+// ===================================================================== timing diagnostics
+extern "C" int pat_timing_begin(int32_t direction, int32_t pass_index) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (direction < 0 || direction > 1 || pass_index < 0 || pass_index >= 8) return PAT_EINVAL;
+  g_timing.dir = direction;
+  g_timing.index = pass_index;
+  g_timing.used = 0;
+  g_timing.bytes = 0;
+  g_timing.launches = 0;
+  g_timing_on = true;
+  return PAT_OK;
+}
+
+extern "C" int pat_timing_end(double* total_ms, int64_t* launches, double* alg_bytes) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (!total_ms || !launches || !alg_bytes) return PAT_EINVAL;
+  g_timing_on = false;
+  double ms = 0;
+  for (size_t i = 0; i + 1 < g_timing.used; i += 2) {
+    if (hipEventSynchronize(g_timing.ev[i + 1]) != hipSuccess) return PAT_EHIP;
+    float t = 0;
+    if (hipEventElapsedTime(&t, g_timing.ev[i], g_timing.ev[i + 1]) != hipSuccess) return PAT_EHIP;
+    ms += t;
+  }
+  *total_ms = ms;
+  *launches = g_timing.launches;
+  *alg_bytes = g_timing.bytes;
+  g_timing.used = 0;
+  return PAT_OK;
+}
+
+// ===================================================================== batched executor
+namespace {
+
+struct BatchClass {
+  int ndim, nx, ny, nz, nt, lossy, ns_max;
+  std::vector<pat_plan*> plans;
+  std::vector<int> index;  // position of each plan in the caller's list
+  DevPlan* recs = nullptr;
+  int2* row_tab = nullptr;
+  int2* col_tab = nullptr;
+  int2* red_tab = nullptr;
+  int row_n = 0, col_n = 0, red_n = 0;
+  int32_t* ctr = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t done = nullptr;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  Runner runner() const {
+    Runner r{};
+    r.ndim = ndim;
+    r.nx = nx;
+    r.ny = ny;
+    r.nz = nz;
+    r.nt = nt;
+    r.lossy = lossy;
+    r.recs = recs;
+    r.row_tab = row_tab;
+    r.col_tab = col_tab;
+    r.red_tab = red_tab;
+    r.row_n = row_n;
+    r.col_n = col_n;
+    r.red_n = red_n;
+    double pts = 0;
+    for (auto* p : plans) pts += (double)p->npoints;
+    r.points = pts;
+    return r;
+  }
+};
+
+}  // namespace
+
+struct pat_batch {
+  int chunk = 32;
+  std::vector<BatchClass> cls;
+  void* arena = nullptr;
+  hipStream_t cap = nullptr;  // capture-only stream
+  hipEvent_t fork = nullptr;
+  int nb = 0;
+};
+
+namespace {
+
+void destroy_batch(pat_batch* b) {
+  if (!b) return;
+  hipDeviceSynchronize();
+  for (auto& c : b->cls) {
+    for (auto& g : c.graph)
+      if (g) hipGraphExecDestroy(g);
+    if (c.st) hipStreamDestroy(c.st);
+    if (c.done) hipEventDestroy(c.done);
+  }
+  if (b->cap) hipStreamDestroy(b->cap);
+  if (b->fork) hipEventDestroy(b->fork);
+  if (b->arena) hipFree(b->arena);
+  delete b;
+}
+
+// capture `chunk` steps of direction dir (step index = *ctr + k) + counter advance
+int capture(pat_batch* b, BatchClass& c, int dir) {
+  const Runner R = c.runner();
+  PassOp ops[8];
+  const int nops = step_ops(dir, c.lossy, ops);
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return PAT_EHIP;
+  int rc = PAT_OK;
+  for (int k = 0; k < b->chunk && !rc; ++k)
+    for (int i = 0; i < nops && !rc; ++i) rc = R.op(dir, i, ops[i], StepArg{c.ctr, k}, b->cap, false);
+  if (!rc) {
+    hipLaunchKernelGGL(k_add_ctr, dim3(1), dim3(1), 0, b->cap, c.ctr, b->chunk);
+    if (hipGetLastError() != hipSuccess) rc = PAT_EHIP;
+  }
+  if (hipStreamEndCapture(b->cap, &g) != hipSuccess) rc = PAT_EHIP;
+  if (!rc && hipGraphInstantiate(&c.graph[dir], g, nullptr, nullptr, 0) != hipSuccess) rc = PAT_EHIP;
+  if (g) hipGraphDestroy(g);
+  return rc;
+}
+
+// steps [0, nsteps) of direction dir on the class stream: graph chunks, then
+// an eager remainder
+int run_steps(pat_batch* b, BatchClass& c, int dir, int nsteps) {
+  const Runner R = c.runner();
+  const int full = b->chunk > 1 ? nsteps / b->chunk : 0;
+  int rc = PAT_OK;
+  if (full > 0) {
+    if (!c.graph[dir] && (rc = capture(b, c, dir))) return rc;
+    hipLaunchKernelGGL(k_set_ctr, dim3(1), dim3(1), 0, c.st, c.ctr, 0);
+    if (hipGetLastError() != hipSuccess) return PAT_EHIP;
+    for (int i = 0; i < full && !rc; ++i)
+      if (hipGraphLaunch(c.graph[dir], c.st) != hipSuccess) rc = PAT_EHIP;
+  }
+  if (!rc) rc = R.steps(dir, full * b->chunk, nsteps, c.st);
+  return rc;
+}
+
+int set_io_class(BatchClass& c, const float* const* in, float* const* out) {
+  for (size_t i0 = 0; i0 < c.plans.size(); i0 += kIoMax) {
+    IoArgs a{};
+    const int n = (int)std::min<size_t>(kIoMax, c.plans.size() - i0);
+    for (int i = 0; i < n; ++i) {
+      const int k = c.index[i0 + i];
+      if (!in[k] || !out[k]) return PAT_EINVAL;
+      a.in[i] = in[k];
+      a.out[i] = out[k];
+    }
+    hipLaunchKernelGGL(k_set_io_many, dim3(1), dim3(kIoMax), 0, c.st, c.recs + i0, n, a);
+    if (hipGetLastError() != hipSuccess) return PAT_EHIP;
+  }
+  return PAT_OK;
+}
+
+int batch_run(pat_batch* b, int dir, const float* const* in, float* const* out, hipStream_t st) {
+  if (!b || !in || !out) return PAT_EINVAL;
+  if (hipEventRecord(b->fork, st) != hipSuccess) return PAT_EHIP;
+  int rc = PAT_OK;
+  for (auto& c : b->cls) {
+    if (hipStreamWaitEvent(c.st, b->fork, 0) != hipSuccess) return PAT_EHIP;
+    rc = set_io_class(c, in, out);
+    if (rc) return rc;
+    const Runner R = c.runner();
+    if (dir == 0) {
+      rc = R.row(R_FWD_INIT, StepArg{nullptr, 0}, c.st);
+      if (!rc) rc = run_steps(b, c, 0, c.nt - 1);
+      if (!rc) rc = R.reduce(0, 0, c.st, c.red_n);
+    } else if (c.nt == 1) {
+      rc = R.row(R_ADJ_SCATTER_ONLY, StepArg{nullptr, 0}, c.st);
+    } else {
+      rc = run_steps(b, c, 1, c.nt - 1);
+      if (!rc) rc = R.row(R_ADJ_FINAL, StepArg{nullptr, 0}, c.st);
+    }
+    if (rc) return rc;
+    if (hipEventRecord(c.done, c.st) != hipSuccess) return PAT_EHIP;
+  }
+  for (auto& c : b->cls)
+    if (hipStreamWaitEvent(st, c.done, 0) != hipSuccess) return PAT_EHIP;
+  return PAT_OK;
+}
+
+}  // namespace
+
+extern "C" int pat_batch_create(pat_batch** out, pat_plan* const* plans, int32_t nb, int32_t chunk) {
+  if (!out) return PAT_EINVAL;
+  *out = nullptr;
+  if (!plans || nb < 1 || chunk < 0) return PAT_EINVAL;
+  for (int i = 0; i < nb; ++i)
+    if (!plans[i] || plans[i]->desc.ndim != plans[0]->desc.ndim) return PAT_EINVAL;
+  auto* b = new (std::nothrow) pat_batch();
+  if (!b) return PAT_ENOMEM;
+  b->chunk = chunk == 0 ? 32 : chunk;
+  b->nb = nb;
+  // group by (shape, nt, lossy)
+  std::map<std::tuple<int, int, int, int, int>, int> key2cls;
+  for (int i = 0; i < nb; ++i) {
+    const pat_plan* p = plans[i];
+    auto key = std::make_tuple(p->hp.n[0], p->hp.n[1], p->hp.n[2], p->desc.nt, p->lossy);
+    auto it = key2cls.find(key);
+    if (it == key2cls.end()) {
+      BatchClass c{};
+      c.ndim = p->desc.ndim;
+      c.nx = p->hp.n[0];
+      c.ny = p->hp.n[1];
+      c.nz = p->hp.n[2];
+      c.nt = p->desc.nt;
+      c.lossy = p->lossy;
+      c.ns_max = 0;
+      key2cls[key] = (int)b->cls.size();
+      b->cls.push_back(c);
+      it = key2cls.find(key);
+    }
+    BatchClass& c = b->cls[it->second];
+    c.plans.push_back(plans[i]);
+    c.index.push_back(i);
+    c.ns_max = std::max(c.ns_max, p->desc.n_sensors);
+  }
+  // device layout: per class records, tables, counter
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    const size_t at = off;
+    off += bytes;
+    return at;
+  };
+  struct Lay {
+    size_t rec, row, col, red, ctr;
+  };
+  std::vector<Lay> lay;
+  std::vector<std::vector<int2>> rt(b->cls.size()), ct(b->cls.size()), dt(b->cls.size());
+  for (size_t k = 0; k < b->cls.size(); ++k) {
+    BatchClass& c = b->cls[k];
+    const int R = row_tile_rows(c.nx);
+    const int rows_per = (c.ny * c.nz + R - 1) / R;
+    const int cols_per = col_tiles(c.ndim, c.nx, c.ny, c.nz);
+    for (int i = 0; i < (int)c.plans.size(); ++i) {
+      for (int t = 0; t < rows_per; ++t) rt[k].push_back(make_int2(i, t));
+      for (int t = 0; t < cols_per; ++t) ct[k].push_back(make_int2(i, t));
+      const int rb = reduce_blocks(c.nt, c.plans[i]->desc.n_sensors);
+      for (int t = 0; t < rb; ++t) dt[k].push_back(make_int2(i, t));
+    }
+    c.row_n = (int)rt[k].size();
+    c.col_n = (int)ct[k].size();
+    c.red_n = (int)dt[k].size();
+    Lay l;
+    l.rec = take(sizeof(DevPlan) * c.plans.size());
+    l.row = take(sizeof(int2) * rt[k].size());
+    l.col = take(sizeof(int2) * ct[k].size());
+    l.red = take(sizeof(int2) * dt[k].size());
+    l.ctr = take(sizeof(int32_t));
+    lay.push_back(l);
+  }
+  int rc = PAT_OK;
+  if (hipMalloc(&b->arena, off) != hipSuccess) {
+    delete b;
+    return PAT_ENOMEM;
+  }
+  char* A = (char*)b->arena;
+  for (size_t k = 0; k < b->cls.size() && !rc; ++k) {
+    BatchClass& c = b->cls[k];
+    c.recs = (DevPlan*)(A + lay[k].rec);
+    c.row_tab = (int2*)(A + lay[k].row);
+    c.col_tab = (int2*)(A + lay[k].col);
+    c.red_tab = (int2*)(A + lay[k].red);
+    c.ctr = (int32_t*)(A + lay[k].ctr);
+    std::vector<DevPlan> recs;
+    for (auto* p : c.plans) recs.push_back(p->hp);
+    if (hipMemcpy(c.recs, recs.data(), sizeof(DevPlan) * recs.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.row_tab, rt[k].data(), sizeof(int2) * rt[k].size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.col_tab, ct[k].data(), sizeof(int2) * ct[k].size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c.red_tab, dt[k].data(), sizeof(int2) * dt[k].size(), hipMemcpyHostToDevice) != hipSuccess)
+      rc = PAT_EHIP;
+    if (!rc && (hipStreamCreateWithFlags(&c.st, hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&c.done, hipEventDisableTiming) != hipSuccess))
+      rc = PAT_EHIP;
+  }
+  if (!rc && (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+              hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess))
+    rc = PAT_EHIP;
+  if (rc) {
+    destroy_batch(b);
+    return rc;
+  }
+  *out = b;
+  return PAT_OK;
+}
+
+extern "C" void pat_batch_destroy(pat_batch* b) { destroy_batch(b); }
+
+extern "C" int pat_batch_forward(pat_batch* b, const float* const* p0, float* const* data, void* stream) {
+  return batch_run(b, 0, p0, data, (hipStream_t)stream);
+}
+
+extern "C" int pat_batch_adjoint(pat_batch* b, const float* const* data, float* const* img, void* stream) {
+  return batch_run(b, 1, data, img, (hipStream_t)stream);
+}

@@ -547,11 +547,15 @@ __global__ void __launch_bounds__(ColGeo<NY>::NTH) k_col(const DevPlan* __restri
 }
 
 // ------------------------------------------------------------------ gather reduction
-__global__ void __launch_bounds__(256) k_reduce(const DevPlan* __restrict__ plans, const int2* __restrict__ table) {
+// data[n][s] = sum of the sensor's partial row sums, for samples n0 <= n < n1
+// (n1 <= 0 selects nt)
+__global__ void __launch_bounds__(256) k_reduce(const DevPlan* __restrict__ plans, const int2* __restrict__ table,
+                                                int n0, int n1) {
   const int2 job = table ? table[blockIdx.x] : make_int2(0, (int)blockIdx.x);
   const DevPlan& P = plans[job.x];
-  const long idx = (long)job.y * 256 + threadIdx.x;
-  const long total = (long)P.nt * P.ns;
+  const int nend = n1 > 0 ? n1 : P.nt;
+  const long idx = (long)n0 * P.ns + (long)job.y * 256 + threadIdx.x;
+  const long total = (long)nend * P.ns;
   if (idx >= total) return;
   const int n = (int)(idx / P.ns);
   const int s = (int)(idx - (long)n * P.ns);
@@ -670,8 +674,8 @@ hipError_t launch_col(const ColSpec& spec, int ndim, int nx, int ny, int nz, con
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_reduce(const Launch& L, int) {
-  hipLaunchKernelGGL(k_reduce, dim3(L.nblocks), dim3(256), 0, L.stream, L.plans, L.table);
+hipError_t launch_reduce(const Launch& L, int n0, int n1) {
+  hipLaunchKernelGGL(k_reduce, dim3(L.nblocks), dim3(256), 0, L.stream, L.plans, L.table, n0, n1);
   return hipGetLastError();
 }
 

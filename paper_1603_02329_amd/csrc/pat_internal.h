@@ -152,6 +152,35 @@ struct ColSpec {
 hipError_t launch_col(const ColSpec& spec, int ndim, int nx, int ny, int nz, const Launch& L);
 int col_tiles(int ndim, int nx, int ny, int nz);
 
-hipError_t launch_reduce(const Launch& L, int nt_max_ns_blocks);
+hipError_t launch_reduce(const Launch& L, int n0, int n1);
+
+// Forward / adjoint pass sequences shared by the eager and batched executors.
+// Each entry is one launch: a row pass (kind) or a column pass (spec).
+struct PassOp {
+  int32_t is_col;
+  RowKind row;
+  ColSpec col;
+};
+// fills ops[] with the passes of one time step; returns their count
+int step_ops(int direction /*0 fwd, 1 adj*/, int lossy, PassOp* ops);
+
+// algorithmic HBM bytes per grid point of one launch of a pass (float32,
+// 2D): reads + writes of full-grid arrays the pass must touch
+double pass_bytes_per_point(const PassOp& op, int ndim, int lossy);
+
 
 }  // namespace pat
+
+struct pat_plan {
+  pat_desc desc{};
+  int device = 0;
+  double dt = 0, c_ref = 0;
+  int lossy = 0;
+  int64_t npoints = 0;
+  int nslots = 0;
+  pat::DevPlan hp{};            // host image of the device record
+  pat::DevPlan* dp = nullptr;   // device record
+  void* arena = nullptr;        // all device buffers of the plan
+  size_t arena_bytes = 0;
+  size_t state_bytes = 0;
+};

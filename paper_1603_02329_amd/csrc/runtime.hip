@@ -28,19 +28,6 @@ hipError_t upload_twiddles(const Tw* host);
 
 using namespace pat;
 
-struct pat_plan {
-  pat_desc desc{};
-  int device = 0;
-  double dt = 0, c_ref = 0;
-  int lossy = 0;
-  int64_t npoints = 0;
-  int nslots = 0;
-  DevPlan hp{};            // host image of the device record
-  DevPlan* dp = nullptr;   // device record
-  void* arena = nullptr;   // all device buffers of the plan
-  size_t arena_bytes = 0;
-  size_t state_bytes = 0;
-};
 
 namespace {
 
@@ -205,13 +192,6 @@ int build_sensors(const pat_desc& d, const double* pos, SensorOps& so) {
   return PAT_OK;
 }
 
-__global__ void k_set_io(DevPlan* p, const float* in, float* out) {
-  p->in = in;
-  p->out = out;
-}
-
-inline StepArg eager(int k) { return StepArg{nullptr, k}; }
-
 }  // namespace
 
 // ===================================================================== plan
@@ -278,12 +258,15 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
     oBb[j] = cv.take<float2>(tlen[j]);
   }
   const size_t state_begin = (cv.off + 255) & ~size_t(255);
+  // forward state between two steps: u_j, rho_j and the x-spectrum of p (S0),
+  // contiguous so that a snapshot is one copy
+  size_t oS[4] = {0, 0, 0, 0};
   for (int j = 0; j < nd; ++j) oU[j] = cv.take<float>(N);
   for (int j = 0; j < nd; ++j) oR[j] = cv.take<float>(N);
+  oS[0] = cv.take<float2>((size_t)N / 2);
   const size_t state_end = cv.off;
   const size_t o_q = cv.take<float>(N);
-  size_t oS[4] = {0, 0, 0, 0};
-  for (int j = 0; j <= nd; ++j) oS[j] = cv.take<float2>((size_t)N / 2);
+  for (int j = 1; j <= nd; ++j) oS[j] = cv.take<float2>((size_t)N / 2);
   const size_t o_gptr = cv.take<int32_t>(so.g_ptr.size()), o_gtap = cv.take<GTap>(std::max<size_t>(1, so.g_tap.size()));
   const size_t o_sptr = cv.take<int32_t>(so.s_ptr.size()), o_sgrp = cv.take<SGroup>(std::max<size_t>(1, so.s_grp.size()));
   const size_t o_stap = cv.take<STap>(std::max<size_t>(1, so.s_tap.size()));
@@ -434,102 +417,6 @@ extern "C" int pat_plan_info(const pat_plan* p, pat_info* info) {
   return PAT_OK;
 }
 
-// ===================================================================== eager executors
-namespace {
-
-struct Eager {
-  const pat_plan* p;
-  hipStream_t st;
-  Launch L(int nblocks) const { return Launch{p->dp, nullptr, nblocks, st}; }
-  int rows_blocks() const {
-    const int R = row_tile_rows(p->desc.n[0]);
-    return (p->hp.nrows + R - 1) / R;
-  }
-  int row(RowKind k, int step) const {
-    return launch_row(k, p->desc.ndim, p->desc.n[0], L(rows_blocks()), eager(step)) == hipSuccess ? PAT_OK
-                                                                                                 : PAT_EHIP;
-  }
-  int col(int mode, int nf, int m0, int m1, int m2 = 0) const {
-    ColSpec cs{mode, nf, {m0, m1, m2}};
-    const int nb = col_tiles(p->desc.ndim, p->desc.n[0], p->desc.n[1], p->hp.n[2]);
-    return launch_col(cs, p->desc.ndim, p->desc.n[0], p->desc.n[1], p->hp.n[2], L(nb)) == hipSuccess ? PAT_OK
-                                                                                                     : PAT_EHIP;
-  }
-  int reduce() const {
-    const long total = (long)p->desc.nt * p->desc.n_sensors;
-    return launch_reduce(L((int)((total + 255) / 256)), 0) == hipSuccess ? PAT_OK : PAT_EHIP;
-  }
-  int set_io(const float* in, float* out) const {
-    hipLaunchKernelGGL(k_set_io, dim3(1), dim3(1), 0, st, p->dp, in, out);
-    return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
-  }
-};
-
-// forward steps n in [n0, n1): each computes p^{n+1} and records sample n+1
-int forward_steps(const Eager& X, int n0, int n1) {
-  const bool lossy = X.p->lossy;
-  int rc = PAT_OK;
-  for (int n = n0; n < n1 && !rc; ++n) {
-    rc = X.col(0, 2, M_AX, M_AY);
-    if (!rc) rc = X.row(R_FWD_1, n);
-    if (!rc) rc = X.col(1, 2, M_BX, M_BY);
-    if (lossy) {
-      if (!rc) rc = X.row(R_FWD_2, n);
-      if (!rc) rc = X.col(1, 2, M_L1DT, M_L2);
-      if (!rc) rc = X.row(R_FWD_3, n);
-    } else {
-      if (!rc) rc = X.row(R_FWD_2LL, n);
-    }
-  }
-  return rc;
-}
-
-int adjoint_steps(const Eager& X) {
-  const bool lossy = X.p->lossy;
-  const int nt = X.p->desc.nt;
-  int rc = PAT_OK;
-  for (int i = 0; i + 1 < nt && !rc; ++i) {
-    if (lossy) {
-      rc = X.row(R_ADJ_3, i);
-      if (!rc) rc = X.col(1, 2, M_L2, M_L1DT);
-      if (!rc) rc = X.row(R_ADJ_2, i);
-    } else {
-      rc = X.row(R_ADJ_32LL, i);
-    }
-    if (!rc) rc = X.col(1, 2, M_AX, M_AY);
-    if (!rc) rc = X.row(R_ADJ_1, i);
-    if (!rc) rc = X.col(2, 2, M_BX, M_BY);
-  }
-  return rc;
-}
-
-}  // namespace
-
-extern "C" int pat_forward(pat_plan* p, const float* p0, float* data, void* stream) {
-  if (!p || !p0 || !data) return PAT_EINVAL;
-  Eager X{p, (hipStream_t)stream};
-  int rc = X.set_io(p0, data);
-  if (!rc) rc = X.row(R_FWD_INIT, 0);
-  if (!rc) rc = forward_steps(X, 0, p->desc.nt - 1);
-  if (!rc) rc = X.reduce();
-  return rc;
-}
-
-extern "C" int pat_adjoint(pat_plan* p, const float* data, float* img, void* stream) {
-  if (!p || !data || !img) return PAT_EINVAL;
-  Eager X{p, (hipStream_t)stream};
-  int rc = X.set_io(data, img);
-  if (rc) return rc;
-  if (p->desc.nt == 1) return X.row(R_ADJ_SCATTER_ONLY, 0);
-  rc = adjoint_steps(X);
-  if (!rc) rc = X.row(R_ADJ_FINAL, 0);
-  return rc;
-}
-
-extern "C" int pat_forward_range(pat_plan*, const float*, float*, int32_t, int32_t, void*, void*) {
-  return PAT_ENOSYS;
-}
-
 extern "C" int pat_plan_sync(pat_plan* p, void* stream) {
   if (!p) return PAT_EINVAL;
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return PAT_EHIP;
@@ -555,14 +442,3 @@ extern "C" const char* pat_strerror(int code) {
   return "unknown error";
 }
 
-// ===================================================================== batched (filled by the batch executor)
-struct pat_batch {
-  int dummy;
-};
-extern "C" int pat_batch_create(pat_batch** out, pat_plan* const*, int32_t, int32_t) {
-  if (out) *out = nullptr;
-  return PAT_ENOSYS;
-}
-extern "C" void pat_batch_destroy(pat_batch*) {}
-extern "C" int pat_batch_forward(pat_batch*, const float* const*, float* const*, void*) { return PAT_ENOSYS; }
-extern "C" int pat_batch_adjoint(pat_batch*, const float* const*, float* const*, void*) { return PAT_ENOSYS; }

@@ -1,0 +1,64 @@
+"""GPU parity of the TV prox, the transfers and the FP64 reductions."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import prox as OP
+from oracle import transfer as OT
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1603_02329_amd as pat  # noqa: E402
+
+DEV = "cuda"
+
+
+@pytest.mark.parametrize("shape,lam", [((64, 48), 0.05), ((512, 512), 1e-3), ((17, 9), 0.3), ((16, 12, 10), 0.1)])
+def test_tv_prox_parity(shape, lam):
+    rng = np.random.default_rng(1)
+    z = (rng.standard_normal(shape) * 0.1 + 0.3).astype(np.float32)
+    lo = (rng.uniform(-0.2, 0.2, size=shape)).astype(np.float32)
+    for lower in (None, lo):
+        ref = OP.tv_prox(z, lam, 20, lower)
+        got = pat.tv_prox(torch.from_numpy(z).to(DEV), lam, 20,
+                          None if lower is None else torch.from_numpy(lower).to(DEV)).cpu().numpy()
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert err <= 1e-5, err
+
+
+def test_tv_prox_zero_lambda_is_projection():
+    rng = np.random.default_rng(2)
+    z = rng.standard_normal((32, 32)).astype(np.float32)
+    lo = rng.standard_normal((32, 32)).astype(np.float32)
+    got = pat.tv_prox(torch.from_numpy(z).to(DEV), 0.0, 20, torch.from_numpy(lo).to(DEV)).cpu().numpy()
+    assert np.array_equal(got, np.maximum(z, lo))
+
+
+@pytest.mark.parametrize("shape", [(512, 512), (16, 32), (8, 16, 32)])
+def test_transfers(shape):
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal(shape).astype(np.float32)
+    r = pat.restrict(torch.from_numpy(x).to(DEV)).cpu().numpy()
+    ref = OT.restrict(x)
+    assert np.abs(r - ref).max() <= 1e-6 * np.abs(ref).max()
+    c = rng.standard_normal(tuple(s // 2 for s in shape)).astype(np.float32)
+    p = pat.prolong(torch.from_numpy(c).to(DEV)).cpu().numpy()
+    assert np.array_equal(p, OT.prolong(c).astype(np.float32))
+
+
+@pytest.mark.parametrize("n", [1, 1000, 262144, 3_000_001])
+def test_dot_f64(n):
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal(n).astype(np.float32)
+    b = rng.standard_normal(n).astype(np.float32)
+    ta, tb = torch.from_numpy(a).to(DEV), torch.from_numpy(b).to(DEV)
+    got = pat.dot_f64(ta, tb)
+    ref = OT.dot(a, b)
+    scale = math.sqrt(OT.dot(a, a) * OT.dot(b, b))
+    assert abs(got - ref) <= 1e-14 * scale
+    assert pat.dot_f64(ta, tb) == got  # deterministic
+    r, half = pat.residual_f64(ta, tb)
+    assert np.array_equal(r.cpu().numpy(), a - b)
+    assert abs(half - 0.5 * OT.norm2(a - b)) <= 1e-13 * half
