@@ -118,15 +118,32 @@ struct Dft<8, SIGN> {
   }
 };
 
+// Barrier flavours between Stockham stages: the whole block, or only the
+// wavefront (when every thread of a transform lives in the same wavefront,
+// the LDS exchange needs no block-wide barrier, only ordering of this
+// wavefront's LDS accesses).
+struct BlockSync {
+  __device__ __forceinline__ static void sync() { __syncthreads(); }
+};
+struct WaveSync {
+  __device__ __forceinline__ static void sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+};
+
 // One Stockham stage of span L (product of the radices already applied).
-template <int M, int E, int SIGN, int L>
+// `tw` is the twiddle table of this transform length: tw[q] = exp(-2 pi i q / TL)
+// with TL = TWS * M (TWS = 1 for a table of length M, 2 for length 2M).
+template <int M, int E, int SIGN, int L, class Sync, int TWS>
 struct FftStage {
   static constexpr int T = M / E;
   static constexpr int R = (M / L) < E ? (M / L) : E;
   static constexpr int NB = E / R;
   static constexpr bool LAST = (L * R == M);
 
-  __device__ __forceinline__ static void run(float2 (&v)[E], float2* lds, int t, const Tw* __restrict__ tw) {
+  __device__ __forceinline__ static void run(float2 (&v)[E], float2* lds, int t, const Tw* tw) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int k = t + T * b;
@@ -136,7 +153,7 @@ struct FftStage {
       for (int i = 0; i < R; ++i) x[i] = v[b + i * NB];
       if constexpr (L > 1) {
 #pragma unroll
-        for (int i = 1; i < R; ++i) x[i] = twmul<SIGN>(x[i], tw[(i * j) * (TWN / (L * R))]);
+        for (int i = 1; i < R; ++i) x[i] = twmul<SIGN>(x[i], tw[(i * j) * (TWS * M / (L * R))]);
       }
       Dft<R, SIGN>::run(x);
       if constexpr (LAST) {
@@ -149,23 +166,30 @@ struct FftStage {
       }
     }
     if constexpr (!LAST) {
-      __syncthreads();
+      Sync::sync();
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = lds[t + T * m];
-      __syncthreads();
-      FftStage<M, E, SIGN, L * R>::run(v, lds, t, tw);
+      Sync::sync();
+      FftStage<M, E, SIGN, L * R, Sync, TWS>::run(v, lds, t, tw);
     }
   }
 };
 
 // Unnormalised DFT of length M (SIGN = -1 forward, +1 inverse) of the values
 // v[m] = x[t + T m] held by the T threads of one transform; `lds` is that
-// transform's region of M complex values.  Every thread of the block must
-// call it (it synchronises the block).
-template <int M, int E, int SIGN>
-__device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, int t, const Tw* __restrict__ tw) {
+// transform's region of M complex values and `tw` a twiddle table of length
+// TWS*M.  With BlockSync every thread of the block must call it.
+template <int M, int E, int SIGN, class Sync = BlockSync, int TWS = 1>
+__device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, int t, const Tw* tw) {
   static_assert((M & (M - 1)) == 0 && M >= E && M <= TWN, "unsupported FFT length");
-  FftStage<M, E, SIGN, 1>::run(v, lds, t, tw);
+  FftStage<M, E, SIGN, 1, Sync, TWS>::run(v, lds, t, tw);
+}
+
+// Copy the length-TL twiddle table (from the global length-TWN one) into LDS.
+template <int TL, int NTH>
+__device__ __forceinline__ void load_twiddles(Tw* dst, const Tw* __restrict__ g) {
+  static_assert(TWN % TL == 0, "table length must divide TWN");
+  for (int q = threadIdx.x; q < TL; q += NTH) dst[q] = g[q * (TWN / TL)];
 }
 
 }  // namespace pat

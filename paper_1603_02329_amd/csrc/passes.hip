@@ -62,12 +62,12 @@ __device__ __forceinline__ float2 scl2(float s, float2 a) { return make_float2(s
 // n = t + T m.  Unnormalised inverse real DFT.
 template <int N>
 __device__ __forceinline__ void c2r(const float2* __restrict__ src, float2 (&r)[RowGeo<N>::E], float2* L, int t,
-                                    bool valid) {
+                                    bool valid, const Tw* tw) {
   using G = RowGeo<N>;
   constexpr int M = G::M, E = G::E, T = G::T;
 #pragma unroll
   for (int m = 0; m < E; ++m) L[t + T * m] = valid ? src[t + T * m] : f2(0.f, 0.f);
-  __syncthreads();
+  WaveSync::sync();
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = t + T * m;
@@ -77,24 +77,24 @@ __device__ __forceinline__ void c2r(const float2* __restrict__ src, float2 (&r)[
     } else {
       const float2 Y = conjf2(L[M - k]);
       const float2 A = X + Y;
-      const float2 B = twmul<+1>(X - Y, g_tw[k * (TWN / N)]);
+      const float2 B = twmul<+1>(X - Y, tw[k]);
       r[m] = A + mul_si<+1>(B);
     }
   }
-  __syncthreads();
-  fft<M, E, +1>(r, L, t, g_tw);
+  WaveSync::sync();
+  fft<M, E, +1, WaveSync, 2>(r, L, t, tw);
 }
 
 // Real row held as pairs (x[2n], x[2n+1]) -> packed half spectrum stored at dst.
 template <int N>
 __device__ __forceinline__ void r2c(float2 (&r)[RowGeo<N>::E], float2* __restrict__ dst, float2* L, int t,
-                                    bool valid) {
+                                    bool valid, const Tw* tw) {
   using G = RowGeo<N>;
   constexpr int M = G::M, E = G::E, T = G::T;
-  fft<M, E, -1>(r, L, t, g_tw);
+  fft<M, E, -1, WaveSync, 2>(r, L, t, tw);
 #pragma unroll
   for (int m = 0; m < E; ++m) L[t + T * m] = r[m];
-  __syncthreads();
+  WaveSync::sync();
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = t + T * m;
@@ -105,19 +105,19 @@ __device__ __forceinline__ void r2c(float2 (&r)[RowGeo<N>::E], float2* __restric
     } else {
       const float2 Y = conjf2(L[M - k]);
       const float2 A = Z + Y;
-      const float2 B = twmul<-1>(Z - Y, g_tw[k * (TWN / N)]);
+      const float2 B = twmul<-1>(Z - Y, tw[k]);
       X = 0.5f * (A + mul_si<-1>(B));
     }
     if (valid) dst[k] = X;
   }
-  __syncthreads();
+  WaveSync::sync();
 }
 
 // Sensor gather of sample `n` from the real row p held in LDS (as floats).
 template <int N>
 __device__ __forceinline__ void gather_row(const DevPlan& P, int n, const float* Lf, int row, int t, bool valid) {
   using G = RowGeo<N>;
-  __syncthreads();
+  WaveSync::sync();
   if (valid) {
     const int e1 = P.g_ptr[row + 1];
     float* out = P.partial + (long)n * P.nslots;
@@ -126,14 +126,14 @@ __device__ __forceinline__ void gather_row(const DevPlan& P, int n, const float*
       out[tap.slot] = fmaf(tap.w0, Lf[tap.x0], tap.w1 * Lf[tap.x0 + 1]);
     }
   }
-  __syncthreads();
+  WaveSync::sync();
 }
 
 // Add W^T h[n] for this row to the real row held in LDS (as floats).
 template <int N>
 __device__ __forceinline__ void scatter_row(const DevPlan& P, int n, float* Lf, int row, int t, bool valid) {
   using G = RowGeo<N>;
-  __syncthreads();
+  WaveSync::sync();
   if (valid) {
     const int g1 = P.s_ptr[row + 1];
     const float* h = P.in + (long)n * P.ns;
@@ -147,7 +147,7 @@ __device__ __forceinline__ void scatter_row(const DevPlan& P, int n, float* Lf, 
       Lf[grp.x] += acc;
     }
   }
-  __syncthreads();
+  WaveSync::sync();
 }
 
 __device__ __forceinline__ void check_finite(const DevPlan& P, float2 v) {
@@ -161,6 +161,9 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
   using G = RowGeo<N>;
   constexpr int M = G::M, E = G::E, T = G::T;
   __shared__ float2 lds[G::ROWS * M];
+  __shared__ Tw tws[N];
+  load_twiddles<N, G::NTH>(tws, g_tw);
+  __syncthreads();
   const int2 job = table ? table[blockIdx.x] : make_int2(0, (int)blockIdx.x);
   const DevPlan& P = plans[job.x];
   const int rl = threadIdx.x / T, t = threadIdx.x % T;
@@ -199,11 +202,11 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
       L[n] = p[m];
     }
     gather_row<N>(P, 0, Lf, rowc, t, valid);
-    r2c<N>(p, P.S[0] + base, L, t, valid);
+    r2c<N>(p, P.S[0] + base, L, t, valid, tws);
   } else if constexpr (K == R_FWD_1) {
     float2 d[D][E];
 #pragma unroll
-    for (int j = 0; j < D; ++j) c2r<N>(P.S[1 + j] + base, d[j], L, t, valid);
+    for (int j = 0; j < D; ++j) c2r<N>(P.S[1 + j] + base, d[j], L, t, valid, tws);
     const bool first = (it == 0);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -221,11 +224,11 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
       }
     }
 #pragma unroll
-    for (int j = 0; j < D; ++j) r2c<N>(d[j], P.S[1 + j] + base, L, t, valid);
+    for (int j = 0; j < D; ++j) r2c<N>(d[j], P.S[1 + j] + base, L, t, valid, tws);
   } else if constexpr (K == R_FWD_2 || K == R_FWD_2LL) {
     float2 g[D][E];
 #pragma unroll
-    for (int j = 0; j < D; ++j) c2r<N>(P.S[1 + j] + base, g[j], L, t, valid);
+    for (int j = 0; j < D; ++j) c2r<N>(P.S[1 + j] + base, g[j], L, t, valid, tws);
     float2 sdiv[E], srho[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -245,8 +248,8 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
       }
     }
     if constexpr (K == R_FWD_2) {
-      r2c<N>(sdiv, P.S[1] + base, L, t, valid);
-      r2c<N>(srho, P.S[2] + base, L, t, valid);
+      r2c<N>(sdiv, P.S[1] + base, L, t, valid, tws);
+      r2c<N>(srho, P.S[2] + base, L, t, valid, tws);
     } else {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
@@ -257,12 +260,12 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
         L[n] = p;
       }
       gather_row<N>(P, it + 1, Lf, rowc, t, valid);
-      r2c<N>(srho, P.S[0] + base, L, t, valid);
+      r2c<N>(srho, P.S[0] + base, L, t, valid, tws);
     }
   } else if constexpr (K == R_FWD_3) {
     float2 a1[E], a2[E];
-    c2r<N>(P.S[1] + base, a1, L, t, valid);
-    c2r<N>(P.S[2] + base, a2, L, t, valid);
+    c2r<N>(P.S[1] + base, a1, L, t, valid, tws);
+    c2r<N>(P.S[2] + base, a2, L, t, valid, tws);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int n = t + T * m;
@@ -279,7 +282,7 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
       L[n] = p;
     }
     gather_row<N>(P, it + 1, Lf, rowc, t, valid);
-    r2c<N>(a1, P.S[0] + base, L, t, valid);
+    r2c<N>(a1, P.S[0] + base, L, t, valid, tws);
   } else if constexpr (K == R_ADJ_3 || K == R_ADJ_32LL) {
     const bool first = (it == 0);
     const int nsamp = P.nt - 1 - it;  // h[n+1] with n = nt-2-it
@@ -288,14 +291,14 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = f2(0.f, 0.f);
     } else {
-      c2r<N>(P.S[0] + base, v, L, t, valid);
+      c2r<N>(P.S[0] + base, v, L, t, valid, tws);
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) L[t + T * m] = v[m];
     scatter_row<N>(P, nsamp, Lf, rowc, t, valid);
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = L[t + T * m];
-    __syncthreads();
+    WaveSync::sync();
     if constexpr (K == R_ADJ_3) {
       float2 e[E], ta[E];
 #pragma unroll
@@ -308,8 +311,8 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
         e[m] = mul2(ld2(P.c2eta, base + n), v[m]);
         ta[m] = mul2(ld2(P.c2tau, base + n), v[m]);
       }
-      r2c<N>(e, P.S[1] + base, L, t, valid);
-      r2c<N>(ta, P.S[2] + base, L, t, valid);
+      r2c<N>(e, P.S[1] + base, L, t, valid, tws);
+      r2c<N>(ta, P.S[2] + base, L, t, valid, tws);
     } else {
       float2 g[D][E];
 #pragma unroll
@@ -329,13 +332,13 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
         }
       }
 #pragma unroll
-      for (int j = 0; j < D; ++j) r2c<N>(g[j], P.S[1 + j] + base, L, t, valid);
+      for (int j = 0; j < D; ++j) r2c<N>(g[j], P.S[1 + j] + base, L, t, valid, tws);
     }
   } else if constexpr (K == R_ADJ_2) {
     const bool first = (it == 0);
     float2 a2[E], a1[E];
-    c2r<N>(P.S[1] + base, a2, L, t, valid);
-    c2r<N>(P.S[2] + base, a1, L, t, valid);
+    c2r<N>(P.S[1] + base, a2, L, t, valid, tws);
+    c2r<N>(P.S[2] + base, a1, L, t, valid, tws);
     float2 g[D][E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -354,13 +357,13 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
       }
     }
 #pragma unroll
-    for (int j = 0; j < D; ++j) r2c<N>(g[j], P.S[1 + j] + base, L, t, valid);
+    for (int j = 0; j < D; ++j) r2c<N>(g[j], P.S[1 + j] + base, L, t, valid, tws);
   } else if constexpr (K == R_ADJ_1) {
     const bool first = (it == 0);
     const bool last = (it == P.nt - 2);
     float2 d[D][E];
 #pragma unroll
-    for (int j = 0; j < D; ++j) c2r<N>(P.S[1 + j] + base, d[j], L, t, valid);
+    for (int j = 0; j < D; ++j) c2r<N>(P.S[1 + j] + base, d[j], L, t, valid, tws);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
 #pragma unroll
@@ -383,11 +386,11 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
       }
     }
 #pragma unroll
-    for (int j = 0; j < D; ++j) r2c<N>(d[j], P.S[1 + j] + base, L, t, valid);
+    for (int j = 0; j < D; ++j) r2c<N>(d[j], P.S[1 + j] + base, L, t, valid, tws);
   } else if constexpr (K == R_ADJ_FINAL || K == R_ADJ_SCATTER_ONLY) {
     float2 v[E];
     if constexpr (K == R_ADJ_FINAL) {
-      c2r<N>(P.S[0] + base, v, L, t, valid);
+      c2r<N>(P.S[0] + base, v, L, t, valid, tws);
     } else {
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = f2(0.f, 0.f);
@@ -413,72 +416,83 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
 }
 
 // ------------------------------------------------------------------ column passes
-// k-space multiplier `kind` at x-bin kxi (0..nx/2) and y-bin ky, including the
-// normalisation 1/(nx ny).
-__device__ __forceinline__ float2 mult_at(const DevPlan& P, int kind, int kxi, int ky) {
-  const float k2 = P.ksq[0][kxi] + P.ksq[1][ky];
-  float2 m;
-  if (kind <= M_BZ) {
-    const float th = P.kap * sqrtf(k2);
-    const float kap = (th < 1e-4f) ? 1.f - th * th * (1.f / 6.f) : sinf(th) / th;
-    const float2 sh = (kind == M_AX) ? P.shA[0][kxi]
-                      : (kind == M_AY) ? P.shA[1][ky]
-                      : (kind == M_BX) ? P.shB[0][kxi]
-                                       : P.shB[1][ky];
-    m = scl2(kap * P.scale, sh);
-  } else {
-    float v = 0.f;
-    if (k2 > 0.f) v = (kind == M_L1DT) ? powf(k2, P.ym2h) * P.inv_dt : powf(k2, P.ym1h);
-    m = f2(v * P.scale, 0.f);
-  }
-  return m;
+// sinc(sqrt(s)) = sum_n (-s)^n / (2n+1)!, nine terms: exact to float32
+// rounding for s <= (pi/2)^2, i.e. for every time step the stability bound
+// admits (c_ref dt |k|_max / 2 <= pi/2).
+__device__ __forceinline__ float sinc_sqrt(float s) {
+  float p = 2.8114572543455208e-15f;        // 1/17!
+  p = fmaf(p, s, -7.6471637318198164e-13f);  // -1/15!
+  p = fmaf(p, s, 1.6059043836821613e-10f);   // 1/13!
+  p = fmaf(p, s, -2.5052108385441720e-08f);  // -1/11!
+  p = fmaf(p, s, 2.7557319223985893e-06f);   // 1/9!
+  p = fmaf(p, s, -1.9841269841269841e-04f);  // -1/7!
+  p = fmaf(p, s, 8.3333333333333333e-03f);   // 1/5!
+  p = fmaf(p, s, -1.6666666666666667e-01f);  // -1/3!
+  return fmaf(p, s, 1.0f);
 }
 
-// y-transform tile of up to TILE packed columns starting at c0.
-template <int NY>
-struct ColTile {
-  using G = ColGeo<NY>;
-  static constexpr int E = G::E, TC = G::TC, LD = G::LD;
+// |k|^(2e) from |k|^2 (e = (y-2)/2 or (y-1)/2): the absorption terms are
+// small corrections, so the hardware log2/exp2 suffice.
+__device__ __forceinline__ float kpow(float k2, float e) {
+  return k2 > 0.f ? __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(k2)) : 0.f;
+}
 
-  __device__ static void load(float2* lds, const float2* __restrict__ src, int M, int c0, int width) {
-    for (int idx = threadIdx.x; idx < NY * width; idx += G::NTH) {
-      const int y = idx / width, cc = idx - y * width;
-      lds[cc * LD + y] = src[(long)y * M + c0 + cc];
-    }
-  }
-  __device__ static void store(const float2* lds, float2* __restrict__ dst, int M, int c0, int width) {
-    for (int idx = threadIdx.x; idx < NY * width; idx += G::NTH) {
-      const int y = idx / width, cc = idx - y * width;
-      dst[(long)y * M + c0 + cc] = lds[cc * LD + y];
-    }
-  }
+// the x-bin part of the multipliers, constant per column
+struct XBin {
+  float k2;
+  float2 sa, sb;
 };
+__device__ __forceinline__ XBin xbin(const DevPlan& P, int kxi) {
+  return XBin{P.ksq[0][kxi], P.shA[0][kxi], P.shB[0][kxi]};
+}
 
+// k-space multiplier `kind` at (x-bin, y-bin ky), normalised by 1/(nx ny)
+__device__ __forceinline__ float2 mult_at(const DevPlan& P, int kind, const XBin& xb, int ky) {
+  const float k2 = xb.k2 + P.ksq[1][ky];
+  if (kind <= M_BZ) {
+    const float kap = sinc_sqrt(P.kap2 * k2) * P.scale;
+    const float2 sh = (kind == M_AX) ? xb.sa : (kind == M_AY) ? P.shA[1][ky] : (kind == M_BX) ? xb.sb : P.shB[1][ky];
+    return scl2(kap, sh);
+  }
+  const float v = (kind == M_L1DT) ? kpow(k2, P.ym2h) * P.inv_dt : kpow(k2, P.ym1h);
+  return f2(v * P.scale, 0.f);
+}
+
+// Column pass over a tile of TILE consecutive packed x-bins, all NY y-rows.
+// Thread (t, c) with the column c fastest: a wavefront's global loads and
+// stores at one y-row cover TILE consecutive complex values (coalesced), and
+// the values arrive directly in the FFT's register order (y = t + TC m).
 template <int NY, int MODE, int NF>
 __global__ void __launch_bounds__(ColGeo<NY>::NTH) k_col(const DevPlan* __restrict__ plans,
                                                          const int2* __restrict__ table, ColSpec spec) {
   using G = ColGeo<NY>;
-  using CT = ColTile<NY>;
-  constexpr int E = G::E, TC = G::TC, LD = G::LD;
-  __shared__ float2 lds[G::TILE * LD];
+  constexpr int E = G::E, TC = G::TC, LD = G::LD, TILE = G::TILE;
+  __shared__ float2 lds[TILE * LD];
+  __shared__ Tw tws[NY];
+  load_twiddles<NY, G::NTH>(tws, g_tw);
   const int2 job = table ? table[blockIdx.x] : make_int2(0, (int)blockIdx.x);
   const DevPlan& P = plans[job.x];
   const int M = P.n[0] / 2;
-  const int width = M < G::TILE ? M : G::TILE;
-  const int c0 = job.y * G::TILE;
-  const int c = threadIdx.x / TC, t = threadIdx.x % TC;
+  const int width = M < TILE ? M : TILE;
+  const int c0 = job.y * TILE;
+  const int c = threadIdx.x % TILE, t = threadIdx.x / TILE;
   float2* Lc = lds + c * LD;
-  const int kxi = c0 + c;
-  const bool special = (c0 == 0);  // tile holds packed column 0 = (kx = 0, kx = nx/2)
   const bool cvalid = c < width;
+  const int kxi = c0 + (cvalid ? c : 0);
+  const bool special = (c0 == 0);  // tile holds packed column 0 = (kx = 0, kx = nx/2)
+  const bool col0 = special && c == 0;
+  const XBin xb = xbin(P, kxi);
+  const XBin xbN = xbin(P, M);
+  __syncthreads();
 
-  auto forward = [&](const float2* src, float2 (&v)[E]) {
-    CT::load(lds, src, M, c0, width);
-    __syncthreads();
+  auto load = [&](const float2* __restrict__ src, float2 (&v)[E]) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = Lc[t + TC * m];
-    __syncthreads();
-    fft<NY, E, -1>(v, Lc, t, g_tw);
+    for (int m = 0; m < E; ++m) v[m] = cvalid ? src[(long)(t + TC * m) * M + kxi] : f2(0.f, 0.f);
+  };
+  auto store = [&](float2* __restrict__ dst, const float2 (&v)[E]) {
+    if (!cvalid) return;
+#pragma unroll
+    for (int m = 0; m < E; ++m) dst[(long)(t + TC * m) * M + kxi] = v[m];
   };
   // conj(C[-ky]) of packed column 0 (block-uniform call when `special`)
   auto partner = [&](const float2 (&v)[E], float2 (&vm)[E]) {
@@ -489,60 +503,58 @@ __global__ void __launch_bounds__(ColGeo<NY>::NTH) k_col(const DevPlan* __restri
     for (int m = 0; m < E; ++m) vm[m] = conjf2(Lc[(NY - (t + TC * m)) & (NY - 1)]);
     __syncthreads();
   };
-  // accumulate mult * spectrum into acc (column-0 aware)
+  // acc += mult * spectrum (column 0 carries the kx = 0 and kx = nx/2 lines)
   auto apply = [&](int kind, const float2 (&v)[E], const float2 (&vm)[E], float2 (&acc)[E]) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int ky = t + TC * m;
-      if (special && c == 0) {
-        const float2 m0 = mult_at(P, kind, 0, ky);
-        const float2 mM = mult_at(P, kind, M, ky);
+      if (col0) {
+        const float2 m0 = mult_at(P, kind, xb, ky);
+        const float2 mM = mult_at(P, kind, xbN, ky);
         acc[m] = acc[m] + cmul(0.5f * (m0 + mM), v[m]) + cmul(0.5f * (m0 - mM), vm[m]);
       } else {
-        acc[m] = acc[m] + cmul(mult_at(P, kind, cvalid ? kxi : 0, ky), v[m]);
+        acc[m] = acc[m] + cmul(mult_at(P, kind, xb, ky), v[m]);
       }
     }
-  };
-  auto inverse_store = [&](float2 (&acc)[E], float2* dst) {
-    fft<NY, E, +1>(acc, Lc, t, g_tw);
-#pragma unroll
-    for (int m = 0; m < E; ++m) Lc[t + TC * m] = acc[m];
-    __syncthreads();
-    CT::store(lds, dst, M, c0, width);
-    __syncthreads();
   };
 
   float2 v[E], vm[E], acc[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) vm[m] = f2(0.f, 0.f);
   if constexpr (MODE == 0) {
-    forward(P.S[0], v);
+    load(P.S[0], v);
+    fft<NY, E, -1>(v, Lc, t, tws);
     if (special) partner(v, vm);
 #pragma unroll
     for (int o = 0; o < NF; ++o) {
 #pragma unroll
       for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
       apply(spec.mult[o], v, vm, acc);
-      inverse_store(acc, P.S[1 + o]);
+      fft<NY, E, +1>(acc, Lc, t, tws);
+      store(P.S[1 + o], acc);
     }
   } else if constexpr (MODE == 1) {
     const int f = 1 + (int)blockIdx.y;
-    forward(P.S[f], v);
+    load(P.S[f], v);
+    fft<NY, E, -1>(v, Lc, t, tws);
     if (special) partner(v, vm);
 #pragma unroll
     for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
     apply(spec.mult[f - 1], v, vm, acc);
-    inverse_store(acc, P.S[f]);
+    fft<NY, E, +1>(acc, Lc, t, tws);
+    store(P.S[f], acc);
   } else {
 #pragma unroll
     for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
 #pragma unroll
     for (int f = 1; f <= NF; ++f) {
-      forward(P.S[f], v);
+      load(P.S[f], v);
+      fft<NY, E, -1>(v, Lc, t, tws);
       if (special) partner(v, vm);
       apply(spec.mult[f - 1], v, vm, acc);
     }
-    inverse_store(acc, P.S[0]);
+    fft<NY, E, +1>(acc, Lc, t, tws);
+    store(P.S[0], acc);
   }
 }
 

@@ -54,7 +54,7 @@ struct DevPlan {
   int32_t lossy;
   uint32_t flags;
   float dt;
-  float kap;         // c_ref * dt / 2: kappa = sinc(kap * |k|)
+  float kap2;        // (c_ref * dt / 2)^2: kappa = sinc(sqrt(kap2 * |k|^2))
   float ym2h, ym1h;  // (y - 2)/2 and (y - 1)/2: |k|^(y-2) = (|k|^2)^ym2h
   float inv_dt;
   float scale;       // 1 / (nx ny nz): normalisation of a forward+inverse pair

@@ -356,7 +356,7 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
   h.lossy = lossy;
   h.flags = d.flags;
   h.dt = (float)dt;
-  h.kap = (float)(cmax * dt / 2.0);
+  h.kap2 = (float)((cmax * dt / 2.0) * (cmax * dt / 2.0));
   h.ym2h = (float)((y - 2.0) / 2.0);
   h.ym1h = (float)((y - 1.0) / 2.0);
   h.inv_dt = (float)(1.0 / dt);
