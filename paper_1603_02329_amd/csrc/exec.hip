@@ -16,32 +16,49 @@
 namespace pat {
 
 // ------------------------------------------------------------------ pass sequences
-int step_ops(int dir, int lossy, PassOp* ops) {
+int step_ops(int dir, int ndim, int lossy, PassOp* ops) {
   int n = 0;
-  auto row = [&](RowKind k) { ops[n++] = PassOp{0, k, ColSpec{0, 0, {0, 0, 0}}}; };
-  auto col = [&](int mode, int nf, int a, int b) { ops[n++] = PassOp{1, R_COUNT, ColSpec{mode, nf, {a, b, 0}}}; };
+  auto row = [&](RowKind k) { ops[n++] = PassOp{0, k, ColSpec{0, 0, {0, 0, 0}, 0}}; };
+  auto col = [&](int mode, int nf, int f0, int a, int b, int c) {
+    ops[n++] = PassOp{1, R_COUNT, ColSpec{mode, nf, {a, b, c}, f0}};
+  };
+  // spectral operator on fields [f0, f0+nf) along the remaining axes: 2D one
+  // column pass; 3D a y-transform pass, the z pass with the multipliers and
+  // the inverse y-transform of the outputs
+  auto spec = [&](int mode, int nf, int f0, int a, int b, int c) {
+    if (ndim == 2) {
+      col(mode, nf, f0, a, b, c);
+      return;
+    }
+    const int in0 = (mode == 0) ? 0 : f0, nin = (mode == 0) ? 1 : nf;
+    const int out0 = (mode == 2) ? 0 : (mode == 0 ? 1 : f0), nout = (mode == 2) ? 1 : nf;
+    col(3, nin, in0, 0, 0, 0);
+    col(mode, nf, f0, a, b, c);
+    col(4, nout, out0, 0, 0, 0);
+  };
+  const int d = ndim;
   if (dir == 0) {
-    col(0, 2, M_AX, M_AY);  // gradient of p at the staggered points
-    row(R_FWD_1);           // velocity update
-    col(1, 2, M_BX, M_BY);  // divergence components back on the nodes
+    spec(0, d, 1, M_AX, M_AY, M_AZ);    // gradient of p at the staggered points
+    row(R_FWD_1);                        // velocity update
+    spec(1, d, 1, M_BX, M_BY, M_BZ);    // divergence components back on the nodes
     if (lossy) {
-      row(R_FWD_2);             // density update
-      col(1, 2, M_L1DT, M_L2);  // fractional Laplacians
-      row(R_FWD_3);             // equation of state + sensors
+      row(R_FWD_2);                      // density update
+      spec(1, 2, 1, M_L1DT, M_L2, 0);    // fractional Laplacians
+      row(R_FWD_3);                      // equation of state + sensors
     } else {
-      row(R_FWD_2LL);  // density update + equation of state + sensors
+      row(R_FWD_2LL);                    // density update + equation of state + sensors
     }
   } else {
     if (lossy) {
       row(R_ADJ_3);
-      col(1, 2, M_L2, M_L1DT);
+      spec(1, 2, 1, M_L2, M_L1DT, 0);
       row(R_ADJ_2);
     } else {
       row(R_ADJ_32LL);
     }
-    col(1, 2, M_AX, M_AY);
+    spec(1, d, 1, M_AX, M_AY, M_AZ);
     row(R_ADJ_1);
-    col(2, 2, M_BX, M_BY);
+    spec(2, d, 1, M_BX, M_BY, M_BZ);
   }
   return n;
 }
@@ -53,8 +70,8 @@ double pass_bytes_per_point(const PassOp& op, int ndim, int lossy) {
     const int f = op.col.nfield;
     // packed spectra: 4 bytes per grid point and field
     if (op.col.mode == 0) return 4.0 * (1 + f);
-    if (op.col.mode == 1) return 8.0 * f;
-    return 4.0 * (f + 1);
+    if (op.col.mode == 2) return 4.0 * (f + 1);
+    return 8.0 * f;  // modes 1, 3, 4: each field read and written
   }
   switch (op.row) {
     case R_FWD_INIT: return 4.0 * (d + 3);       // p0, 1/(d c0^2) -> rho_j, S0
@@ -165,8 +182,8 @@ struct Runner {
   }
   // steps [s0, s1) of direction dir, eager
   int steps(int dir, int s0, int s1, hipStream_t st) const {
-    PassOp ops[8];
-    const int nops = step_ops(dir, lossy, ops);
+    PassOp ops[kMaxOps];
+    const int nops = step_ops(dir, ndim, lossy, ops);
     int rc = PAT_OK;
     for (int s = s0; s < s1 && !rc; ++s)
       for (int i = 0; i < nops && !rc; ++i) rc = op(dir, i, ops[i], StepArg{nullptr, s}, st, true);
@@ -258,7 +275,7 @@ extern "C" int pat_forward_range(pat_plan* p, const float* p0, float* data, int3
 // ===================================================================== timing diagnostics
 extern "C" int pat_timing_begin(int32_t direction, int32_t pass_index) {
   std::lock_guard<std::mutex> lk(g_tmu);
-  if (direction < 0 || direction > 1 || pass_index < 0 || pass_index >= 8) return PAT_EINVAL;
+  if (direction < 0 || direction > 1 || pass_index < 0 || pass_index >= kMaxOps) return PAT_EINVAL;
   g_timing.dir = direction;
   g_timing.index = pass_index;
   g_timing.used = 0;
@@ -355,8 +372,8 @@ void destroy_batch(pat_batch* b) {
 // capture `chunk` steps of direction dir (step index = *ctr + k) + counter advance
 int capture(pat_batch* b, BatchClass& c, int dir) {
   const Runner R = c.runner();
-  PassOp ops[8];
-  const int nops = step_ops(dir, c.lossy, ops);
+  PassOp ops[kMaxOps];
+  const int nops = step_ops(dir, c.ndim, c.lossy, ops);
   hipGraph_t g = nullptr;
   if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return PAT_EHIP;
   int rc = PAT_OK;

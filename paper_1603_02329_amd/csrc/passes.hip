@@ -25,6 +25,8 @@
 // and the adjoint runs the transposed passes in reverse order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fft.h"
 #include "pat_internal.h"
 
@@ -446,74 +448,109 @@ __device__ __forceinline__ XBin xbin(const DevPlan& P, int kxi) {
   return XBin{P.ksq[0][kxi], P.shA[0][kxi], P.shB[0][kxi]};
 }
 
-// k-space multiplier `kind` at (x-bin, y-bin ky), normalised by 1/(nx ny)
-__device__ __forceinline__ float2 mult_at(const DevPlan& P, int kind, const XBin& xb, int ky) {
-  const float k2 = xb.k2 + P.ksq[1][ky];
+// k-space multiplier `kind` at (x-bin, y-bin ky, z-bin kz; kz < 0 in 2D),
+// normalised by 1/(nx ny nz)
+__device__ __forceinline__ float2 mult_at(const DevPlan& P, int kind, const XBin& xb, int ky, int kz) {
+  const float k2 = xb.k2 + P.ksq[1][ky] + (kz >= 0 ? P.ksq[2][kz] : 0.f);
   if (kind <= M_BZ) {
     const float kap = sinc_sqrt(P.kap2 * k2) * P.scale;
-    const float2 sh = (kind == M_AX) ? xb.sa : (kind == M_AY) ? P.shA[1][ky] : (kind == M_BX) ? xb.sb : P.shB[1][ky];
+    float2 sh;
+    switch (kind) {
+      case M_AX: sh = xb.sa; break;
+      case M_AY: sh = P.shA[1][ky]; break;
+      case M_AZ: sh = P.shA[2][kz]; break;
+      case M_BX: sh = xb.sb; break;
+      case M_BY: sh = P.shB[1][ky]; break;
+      default: sh = P.shB[2][kz]; break;
+    }
     return scl2(kap, sh);
   }
   const float v = (kind == M_L1DT) ? kpow(k2, P.ym2h) * P.inv_dt : kpow(k2, P.ym1h);
   return f2(v * P.scale, 0.f);
 }
 
-// Column pass over a tile of TILE consecutive packed x-bins, all NY y-rows.
-// Thread (t, c) with the column c fastest: a wavefront's global loads and
-// stores at one y-row cover TILE consecutive complex values (coalesced), and
-// the values arrive directly in the FFT's register order (y = t + TC m).
-template <int NY, int MODE, int NF>
-__global__ void __launch_bounds__(ColGeo<NY>::NTH) k_col(const DevPlan* __restrict__ plans,
+// Column pass over a tile of TILE consecutive packed x-bins and all NA points
+// of one axis.
+//
+// Packed column 0 holds the x-bins 0 and nx/2 as C = A + iB, A and B being
+// transforms of real lines.  In 2D the pass separates them with the mirror
+// bin C(-ky) of the same column.  In 3D the y-transform pass (mode 3), which
+// holds whole y-columns, stores column 0 unpacked -- A(ky) at 0 < ky < ny/2
+// and B(ky) at ny - ky -- and the inverse y pass (mode 4) packs it again, so
+// the z pass of a y-bin never needs another y-bin's column (y-bins 0 and
+// ny/2 stay packed and are separated along z within their own column).  Modes 0-2 transform along the last axis (y in 2D, z in 3D),
+// apply k-space multipliers and transform back; modes 3/4 are the forward /
+// inverse transform along y alone (3D).  Thread (t, c) with the column c
+// fastest: a wavefront's loads and stores at one axis position cover TILE
+// consecutive complex values (coalesced) and arrive directly in the FFT's
+// register order (a = t + TC m).
+template <int NA, int MODE, int NF>
+__global__ void __launch_bounds__(ColGeo<NA>::NTH) k_col(const DevPlan* __restrict__ plans,
                                                          const int2* __restrict__ table, ColSpec spec) {
-  using G = ColGeo<NY>;
+  using G = ColGeo<NA>;
   constexpr int E = G::E, TC = G::TC, LD = G::LD, TILE = G::TILE;
   __shared__ float2 lds[TILE * LD];
-  __shared__ Tw tws[NY];
-  load_twiddles<NY, G::NTH>(tws, g_tw);
+  __shared__ Tw tws[NA];
+  load_twiddles<NA, G::NTH>(tws, g_tw);
   const int2 job = table ? table[blockIdx.x] : make_int2(0, (int)blockIdx.x);
   const DevPlan& P = plans[job.x];
-  const int M = P.n[0] / 2;
+  const int M = P.n[0] / 2, ny = P.n[1], nz = P.n[2];
+  const bool along_y = (MODE >= 3) || (P.ndim == 2);
+  const long stride = along_y ? (long)M : (long)ny * M;
+  const int other_n = along_y ? nz : ny;
+  const int tiles = (M + TILE - 1) / TILE;
+  const int o = job.y / tiles, kt = job.y - o * tiles;
+  if (o >= other_n) return;  // block-uniform
+  const long obase = along_y ? (long)o * ny * M : (long)o * M;
   const int width = M < TILE ? M : TILE;
-  const int c0 = job.y * TILE;
+  const int c0 = kt * TILE;
   const int c = threadIdx.x % TILE, t = threadIdx.x / TILE;
   float2* Lc = lds + c * LD;
   const bool cvalid = c < width;
   const int kxi = c0 + (cvalid ? c : 0);
-  const bool special = (c0 == 0);  // tile holds packed column 0 = (kx = 0, kx = nx/2)
-  const bool col0 = special && c == 0;
+  const bool tile0 = (c0 == 0);                // tile holds packed column 0 = (kx = 0, kx = nx/2)
+  const bool selfpair = along_y || o == 0 || 2 * o == ny;  // column 0 still packed here
+  const bool special = tile0 && MODE < 3 && selfpair;     // separation needs the mirror bin
+  const bool col0 = tile0 && c == 0;
+  const int ky_fixed = along_y ? -1 : o;       // y-bin of a z-column (3D)
   const XBin xb = xbin(P, kxi);
   const XBin xbN = xbin(P, M);
   __syncthreads();
 
-  auto load = [&](const float2* __restrict__ src, float2 (&v)[E]) {
+  auto load = [&](const float2* __restrict__ src, long base, bool on, float2 (&v)[E]) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = cvalid ? src[(long)(t + TC * m) * M + kxi] : f2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) v[m] = on ? src[base + (long)(t + TC * m) * stride + kxi] : f2(0.f, 0.f);
   };
   auto store = [&](float2* __restrict__ dst, const float2 (&v)[E]) {
     if (!cvalid) return;
 #pragma unroll
-    for (int m = 0; m < E; ++m) dst[(long)(t + TC * m) * M + kxi] = v[m];
+    for (int m = 0; m < E; ++m) dst[obase + (long)(t + TC * m) * stride + kxi] = v[m];
   };
-  // conj(C[-ky]) of packed column 0 (block-uniform call when `special`)
-  auto partner = [&](const float2 (&v)[E], float2 (&vm)[E]) {
+  // mirror bin conj(C[-a]) along this column's axis (block-uniform call)
+  auto mirror = [&](const float2 (&v)[E], float2 (&vm)[E]) {
 #pragma unroll
     for (int m = 0; m < E; ++m) Lc[t + TC * m] = v[m];
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < E; ++m) vm[m] = conjf2(Lc[(NY - (t + TC * m)) & (NY - 1)]);
+    for (int m = 0; m < E; ++m) vm[m] = conjf2(Lc[(NA - (t + TC * m)) & (NA - 1)]);
     __syncthreads();
   };
+  auto partner = [&](const float2* __restrict__, const float2 (&v)[E], float2 (&vm)[E]) { mirror(v, vm); };
   // acc += mult * spectrum (column 0 carries the kx = 0 and kx = nx/2 lines)
   auto apply = [&](int kind, const float2 (&v)[E], const float2 (&vm)[E], float2 (&acc)[E]) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int ky = t + TC * m;
-      if (col0) {
-        const float2 m0 = mult_at(P, kind, xb, ky);
-        const float2 mM = mult_at(P, kind, xbN, ky);
+      const int a = t + TC * m;
+      const int ky = along_y ? a : ky_fixed;
+      const int kz = along_y ? -1 : a;
+      if (col0 && selfpair) {
+        const float2 m0 = mult_at(P, kind, xb, ky, kz);
+        const float2 mM = mult_at(P, kind, xbN, ky, kz);
         acc[m] = acc[m] + cmul(0.5f * (m0 + mM), v[m]) + cmul(0.5f * (m0 - mM), vm[m]);
+      } else if (col0 && 2 * o > ny) {  // 3D unpacked: B of y-bin ny - o, x-bin nx/2
+        acc[m] = acc[m] + cmul(mult_at(P, kind, xbN, ny - o, kz), v[m]);
       } else {
-        acc[m] = acc[m] + cmul(mult_at(P, kind, xb, ky), v[m]);
+        acc[m] = acc[m] + cmul(mult_at(P, kind, xb, ky, kz), v[m]);
       }
     }
   };
@@ -522,39 +559,84 @@ __global__ void __launch_bounds__(ColGeo<NY>::NTH) k_col(const DevPlan* __restri
 #pragma unroll
   for (int m = 0; m < E; ++m) vm[m] = f2(0.f, 0.f);
   if constexpr (MODE == 0) {
-    load(P.S[0], v);
-    fft<NY, E, -1>(v, Lc, t, tws);
-    if (special) partner(v, vm);
+    load(P.S[0], obase, cvalid, v);
+    fft<NA, E, -1>(v, Lc, t, tws);
+    if (special) partner(P.S[0], v, vm);
 #pragma unroll
-    for (int o = 0; o < NF; ++o) {
+    for (int oo = 0; oo < NF; ++oo) {
 #pragma unroll
       for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
-      apply(spec.mult[o], v, vm, acc);
-      fft<NY, E, +1>(acc, Lc, t, tws);
-      store(P.S[1 + o], acc);
+      apply(spec.mult[oo], v, vm, acc);
+      fft<NA, E, +1>(acc, Lc, t, tws);
+      store(P.S[1 + oo], acc);
     }
   } else if constexpr (MODE == 1) {
-    const int f = 1 + (int)blockIdx.y;
-    load(P.S[f], v);
-    fft<NY, E, -1>(v, Lc, t, tws);
-    if (special) partner(v, vm);
+    const int f = spec.f0 + (int)blockIdx.y;
+    load(P.S[f], obase, cvalid, v);
+    fft<NA, E, -1>(v, Lc, t, tws);
+    if (special) partner(P.S[f], v, vm);
 #pragma unroll
     for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
-    apply(spec.mult[f - 1], v, vm, acc);
-    fft<NY, E, +1>(acc, Lc, t, tws);
+    apply(spec.mult[blockIdx.y], v, vm, acc);
+    fft<NA, E, +1>(acc, Lc, t, tws);
     store(P.S[f], acc);
-  } else {
+  } else if constexpr (MODE == 2) {
 #pragma unroll
     for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
 #pragma unroll
-    for (int f = 1; f <= NF; ++f) {
-      load(P.S[f], v);
-      fft<NY, E, -1>(v, Lc, t, tws);
-      if (special) partner(v, vm);
-      apply(spec.mult[f - 1], v, vm, acc);
+    for (int i = 0; i < NF; ++i) {
+      const int f = spec.f0 + i;
+      load(P.S[f], obase, cvalid, v);
+      fft<NA, E, -1>(v, Lc, t, tws);
+      if (special) partner(P.S[f], v, vm);
+      apply(spec.mult[i], v, vm, acc);
     }
-    fft<NY, E, +1>(acc, Lc, t, tws);
+    fft<NA, E, +1>(acc, Lc, t, tws);
     store(P.S[0], acc);
+  } else if constexpr (MODE == 3) {
+    const int f = spec.f0 + (int)blockIdx.y;
+    load(P.S[f], obase, cvalid, v);
+    fft<NA, E, -1>(v, Lc, t, tws);
+    if (tile0) {  // unpack column 0: A(a) at 0 < a < ny/2, B(ny - a) at ny/2 < a < ny
+      mirror(v, vm);
+      if (c == 0) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const int a = t + TC * m;
+          if (a == 0 || 2 * a == NA) continue;
+          if (2 * a < NA)
+            v[m] = 0.5f * (v[m] + vm[m]);
+          else  // (conj(Q) - conj(P)) (-i/2), P = C(a), Q = conj(C(-a))
+            v[m] = 0.5f * mul_si<-1>(conjf2(vm[m]) - conjf2(v[m]));
+        }
+      }
+    }
+    store(P.S[f], v);
+  } else {
+    const int f = spec.f0 + (int)blockIdx.y;
+    load(P.S[f], obase, cvalid, v);
+    if (tile0) {  // pack column 0 again: C(a) = A(a) + i B(a), C(-a) = conj(A(a)) + i conj(B(a))
+      float2 u[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) Lc[t + TC * m] = v[m];
+      __syncthreads();
+#pragma unroll
+      for (int m = 0; m < E; ++m) u[m] = Lc[(NA - (t + TC * m)) & (NA - 1)];  // U(ny - a)
+      __syncthreads();
+      if (c == 0) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          const int a = t + TC * m;
+          if (a == 0 || 2 * a == NA) continue;
+          if (2 * a < NA)
+            v[m] = v[m] + mul_si<+1>(u[m]);
+          else
+            v[m] = conjf2(u[m]) + mul_si<+1>(conjf2(v[m]));
+        }
+      }
+    }
+    fft<NA, E, +1>(v, Lc, t, tws);
+    store(P.S[f], v);
   }
 }
 
@@ -626,55 +708,76 @@ hipError_t launch_row(RowKind kind, int ndim, int nx, const Launch& L, StepArg s
       case 512: return launch_row_nd<512, 2>(kind, L, s);
       case 1024: return launch_row_nd<1024, 2>(kind, L, s);
     }
+  } else if (ndim == 3) {
+    switch (nx) {
+      case 16: return launch_row_nd<16, 3>(kind, L, s);
+      case 32: return launch_row_nd<32, 3>(kind, L, s);
+      case 64: return launch_row_nd<64, 3>(kind, L, s);
+      case 128: return launch_row_nd<128, 3>(kind, L, s);
+      case 256: return launch_row_nd<256, 3>(kind, L, s);
+    }
   }
   return hipErrorInvalidValue;
 }
 
-int col_tiles(int ndim, int nx, int ny, int nz) {
-  const int M = nx / 2;
-  int tile = 0;
-  switch (ny) {
-    case 16: tile = ColGeo<16>::TILE; break;
-    case 32: tile = ColGeo<32>::TILE; break;
-    case 64: tile = ColGeo<64>::TILE; break;
-    case 128: tile = ColGeo<128>::TILE; break;
-    case 256: tile = ColGeo<256>::TILE; break;
-    case 512: tile = ColGeo<512>::TILE; break;
-    case 1024: tile = ColGeo<1024>::TILE; break;
-    default: return 0;
+static int col_tile_width(int na) {
+  switch (na) {
+    case 16: return ColGeo<16>::TILE;
+    case 32: return ColGeo<32>::TILE;
+    case 64: return ColGeo<64>::TILE;
+    case 128: return ColGeo<128>::TILE;
+    case 256: return ColGeo<256>::TILE;
+    case 512: return ColGeo<512>::TILE;
+    case 1024: return ColGeo<1024>::TILE;
   }
-  (void)ndim;
-  (void)nz;
-  return (M + tile - 1) / tile;
+  return 0;
 }
 
-template <int NY>
-static hipError_t launch_col_n(const ColSpec& spec, const Launch& L) {
-  const dim3 block(ColGeo<NY>::NTH);
-  if (spec.mode == 0) {
-    const dim3 grid(L.nblocks);
-    if (spec.nfield == 2)
-      hipLaunchKernelGGL((k_col<NY, 0, 2>), grid, block, 0, L.stream, L.plans, L.table, spec);
-    else
-      return hipErrorInvalidValue;
-  } else if (spec.mode == 1) {
-    const dim3 grid(L.nblocks, spec.nfield);
-    hipLaunchKernelGGL((k_col<NY, 1, 1>), grid, block, 0, L.stream, L.plans, L.table, spec);
-  } else {
-    const dim3 grid(L.nblocks);
-    if (spec.nfield == 2)
-      hipLaunchKernelGGL((k_col<NY, 2, 2>), grid, block, 0, L.stream, L.plans, L.table, spec);
-    else
-      return hipErrorInvalidValue;
+// blocks of one column-pass launch of one instance (the maximum over the
+// passes of the step: y-axis passes use nz groups, z-axis passes ny groups)
+int col_tiles(int ndim, int nx, int ny, int nz) {
+  const int M = nx / 2;
+  int best = 0;
+  for (int pass = 0; pass < (ndim == 3 ? 2 : 1); ++pass) {
+    const int na = (ndim == 2 || pass == 0) ? ny : nz;
+    const int other = (ndim == 2) ? 1 : (pass == 0 ? nz : ny);
+    const int tile = col_tile_width(na);
+    if (!tile) return 0;
+    best = std::max(best, other * ((M + tile - 1) / tile));
   }
+  return best;
+}
+
+template <int NA>
+static hipError_t launch_col_n(const ColSpec& spec, const Launch& L) {
+  const dim3 block(ColGeo<NA>::NTH);
+  const dim3 grid1(L.nblocks), gridf(L.nblocks, spec.nfield);
+#define PAT_COL(MODE, NF, GRID) \
+  hipLaunchKernelGGL((k_col<NA, MODE, NF>), GRID, block, 0, L.stream, L.plans, L.table, spec)
+  switch (spec.mode) {
+    case 0:
+      if (spec.nfield == 2) PAT_COL(0, 2, grid1);
+      else if (spec.nfield == 3) PAT_COL(0, 3, grid1);
+      else return hipErrorInvalidValue;
+      break;
+    case 1: PAT_COL(1, 1, gridf); break;
+    case 2:
+      if (spec.nfield == 2) PAT_COL(2, 2, grid1);
+      else if (spec.nfield == 3) PAT_COL(2, 3, grid1);
+      else return hipErrorInvalidValue;
+      break;
+    case 3: PAT_COL(3, 1, gridf); break;
+    case 4: PAT_COL(4, 1, gridf); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef PAT_COL
   return hipGetLastError();
 }
 
 hipError_t launch_col(const ColSpec& spec, int ndim, int nx, int ny, int nz, const Launch& L) {
   (void)nx;
-  (void)nz;
-  if (ndim != 2) return hipErrorInvalidValue;
-  switch (ny) {
+  const int na = (ndim == 2 || spec.mode >= 3) ? ny : nz;
+  switch (na) {
     case 16: return launch_col_n<16>(spec, L);
     case 32: return launch_col_n<32>(spec, L);
     case 64: return launch_col_n<64>(spec, L);

@@ -140,14 +140,18 @@ hipError_t launch_row(RowKind kind, int ndim, int nx, const Launch& L, StepArg s
 // rows per work item of the row passes for row length nx
 int row_tile_rows(int nx);
 
-// column passes along y (2D) -- and along y/z in 3D.
-// mode 0: out S[o] = mult[o] * in S[0]         (o = 1..nout)
-// mode 1: out S[f] = mult[f] * in S[f]         (blockIdx.y = field index f-1)
-// mode 2: out S[0] = sum_f mult[f] * in S[f]   (f = 1..nin)
+// Column passes.  Modes 0-2 run along the last axis (y in 2D, z in 3D):
+// transform, k-space multiplier(s), inverse transform.  Modes 3-4 are the
+// forward / inverse transform along y alone (3D).
+// mode 0: S[1+i] = mult[i] S[0]                    (i < nfield)
+// mode 1: S[f]   = mult[i] S[f],  f = f0 + i       (blockIdx.y = i)
+// mode 2: S[0]   = sum_i mult[i] S[f0 + i]
+// mode 3/4: S[f0 + i] <- F_y / F_y^-1 S[f0 + i]    (blockIdx.y = i)
 struct ColSpec {
   int32_t mode;
   int32_t nfield;
   int32_t mult[3];
+  int32_t f0;
 };
 hipError_t launch_col(const ColSpec& spec, int ndim, int nx, int ny, int nz, const Launch& L);
 int col_tiles(int ndim, int nx, int ny, int nz);
@@ -162,7 +166,8 @@ struct PassOp {
   ColSpec col;
 };
 // fills ops[] with the passes of one time step; returns their count
-int step_ops(int direction /*0 fwd, 1 adj*/, int lossy, PassOp* ops);
+constexpr int kMaxOps = 16;
+int step_ops(int direction /*0 fwd, 1 adj*/, int ndim, int lossy, PassOp* ops);
 
 // algorithmic HBM bytes per grid point of one launch of a pass (float32,
 // 2D): reads + writes of full-grid arrays the pass must touch

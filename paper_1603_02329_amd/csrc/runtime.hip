@@ -204,7 +204,6 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
   if (rc) return rc;
   if (!c0_d || !rho0_d || !sensor_pos) return PAT_EINVAL;
   const pat_desc d = *desc;
-  if (d.ndim == 3) return PAT_ENOSYS;
   hipStream_t st = (hipStream_t)stream;
   const int nd = d.ndim;
   const int nx = d.n[0], ny = d.n[1], nz = nd == 3 ? d.n[2] : 1;

@@ -1,0 +1,90 @@
+"""Write the full-size oracle results the GPU parity tests compare against.
+
+Every value stored here is computed by the FP64 oracle (``oracle/``) from the
+seeded synthetic inputs (``synth/``) and rounded to float32 once; nothing
+comes from the GPU library.  For each case the file holds:
+
+  data       oracle forward H p0 on the sensors listed in ``sensor_idx``
+             (a fixed subsample of the sensors, all time samples), (nt, k)
+  sensor_idx the sensor indices kept
+  h_seed     seed of the standard-normal float32 data h fed to the adjoint
+  img        oracle adjoint H^T h on the voxels listed in ``img_idx``
+             (flat indices; all voxels for 2D cases, a subsample in 3D)
+  img_idx    flat voxel indices kept
+
+Usage:  python tests/golden/make_golden.py [case ...]   (default: all)
+Cases: cfg2, cfg3f, cfg3c, cfg4_<i> (i = 0, 1, 16, 17, 32, 33), cfg5.
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import synth  # noqa: E402
+from oracle import kspace as K  # noqa: E402
+
+CFG4_IDS = (0, 1, 16, 17, 32, 33)
+
+
+def instance(case: str):
+    if case == "cfg2":
+        return synth.config2()
+    if case == "cfg3f":
+        return synth.config3()[0]
+    if case == "cfg3c":
+        return synth.config3()[1]
+    if case.startswith("cfg4_"):
+        return synth.config4()[int(case.split("_")[1])]
+    if case == "cfg5":
+        return synth.config5()
+    raise KeyError(case)
+
+
+def subsample(case: str, inst):
+    ns = inst.ns
+    if case == "cfg5":
+        sens = np.arange(0, ns, 16)
+        n = int(np.prod(inst.desc.shape))
+        grid = np.arange(n).reshape(inst.desc.shape)[::4, ::4, ::4]
+        return sens, grid.ravel()
+    return np.arange(0, ns, 4), np.arange(int(np.prod(inst.desc.shape)))
+
+
+def h_for(case: str, inst):
+    seed = 97 + sum(ord(ch) for ch in case)
+    h = np.random.default_rng(seed).standard_normal((inst.desc.nt, inst.ns)).astype(np.float32)
+    return seed, h
+
+
+def make(case: str, workers: int) -> None:
+    K.WORKERS = workers
+    inst = instance(case)
+    t0 = time.time()
+    op = K.make_plan(inst.desc, inst.c0, inst.rho0, inst.alpha0_db, inst.sensors)
+    data = K.forward(op, inst.p0)
+    seed, h = h_for(case, inst)
+    img = K.adjoint(op, h)
+    sidx, iidx = subsample(case, inst)
+    out = os.path.join(HERE, f"{case}.npz")
+    np.savez_compressed(out, data=data[:, sidx].astype(np.float32), sensor_idx=sidx.astype(np.int32),
+                        h_seed=np.int64(seed), img=img.ravel()[iidx].astype(np.float32),
+                        img_idx=iidx.astype(np.int64), nt=np.int64(inst.desc.nt))
+    print(f"{case}: {time.time() - t0:.1f} s -> {out} ({os.path.getsize(out) / 1e6:.2f} MB)", flush=True)
+
+
+def main():
+    cases = sys.argv[1:] or (["cfg2", "cfg3c", "cfg3f"] + [f"cfg4_{i}" for i in CFG4_IDS] + ["cfg5"])
+    workers = int(os.environ.get("ORACLE_WORKERS", os.cpu_count() or 1))
+    for c in cases:
+        make(c, workers)
+
+
+if __name__ == "__main__":
+    main()

@@ -71,3 +71,36 @@ def test_config2_short_parity():
     print("cfg2/150", rel(d, rd), rel(img, ri), flush=True)
     assert rel(d, rd) <= 1e-5
     assert rel(img, ri) <= 1e-5
+
+
+CASES3 = [
+    dict(n=(16, 16, 16), nt=8, ns=5, pml=2, lossy=True, hetero=True),
+    dict(n=(32, 16, 64), nt=10, ns=7, pml=3, lossy=True, hetero=True),
+    dict(n=(16, 32, 16), nt=9, ns=4, pml=2, lossy=False, hetero=True),
+    dict(n=(32, 32, 32), nt=12, ns=6, pml=0, lossy=True, hetero=True, pml_on=False),
+    dict(n=(64, 64, 64), nt=10, ns=9, pml=6, lossy=True, hetero=True),
+    dict(n=(64, 128, 32), nt=8, ns=5, pml=4, lossy=False, hetero=True),
+]
+
+
+@pytest.mark.parametrize("case", CASES3, ids=[f"{c['n']}-nt{c['nt']}" for c in CASES3])
+def test_small_parity_3d(case):
+    inst = synth.small_instance(200 + CASES3.index(case), **case)
+    print("case3", case, flush=True)
+    _, d, img, rd, ri, _ = run_pair(inst)
+    print("rel", rel(d, rd), rel(img, ri), flush=True)
+    assert rel(d, rd) <= 1e-5
+    assert rel(img, ri) <= 1e-5
+
+
+def test_config5_short_parity():
+    """128^3 lossy medium and phantom, planar 128x128 sensor moved to z = 64
+    (inside the source region, so that 12 samples already carry signal)."""
+    inst = synth.config5()
+    d = inst.desc
+    sens = synth.plane_sensors(128, 128, d.dx, d.origin, 64)
+    inst = synth.Instance(replace(d, nt=12), inst.c0, inst.rho0, inst.alpha0_db, sens, inst.p0)
+    _, d, img, rd, ri, _ = run_pair(inst)
+    print("cfg5/12", rel(d, rd), rel(img, ri), flush=True)
+    assert rel(d, rd) <= 1e-5
+    assert rel(img, ri) <= 1e-5
