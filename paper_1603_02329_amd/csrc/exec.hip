@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <new>
@@ -461,11 +462,18 @@ extern "C" int pat_batch_create(pat_batch** out, pat_plan* const* plans, int32_t
   if (!b) return PAT_ENOMEM;
   b->chunk = chunk == 0 ? 32 : chunk;
   b->nb = nb;
-  // group by (shape, nt, lossy)
-  std::map<std::tuple<int, int, int, int, int>, int> key2cls;
+  // group by (shape, nt, lossy); a group holds at most `gmax` instances so
+  // that large classes run as several concurrent streams whose passes of
+  // different kinds (memory-heavy rows, arithmetic-heavy columns) overlap
+  int gmax = 64;
+  if (const char* env = std::getenv("PAT_BATCH_GROUP")) gmax = std::max(1, std::atoi(env));
+  std::map<std::tuple<int, int, int, int, int>, int> count;
+  std::map<std::tuple<int, int, int, int, int, int>, int> key2cls;
   for (int i = 0; i < nb; ++i) {
     const pat_plan* p = plans[i];
-    auto key = std::make_tuple(p->hp.n[0], p->hp.n[1], p->hp.n[2], p->desc.nt, p->lossy);
+    const auto shape_key = std::make_tuple(p->hp.n[0], p->hp.n[1], p->hp.n[2], p->desc.nt, p->lossy);
+    const int grp = count[shape_key]++ / gmax;
+    auto key = std::make_tuple(p->hp.n[0], p->hp.n[1], p->hp.n[2], p->desc.nt, p->lossy, grp);
     auto it = key2cls.find(key);
     if (it == key2cls.end()) {
       BatchClass c{};

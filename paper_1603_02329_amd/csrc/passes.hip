@@ -448,25 +448,19 @@ __device__ __forceinline__ XBin xbin(const DevPlan& P, int kxi) {
   return XBin{P.ksq[0][kxi], P.shA[0][kxi], P.shB[0][kxi]};
 }
 
-// k-space multiplier `kind` at (x-bin, y-bin ky, z-bin kz; kz < 0 in 2D),
-// normalised by 1/(nx ny nz)
-__device__ __forceinline__ float2 mult_at(const DevPlan& P, int kind, const XBin& xb, int ky, int kz) {
-  const float k2 = xb.k2 + P.ksq[1][ky] + (kz >= 0 ? P.ksq[2][kz] : 0.f);
-  if (kind <= M_BZ) {
-    const float kap = sinc_sqrt(P.kap2 * k2) * P.scale;
-    float2 sh;
-    switch (kind) {
-      case M_AX: sh = xb.sa; break;
-      case M_AY: sh = P.shA[1][ky]; break;
-      case M_AZ: sh = P.shA[2][kz]; break;
-      case M_BX: sh = xb.sb; break;
-      case M_BY: sh = P.shB[1][ky]; break;
-      default: sh = P.shB[2][kz]; break;
-    }
-    return scl2(kap, sh);
-  }
-  const float v = (kind == M_L1DT) ? kpow(k2, P.ym2h) * P.inv_dt : kpow(k2, P.ym1h);
-  return f2(v * P.scale, 0.f);
+// Multiplier families of the column passes (compile-time): staggered
+// derivatives a_j = i k_j kappa e^{+i k_j dx_j/2}, b_j (e^{-...}), or the
+// fractional Laplacians |k|^(y-2)/dt, |k|^(y-1).
+enum ColFam : int { F_A = 0, F_B = 1, F_ABS = 2 };
+
+// Per-point multiplier factors, normalised by 1/(nx ny nz):
+//   derivative family: kap = kappa/N and the axis shift of `axis`
+//   absorption family: the two real Laplacian factors
+template <int FAM>
+__device__ __forceinline__ float2 axis_shift(const DevPlan& P, const XBin& xb, int axis, int ky, int kz) {
+  if (axis == 0) return FAM == F_A ? xb.sa : xb.sb;
+  if (axis == 1) return FAM == F_A ? P.shA[1][ky] : P.shB[1][ky];
+  return FAM == F_A ? P.shA[2][kz] : P.shB[2][kz];
 }
 
 // Column pass over a tile of TILE consecutive packed x-bins and all NA points
@@ -478,13 +472,15 @@ __device__ __forceinline__ float2 mult_at(const DevPlan& P, int kind, const XBin
 // holds whole y-columns, stores column 0 unpacked -- A(ky) at 0 < ky < ny/2
 // and B(ky) at ny - ky -- and the inverse y pass (mode 4) packs it again, so
 // the z pass of a y-bin never needs another y-bin's column (y-bins 0 and
-// ny/2 stay packed and are separated along z within their own column).  Modes 0-2 transform along the last axis (y in 2D, z in 3D),
-// apply k-space multipliers and transform back; modes 3/4 are the forward /
-// inverse transform along y alone (3D).  Thread (t, c) with the column c
-// fastest: a wavefront's loads and stores at one axis position cover TILE
-// consecutive complex values (coalesced) and arrive directly in the FFT's
-// register order (a = t + TC m).
-template <int NA, int MODE, int NF>
+// ny/2 stay packed and are separated along z within their own column).
+//
+// Modes 0-2 transform along the last axis (y in 2D, z in 3D), apply k-space
+// multipliers and transform back; modes 3/4 are the forward / inverse
+// transform along y alone (3D).  Thread (t, c) with the column c fastest: a
+// wavefront's loads and stores at one axis position cover TILE consecutive
+// complex values (coalesced) and arrive directly in the FFT's register order
+// (a = t + TC m).
+template <int NA, int MODE, int NF, int FAM>
 __global__ void __launch_bounds__(ColGeo<NA>::NTH) k_col(const DevPlan* __restrict__ plans,
                                                          const int2* __restrict__ table, ColSpec spec) {
   using G = ColGeo<NA>;
@@ -496,35 +492,32 @@ __global__ void __launch_bounds__(ColGeo<NA>::NTH) k_col(const DevPlan* __restri
   const DevPlan& P = plans[job.x];
   const int M = P.n[0] / 2, ny = P.n[1], nz = P.n[2];
   const bool along_y = (MODE >= 3) || (P.ndim == 2);
-  const long stride = along_y ? (long)M : (long)ny * M;
+  const int stride = along_y ? M : ny * M;
   const int other_n = along_y ? nz : ny;
   const int tiles = (M + TILE - 1) / TILE;
   const int o = job.y / tiles, kt = job.y - o * tiles;
   if (o >= other_n) return;  // block-uniform
-  const long obase = along_y ? (long)o * ny * M : (long)o * M;
+  const int obase = along_y ? o * ny * M : o * M;
   const int width = M < TILE ? M : TILE;
   const int c0 = kt * TILE;
   const int c = threadIdx.x % TILE, t = threadIdx.x / TILE;
   float2* Lc = lds + c * LD;
   const bool cvalid = c < width;
   const int kxi = c0 + (cvalid ? c : 0);
-  const bool tile0 = (c0 == 0);                // tile holds packed column 0 = (kx = 0, kx = nx/2)
+  const bool tile0 = (c0 == 0);                            // tile holds packed column 0
   const bool selfpair = along_y || o == 0 || 2 * o == ny;  // column 0 still packed here
-  const bool special = tile0 && MODE < 3 && selfpair;     // separation needs the mirror bin
+  const bool special = tile0 && MODE < 3 && selfpair;      // separation needs the mirror bin
   const bool col0 = tile0 && c == 0;
-  const int ky_fixed = along_y ? -1 : o;       // y-bin of a z-column (3D)
-  const XBin xb = xbin(P, kxi);
-  const XBin xbN = xbin(P, M);
   __syncthreads();
 
-  auto load = [&](const float2* __restrict__ src, long base, bool on, float2 (&v)[E]) {
+  auto load = [&](const float2* __restrict__ src, float2 (&v)[E]) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = on ? src[base + (long)(t + TC * m) * stride + kxi] : f2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) v[m] = cvalid ? src[obase + (t + TC * m) * stride + kxi] : f2(0.f, 0.f);
   };
   auto store = [&](float2* __restrict__ dst, const float2 (&v)[E]) {
     if (!cvalid) return;
 #pragma unroll
-    for (int m = 0; m < E; ++m) dst[obase + (long)(t + TC * m) * stride + kxi] = v[m];
+    for (int m = 0; m < E; ++m) dst[obase + (t + TC * m) * stride + kxi] = v[m];
   };
   // mirror bin conj(C[-a]) along this column's axis (block-uniform call)
   auto mirror = [&](const float2 (&v)[E], float2 (&vm)[E]) {
@@ -535,108 +528,146 @@ __global__ void __launch_bounds__(ColGeo<NA>::NTH) k_col(const DevPlan* __restri
     for (int m = 0; m < E; ++m) vm[m] = conjf2(Lc[(NA - (t + TC * m)) & (NA - 1)]);
     __syncthreads();
   };
-  auto partner = [&](const float2* __restrict__, const float2 (&v)[E], float2 (&vm)[E]) { mirror(v, vm); };
-  // acc += mult * spectrum (column 0 carries the kx = 0 and kx = nx/2 lines)
-  auto apply = [&](int kind, const float2 (&v)[E], const float2 (&vm)[E], float2 (&acc)[E]) {
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int a = t + TC * m;
-      const int ky = along_y ? a : ky_fixed;
-      const int kz = along_y ? -1 : a;
-      if (col0 && selfpair) {
-        const float2 m0 = mult_at(P, kind, xb, ky, kz);
-        const float2 mM = mult_at(P, kind, xbN, ky, kz);
-        acc[m] = acc[m] + cmul(0.5f * (m0 + mM), v[m]) + cmul(0.5f * (m0 - mM), vm[m]);
-      } else if (col0 && 2 * o > ny) {  // 3D unpacked: B of y-bin ny - o, x-bin nx/2
-        acc[m] = acc[m] + cmul(mult_at(P, kind, xbN, ny - o, kz), v[m]);
-      } else {
-        acc[m] = acc[m] + cmul(mult_at(P, kind, xb, ky, kz), v[m]);
-      }
-    }
-  };
 
-  float2 v[E], vm[E], acc[E];
+  if constexpr (MODE >= 3) {
+    const int f = spec.f0 + (int)blockIdx.y;
+    float2 v[E], vm[E];
+    load(P.S[f], v);
+    if constexpr (MODE == 3) {
+      fft<NA, E, -1>(v, Lc, t, tws);
+      if (tile0) {  // unpack column 0: A(a) at 0 < a < ny/2, B(ny - a) at ny/2 < a < ny
+        mirror(v, vm);
+        if (c == 0) {
 #pragma unroll
-  for (int m = 0; m < E; ++m) vm[m] = f2(0.f, 0.f);
-  if constexpr (MODE == 0) {
-    load(P.S[0], obase, cvalid, v);
-    fft<NA, E, -1>(v, Lc, t, tws);
-    if (special) partner(P.S[0], v, vm);
+          for (int m = 0; m < E; ++m) {
+            const int a = t + TC * m;
+            if (a == 0 || 2 * a == NA) continue;
+            if (2 * a < NA)
+              v[m] = 0.5f * (v[m] + vm[m]);
+            else  // (conj(Q) - conj(P)) (-i/2), P = C(a), Q = conj(C(-a))
+              v[m] = 0.5f * mul_si<-1>(conjf2(vm[m]) - conjf2(v[m]));
+          }
+        }
+      }
+    } else {
+      if (tile0) {  // pack column 0 again: C(a) = A(a) + i B(a), C(-a) = conj(A(a)) + i conj(B(a))
 #pragma unroll
-    for (int oo = 0; oo < NF; ++oo) {
+        for (int m = 0; m < E; ++m) Lc[t + TC * m] = v[m];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < E; ++m) vm[m] = Lc[(NA - (t + TC * m)) & (NA - 1)];  // U(ny - a)
+        __syncthreads();
+        if (c == 0) {
+#pragma unroll
+          for (int m = 0; m < E; ++m) {
+            const int a = t + TC * m;
+            if (a == 0 || 2 * a == NA) continue;
+            if (2 * a < NA)
+              v[m] = v[m] + mul_si<+1>(vm[m]);
+            else
+              v[m] = conjf2(vm[m]) + mul_si<+1>(conjf2(v[m]));
+          }
+        }
+      }
+      fft<NA, E, +1>(v, Lc, t, tws);
+    }
+    store(P.S[f], v);
+    return;
+  } else {
+    // ---- multiplier geometry, shared by every field and output of the block
+    // y/z bin of element m: along y (2D) ky = a; along z (3D) ky = o, kz = a.
+    // Column 0 outside the self-paired y-bins holds B of y-bin ny - o at
+    // x-bin nx/2 (3D unpacked layout).
+    const bool unpackedB = col0 && !selfpair && 2 * o > ny;
+    const int kyf = along_y ? 0 : (unpackedB ? ny - o : o);
+    const XBin xb = xbin(P, unpackedB ? M : kxi);
+    const XBin xbN = xbin(P, M);
+    const float k2fix = xb.k2 + (along_y ? 0.f : P.ksq[1][kyf]);
+    const float k2fixN = xbN.k2 + (along_y ? 0.f : P.ksq[1][kyf]);
+    const int ax_last = along_y ? 1 : 2;
+    float k2v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) k2v[m] = P.ksq[ax_last][t + TC * m];
+    // per-element factor g (kappa/N, or the Laplacian factor) at the column's
+    // x-bin and, for the packed column, at x-bin nx/2
+    auto factor = [&](float k2, int which) -> float {
+      if constexpr (FAM == F_ABS) {
+        return (which == M_L1DT ? kpow(k2, P.ym2h) * P.inv_dt : kpow(k2, P.ym1h)) * P.scale;
+      } else {
+        return sinc_sqrt(P.kap2 * k2) * P.scale;
+      }
+    };
+    auto shift = [&](const XBin& x, int axis, int m) -> float2 {
+      const int a = t + TC * m;
+      return along_y ? axis_shift<FAM == F_ABS ? F_A : FAM>(P, x, axis, a, -1)
+                     : axis_shift<FAM == F_ABS ? F_A : FAM>(P, x, axis, kyf, a);
+    };
+    // acc += mult(kind/axis) * spectrum for one field
+    auto apply = [&](int which, const float2 (&v)[E], const float2 (&vm)[E], float2 (&acc)[E]) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        float2 mv, mN;
+        const float g = factor(k2fix + k2v[m], which);
+        if constexpr (FAM == F_ABS) {
+          mv = f2(g, 0.f);
+        } else {
+          mv = scl2(g, shift(xb, which, m));
+        }
+        if (col0 && selfpair) {
+          const float gN = factor(k2fixN + k2v[m], which);
+          if constexpr (FAM == F_ABS) {
+            mN = f2(gN, 0.f);
+          } else {
+            mN = scl2(gN, shift(xbN, which, m));
+          }
+          acc[m] = acc[m] + cmul(0.5f * (mv + mN), v[m]) + cmul(0.5f * (mv - mN), vm[m]);
+        } else {
+          acc[m] = acc[m] + cmul(mv, v[m]);
+        }
+      }
+    };
+    // which: derivative axis (0, 1, 2) for F_A / F_B, else the Mult kind
+    auto which_of = [&](int i) { return FAM == F_ABS ? spec.mult[i] : i; };
+
+    float2 v[E], vm[E], acc[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) vm[m] = f2(0.f, 0.f);
+    if constexpr (MODE == 0) {
+      load(P.S[0], v);
+      fft<NA, E, -1>(v, Lc, t, tws);
+      if (special) mirror(v, vm);
+#pragma unroll
+      for (int i = 0; i < NF; ++i) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
+        apply(which_of(i), v, vm, acc);
+        fft<NA, E, +1>(acc, Lc, t, tws);
+        store(P.S[1 + i], acc);
+      }
+    } else if constexpr (MODE == 1) {
+      const int i = (int)blockIdx.y;
+      const int f = spec.f0 + i;
+      load(P.S[f], v);
+      fft<NA, E, -1>(v, Lc, t, tws);
+      if (special) mirror(v, vm);
 #pragma unroll
       for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
-      apply(spec.mult[oo], v, vm, acc);
+      apply(which_of(i), v, vm, acc);
       fft<NA, E, +1>(acc, Lc, t, tws);
-      store(P.S[1 + oo], acc);
-    }
-  } else if constexpr (MODE == 1) {
-    const int f = spec.f0 + (int)blockIdx.y;
-    load(P.S[f], obase, cvalid, v);
-    fft<NA, E, -1>(v, Lc, t, tws);
-    if (special) partner(P.S[f], v, vm);
+      store(P.S[f], acc);
+    } else {
 #pragma unroll
-    for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
-    apply(spec.mult[blockIdx.y], v, vm, acc);
-    fft<NA, E, +1>(acc, Lc, t, tws);
-    store(P.S[f], acc);
-  } else if constexpr (MODE == 2) {
+      for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
 #pragma unroll
-    for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
-#pragma unroll
-    for (int i = 0; i < NF; ++i) {
-      const int f = spec.f0 + i;
-      load(P.S[f], obase, cvalid, v);
-      fft<NA, E, -1>(v, Lc, t, tws);
-      if (special) partner(P.S[f], v, vm);
-      apply(spec.mult[i], v, vm, acc);
-    }
-    fft<NA, E, +1>(acc, Lc, t, tws);
-    store(P.S[0], acc);
-  } else if constexpr (MODE == 3) {
-    const int f = spec.f0 + (int)blockIdx.y;
-    load(P.S[f], obase, cvalid, v);
-    fft<NA, E, -1>(v, Lc, t, tws);
-    if (tile0) {  // unpack column 0: A(a) at 0 < a < ny/2, B(ny - a) at ny/2 < a < ny
-      mirror(v, vm);
-      if (c == 0) {
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-          const int a = t + TC * m;
-          if (a == 0 || 2 * a == NA) continue;
-          if (2 * a < NA)
-            v[m] = 0.5f * (v[m] + vm[m]);
-          else  // (conj(Q) - conj(P)) (-i/2), P = C(a), Q = conj(C(-a))
-            v[m] = 0.5f * mul_si<-1>(conjf2(vm[m]) - conjf2(v[m]));
-        }
+      for (int i = 0; i < NF; ++i) {
+        load(P.S[spec.f0 + i], v);
+        fft<NA, E, -1>(v, Lc, t, tws);
+        if (special) mirror(v, vm);
+        apply(which_of(i), v, vm, acc);
       }
+      fft<NA, E, +1>(acc, Lc, t, tws);
+      store(P.S[0], acc);
     }
-    store(P.S[f], v);
-  } else {
-    const int f = spec.f0 + (int)blockIdx.y;
-    load(P.S[f], obase, cvalid, v);
-    if (tile0) {  // pack column 0 again: C(a) = A(a) + i B(a), C(-a) = conj(A(a)) + i conj(B(a))
-      float2 u[E];
-#pragma unroll
-      for (int m = 0; m < E; ++m) Lc[t + TC * m] = v[m];
-      __syncthreads();
-#pragma unroll
-      for (int m = 0; m < E; ++m) u[m] = Lc[(NA - (t + TC * m)) & (NA - 1)];  // U(ny - a)
-      __syncthreads();
-      if (c == 0) {
-#pragma unroll
-        for (int m = 0; m < E; ++m) {
-          const int a = t + TC * m;
-          if (a == 0 || 2 * a == NA) continue;
-          if (2 * a < NA)
-            v[m] = v[m] + mul_si<+1>(u[m]);
-          else
-            v[m] = conjf2(u[m]) + mul_si<+1>(conjf2(v[m]));
-        }
-      }
-    }
-    fft<NA, E, +1>(v, Lc, t, tws);
-    store(P.S[f], v);
   }
 }
 
@@ -752,24 +783,40 @@ template <int NA>
 static hipError_t launch_col_n(const ColSpec& spec, const Launch& L) {
   const dim3 block(ColGeo<NA>::NTH);
   const dim3 grid1(L.nblocks), gridf(L.nblocks, spec.nfield);
-#define PAT_COL(MODE, NF, GRID) \
-  hipLaunchKernelGGL((k_col<NA, MODE, NF>), GRID, block, 0, L.stream, L.plans, L.table, spec)
+  // multiplier family from the kinds: derivatives a_j / b_j listed in axis
+  // order, or the two fractional Laplacians
+  int fam;
+  if (spec.mode >= 3)
+    fam = F_A;
+  else if (spec.mult[0] == M_L1DT || spec.mult[0] == M_L2)
+    fam = F_ABS;
+  else
+    fam = (spec.mult[0] >= M_BX) ? F_B : F_A;
+#define PAT_COL(MODE, NF, FAMV, GRID) \
+  hipLaunchKernelGGL((k_col<NA, MODE, NF, FAMV>), GRID, block, 0, L.stream, L.plans, L.table, spec)
+#define PAT_COL_FAM(MODE, NF, GRID)              \
+  do {                                           \
+    if (fam == F_A) PAT_COL(MODE, NF, F_A, GRID);     \
+    else if (fam == F_B) PAT_COL(MODE, NF, F_B, GRID); \
+    else PAT_COL(MODE, NF, F_ABS, GRID);              \
+  } while (0)
   switch (spec.mode) {
     case 0:
-      if (spec.nfield == 2) PAT_COL(0, 2, grid1);
-      else if (spec.nfield == 3) PAT_COL(0, 3, grid1);
+      if (spec.nfield == 2) PAT_COL_FAM(0, 2, grid1);
+      else if (spec.nfield == 3) PAT_COL_FAM(0, 3, grid1);
       else return hipErrorInvalidValue;
       break;
-    case 1: PAT_COL(1, 1, gridf); break;
+    case 1: PAT_COL_FAM(1, 1, gridf); break;
     case 2:
-      if (spec.nfield == 2) PAT_COL(2, 2, grid1);
-      else if (spec.nfield == 3) PAT_COL(2, 3, grid1);
+      if (spec.nfield == 2) PAT_COL_FAM(2, 2, grid1);
+      else if (spec.nfield == 3) PAT_COL_FAM(2, 3, grid1);
       else return hipErrorInvalidValue;
       break;
-    case 3: PAT_COL(3, 1, gridf); break;
-    case 4: PAT_COL(4, 1, gridf); break;
+    case 3: PAT_COL(3, 1, F_A, gridf); break;
+    case 4: PAT_COL(4, 1, F_A, gridf); break;
     default: return hipErrorInvalidValue;
   }
+#undef PAT_COL_FAM
 #undef PAT_COL
   return hipGetLastError();
 }
