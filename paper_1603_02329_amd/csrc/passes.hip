@@ -62,13 +62,14 @@ __device__ __forceinline__ float2 scl2(float s, float2 a) { return make_float2(s
 
 // Packed half spectrum of one row -> real row, as pairs (x[2n], x[2n+1]) at
 // n = t + T m.  Unnormalised inverse real DFT.
+// r holds the packed bins X[t + T m] on entry (already loaded) and the real
+// pairs on exit.
 template <int N>
-__device__ __forceinline__ void c2r(const float2* __restrict__ src, float2 (&r)[RowGeo<N>::E], float2* L, int t,
-                                    bool valid, const Tw* tw) {
+__device__ __forceinline__ void c2r(float2 (&r)[RowGeo<N>::E], float2* L, int t, const Tw* tw) {
   using G = RowGeo<N>;
   constexpr int M = G::M, E = G::E, T = G::T;
 #pragma unroll
-  for (int m = 0; m < E; ++m) L[t + T * m] = valid ? src[t + T * m] : f2(0.f, 0.f);
+  for (int m = 0; m < E; ++m) L[t + T * m] = r[m];
   WaveSync::sync();
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -157,6 +158,42 @@ __device__ __forceinline__ void check_finite(const DevPlan& P, float2 v) {
 }
 
 // ------------------------------------------------------------------ row passes
+// Each row pass first issues every global load it needs (the packed input
+// spectra and the per-point state and medium values of its rows) so that the
+// memory latency is paid once per block, then runs the transforms from
+// registers.  The velocity passes treat one axis component per block
+// (blockIdx.y): the components are independent, and the split halves the
+// registers a block holds.
+template <int N>
+struct RowIo {
+  static constexpr int E = RowGeo<N>::E, T = RowGeo<N>::T;
+  const long base;
+  const int t;
+  const bool valid;
+  __device__ __forceinline__ void ld(const float* a, float2 (&v)[E]) const {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = valid ? ld2(a, base + t + T * m) : f2(0.f, 0.f);
+  }
+  __device__ __forceinline__ void ld(const float2* a, float2 (&v)[E]) const {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = valid ? a[base + t + T * m] : f2(0.f, 0.f);
+  }
+  // 1-D x table (PML factor along x), pairs at n = t + T m
+  __device__ __forceinline__ void ldx(const float* a, float2 (&v)[E]) const {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = ld2(a, t + T * m);
+  }
+  __device__ __forceinline__ void st(float* a, const float2 (&v)[E]) const {
+    if (!valid) return;
+#pragma unroll
+    for (int m = 0; m < E; ++m) st2(a, base + t + T * m, v[m]);
+  }
+  __device__ __forceinline__ void zero(float2 (&v)[E]) const {
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = f2(0.f, 0.f);
+  }
+};
+
 template <int N, int D, int K>
 __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restrict__ plans,
                                                         const int2* __restrict__ table, StepArg sa) {
@@ -165,7 +202,6 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
   __shared__ float2 lds[G::ROWS * M];
   __shared__ Tw tws[N];
   load_twiddles<N, G::NTH>(tws, g_tw);
-  __syncthreads();
   const int2 job = table ? table[blockIdx.x] : make_int2(0, (int)blockIdx.x);
   const DevPlan& P = plans[job.x];
   const int rl = threadIdx.x / T, t = threadIdx.x % T;
@@ -176,125 +212,157 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
   const int yy = rowc % ny, zz = rowc / ny;
   float2* L = lds + rl * M;
   float* Lf = reinterpret_cast<float*>(L);
-  const long base = (long)rowc * M;  // float2 index of this row
-  const int it = step_of(sa);         // forward step n / adjoint iteration i
+  const RowIo<N> io{(long)rowc * M, t, valid};
+  const int it = step_of(sa);  // forward step n / adjoint iteration i
 
   // per-row PML factors of the y and z axes
-  float qy = 1.f, qsy = 1.f, qz = 1.f, qsz = 1.f;
-  qy = P.Q[1][yy];
-  qsy = P.Qsg[1][yy];
+  float qrow[3] = {1.f, P.Q[1][yy], 1.f};
+  float qsrow[3] = {1.f, P.Qsg[1][yy], 1.f};
   if constexpr (D == 3) {
-    qz = P.Q[2][zz];
-    qsz = P.Qsg[2][zz];
+    qrow[2] = P.Q[2][zz];
+    qsrow[2] = P.Qsg[2][zz];
   }
-  const float qrow[3] = {1.f, qy, qz};
-  const float qsrow[3] = {1.f, qsy, qsz};
+  auto qpair = [&](int j, const float2& qx) { return j == 0 ? qx : f2(qrow[j], qrow[j]); };
+  auto qspair = [&](int j, const float2& qx) { return j == 0 ? qx : f2(qsrow[j], qsrow[j]); };
 
   if constexpr (K == R_FWD_INIT) {
-    float2 p[E];
+    float2 p[E], ic[E];
+    io.ld(P.in, p);
+    io.ld(P.inv_dc2, ic);
+    __syncthreads();  // twiddles
+    float2 rr[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int n = t + T * m;
-      p[m] = valid ? ld2(P.in, base + n) : f2(0.f, 0.f);
-      const float2 rr = mul2(p[m], valid ? ld2(P.inv_dc2, base + n) : f2(0.f, 0.f));
-      if (valid) {
-#pragma unroll
-        for (int j = 0; j < D; ++j) st2(P.r[j], base + n, rr);
-      }
-      L[n] = p[m];
+      rr[m] = mul2(p[m], ic[m]);
+      L[t + T * m] = p[m];
     }
+#pragma unroll
+    for (int j = 0; j < D; ++j) io.st(P.r[j], rr);
     gather_row<N>(P, 0, Lf, rowc, t, valid);
-    r2c<N>(p, P.S[0] + base, L, t, valid, tws);
-  } else if constexpr (K == R_FWD_1) {
-    float2 d[D][E];
-#pragma unroll
-    for (int j = 0; j < D; ++j) c2r<N>(P.S[1 + j] + base, d[j], L, t, valid, tws);
+    r2c<N>(p, P.S[0] + io.base, L, t, valid, tws);
+  } else if constexpr (K == R_FWD_1 || K == R_ADJ_1) {
+    // one axis component j per block
+    const int j = (int)blockIdx.y;
     const bool first = (it == 0);
+    const bool last = (K == R_ADJ_1) && (it == P.nt - 2);
+    float2 d[E], b[E], u[E], qx[E];
+    io.ld(P.S[1 + j], d);
+    io.ld(P.B[j], b);
+    if (first) io.zero(u); else io.ld(P.u[j], u);
+    if (j == 0) io.ldx(P.Qsg[0], qx);
+    __syncthreads();  // twiddles
+    c2r<N>(d, L, t, tws);
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-#pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const int n = t + T * m;
-        if (!valid) continue;
-        const float2 b = ld2(P.B[j], base + n);
-        const float2 qs = (j == 0) ? ld2(P.Qsg[0], n) : f2(qsrow[j], qsrow[j]);
-        const float2 db = mul2(b, d[j][m]);
-        const float2 u = first ? scl2(0.5f, db) : ld2(P.u[j], base + n);
-        const float2 un = mul2(qs, mul2(qs, u) - db);
-        st2(P.u[j], base + n, un);
-        d[j][m] = un;
+    for (int m = 0; m < E; ++m) {
+      const float2 qs = qspair(j, qx[m]);
+      if constexpr (K == R_FWD_1) {
+        // u <- Qsg (Qsg u - B d p); the first step starts from u = (B/2) d p
+        const float2 db = mul2(b[m], d[m]);
+        const float2 u0 = first ? scl2(0.5f, db) : u[m];
+        u[m] = mul2(qs, mul2(qs, u0) - db);
+        d[m] = u[m];
+      } else {
+        // ubar -= d+ gbar; feed B Qsg ubar (last step: B Qsg ubar (1 - Qsg/2)), ubar <- Qsg^2 ubar
+        const float2 ub = u[m] - d[m];
+        const float2 bq = mul2(b[m], mul2(qs, ub));
+        d[m] = last ? mul2(bq, f2(1.f - 0.5f * qs.x, 1.f - 0.5f * qs.y)) : bq;
+        u[m] = mul2(mul2(qs, qs), ub);
       }
     }
-#pragma unroll
-    for (int j = 0; j < D; ++j) r2c<N>(d[j], P.S[1 + j] + base, L, t, valid, tws);
+    if (K == R_FWD_1 || !last) io.st(P.u[j], u);
+    r2c<N>(d, P.S[1 + j] + io.base, L, t, valid, tws);
   } else if constexpr (K == R_FWD_2 || K == R_FWD_2LL) {
-    float2 g[D][E];
+    float2 g[D][E], r[D][E], dr[E], c2[E], qx[E];
 #pragma unroll
-    for (int j = 0; j < D; ++j) c2r<N>(P.S[1 + j] + base, g[j], L, t, valid, tws);
+    for (int j = 0; j < D; ++j) io.ld(P.S[1 + j], g[j]);
+#pragma unroll
+    for (int j = 0; j < D; ++j) io.ld(P.r[j], r[j]);
+    io.ld(P.dtr0, dr);
+    if constexpr (K == R_FWD_2LL) io.ld(P.c2, c2);
+    io.ldx(P.Q[0], qx);
+    __syncthreads();  // twiddles
+#pragma unroll
+    for (int j = 0; j < D; ++j) c2r<N>(g[j], L, t, tws);
     float2 sdiv[E], srho[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int n = t + T * m;
       sdiv[m] = f2(0.f, 0.f);
       srho[m] = f2(0.f, 0.f);
-      if (!valid) continue;
-      const float2 dr = ld2(P.dtr0, base + n);
 #pragma unroll
       for (int j = 0; j < D; ++j) {
-        const float2 q = (j == 0) ? ld2(P.Q[0], n) : f2(qrow[j], qrow[j]);
-        const float2 tj = mul2(dr, g[j][m]);
-        const float2 rn = mul2(q, mul2(q, ld2(P.r[j], base + n)) - tj);
-        st2(P.r[j], base + n, rn);
+        const float2 q = qpair(j, qx[m]);
+        const float2 tj = mul2(dr[m], g[j][m]);
+        r[j][m] = mul2(q, mul2(q, r[j][m]) - tj);
         sdiv[m] = sdiv[m] + tj;
-        srho[m] = srho[m] + rn;
+        srho[m] = srho[m] + r[j][m];
       }
     }
+#pragma unroll
+    for (int j = 0; j < D; ++j) io.st(P.r[j], r[j]);
     if constexpr (K == R_FWD_2) {
-      r2c<N>(sdiv, P.S[1] + base, L, t, valid, tws);
-      r2c<N>(srho, P.S[2] + base, L, t, valid, tws);
+      r2c<N>(sdiv, P.S[1] + io.base, L, t, valid, tws);
+      r2c<N>(srho, P.S[2] + io.base, L, t, valid, tws);
     } else {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const int n = t + T * m;
-        const float2 p = valid ? mul2(ld2(P.c2, base + n), srho[m]) : f2(0.f, 0.f);
-        if (valid) check_finite(P, p);
-        srho[m] = p;
-        L[n] = p;
+        srho[m] = mul2(c2[m], srho[m]);
+        if (valid) check_finite(P, srho[m]);
+        L[t + T * m] = srho[m];
       }
       gather_row<N>(P, it + 1, Lf, rowc, t, valid);
-      r2c<N>(srho, P.S[0] + base, L, t, valid, tws);
+      r2c<N>(srho, P.S[0] + io.base, L, t, valid, tws);
     }
   } else if constexpr (K == R_FWD_3) {
-    float2 a1[E], a2[E];
-    c2r<N>(P.S[1] + base, a1, L, t, valid, tws);
-    c2r<N>(P.S[2] + base, a2, L, t, valid, tws);
+    // the spectra first; the pointwise operands after the transforms (loading
+    // all of them up front would double the registers held across the FFTs)
+    float2 a1[E], a2[E], rs[E], c2[E], ct[E], ce[E];
+    io.ld(P.S[1], a1);
+    io.ld(P.S[2], a2);
+    __syncthreads();  // twiddles
+    c2r<N>(a1, L, t, tws);
+    c2r<N>(a2, L, t, tws);
+    io.ld(P.r[0], rs);
+#pragma unroll
+    for (int j = 1; j < D; ++j) {
+      float2 rj[E];
+      io.ld(P.r[j], rj);
+#pragma unroll
+      for (int m = 0; m < E; ++m) rs[m] = rs[m] + rj[m];
+    }
+    io.ld(P.c2, c2);
+    io.ld(P.c2tau, ct);
+    io.ld(P.c2eta, ce);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int n = t + T * m;
-      float2 p = f2(0.f, 0.f);
-      if (valid) {
-        float2 rs = ld2(P.r[0], base + n);
-#pragma unroll
-        for (int j = 1; j < D; ++j) rs = rs + ld2(P.r[j], base + n);
-        p = mul2(ld2(P.c2, base + n), rs) + mul2(ld2(P.c2tau, base + n), a1[m]) -
-            mul2(ld2(P.c2eta, base + n), a2[m]);
-        check_finite(P, p);
-      }
+      const float2 p = mul2(c2[m], rs[m]) + mul2(ct[m], a1[m]) - mul2(ce[m], a2[m]);
+      if (valid) check_finite(P, p);
       a1[m] = p;
-      L[n] = p;
+      L[t + T * m] = p;
     }
     gather_row<N>(P, it + 1, Lf, rowc, t, valid);
-    r2c<N>(a1, P.S[0] + base, L, t, valid, tws);
+    r2c<N>(a1, P.S[0] + io.base, L, t, valid, tws);
   } else if constexpr (K == R_ADJ_3 || K == R_ADJ_32LL) {
     const bool first = (it == 0);
     const int nsamp = P.nt - 1 - it;  // h[n+1] with n = nt-2-it
-    float2 v[E];
-    if (first) {
-#pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = f2(0.f, 0.f);
+    float2 v[E], c2[E], e1[E], e2[E], dr[E], qx[E];
+    if (first) io.zero(v); else io.ld(P.S[0], v);
+    io.ld(P.c2, c2);
+    if constexpr (K == R_ADJ_3) {
+      io.ld(P.c2eta, e1);
+      io.ld(P.c2tau, e2);
     } else {
-      c2r<N>(P.S[0] + base, v, L, t, valid, tws);
+      io.ld(P.dtr0, dr);
+      io.ldx(P.Q[0], qx);
     }
+    float2 rb[D][E];
+    if constexpr (K == R_ADJ_32LL) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        if (first) io.zero(rb[j]); else io.ld(P.r[j], rb[j]);
+      }
+    }
+    __syncthreads();  // twiddles
+    if (!first) c2r<N>(v, L, t, tws);
 #pragma unroll
     for (int m = 0; m < E; ++m) L[t + T * m] = v[m];
     scatter_row<N>(P, nsamp, Lf, rowc, t, valid);
@@ -302,118 +370,92 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
     for (int m = 0; m < E; ++m) v[m] = L[t + T * m];
     WaveSync::sync();
     if constexpr (K == R_ADJ_3) {
-      float2 e[E], ta[E];
+      float2 q[E];
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const int n = t + T * m;
-        e[m] = f2(0.f, 0.f);
-        ta[m] = f2(0.f, 0.f);
-        if (!valid) continue;
-        st2(P.q, base + n, mul2(ld2(P.c2, base + n), v[m]));
-        e[m] = mul2(ld2(P.c2eta, base + n), v[m]);
-        ta[m] = mul2(ld2(P.c2tau, base + n), v[m]);
+        q[m] = mul2(c2[m], v[m]);
+        e1[m] = mul2(e1[m], v[m]);
+        e2[m] = mul2(e2[m], v[m]);
       }
-      r2c<N>(e, P.S[1] + base, L, t, valid, tws);
-      r2c<N>(ta, P.S[2] + base, L, t, valid, tws);
+      io.st(P.q, q);
+      r2c<N>(e1, P.S[1] + io.base, L, t, valid, tws);
+      r2c<N>(e2, P.S[2] + io.base, L, t, valid, tws);
     } else {
       float2 g[D][E];
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const int n = t + T * m;
-#pragma unroll
-        for (int j = 0; j < D; ++j) g[j][m] = f2(0.f, 0.f);
-        if (!valid) continue;
-        const float2 q = mul2(ld2(P.c2, base + n), v[m]);
-        const float2 dr = ld2(P.dtr0, base + n);
+        const float2 q = mul2(c2[m], v[m]);
 #pragma unroll
         for (int j = 0; j < D; ++j) {
-          const float2 qq = (j == 0) ? ld2(P.Q[0], n) : f2(qrow[j], qrow[j]);
-          const float2 rb = (first ? f2(0.f, 0.f) : ld2(P.r[j], base + n)) + q;
-          g[j][m] = f2(0.f, 0.f) - mul2(dr, mul2(qq, rb));
-          st2(P.r[j], base + n, mul2(mul2(qq, qq), rb));
+          const float2 qq = qpair(j, qx[m]);
+          const float2 r1 = rb[j][m] + q;
+          g[j][m] = f2(0.f, 0.f) - mul2(dr[m], mul2(qq, r1));
+          rb[j][m] = mul2(mul2(qq, qq), r1);
         }
       }
 #pragma unroll
-      for (int j = 0; j < D; ++j) r2c<N>(g[j], P.S[1 + j] + base, L, t, valid, tws);
+      for (int j = 0; j < D; ++j) io.st(P.r[j], rb[j]);
+#pragma unroll
+      for (int j = 0; j < D; ++j) r2c<N>(g[j], P.S[1 + j] + io.base, L, t, valid, tws);
     }
   } else if constexpr (K == R_ADJ_2) {
     const bool first = (it == 0);
-    float2 a2[E], a1[E];
-    c2r<N>(P.S[1] + base, a2, L, t, valid, tws);
-    c2r<N>(P.S[2] + base, a1, L, t, valid, tws);
+    float2 a2[E], a1[E], q[E], dr[E], qx[E], rb[D][E];
+    io.ld(P.S[1], a2);
+    io.ld(P.S[2], a1);
+    __syncthreads();  // twiddles
+    c2r<N>(a2, L, t, tws);
+    c2r<N>(a1, L, t, tws);
+    io.ld(P.q, q);
+    io.ld(P.dtr0, dr);
+    io.ldx(P.Q[0], qx);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      if (first) io.zero(rb[j]); else io.ld(P.r[j], rb[j]);
+    }
     float2 g[D][E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int n = t + T * m;
-#pragma unroll
-      for (int j = 0; j < D; ++j) g[j][m] = f2(0.f, 0.f);
-      if (!valid) continue;
-      const float2 qa = ld2(P.q, base + n) - a2[m];
-      const float2 dr = ld2(P.dtr0, base + n);
+      const float2 qa = q[m] - a2[m];
 #pragma unroll
       for (int j = 0; j < D; ++j) {
-        const float2 qq = (j == 0) ? ld2(P.Q[0], n) : f2(qrow[j], qrow[j]);
-        const float2 rb = (first ? f2(0.f, 0.f) : ld2(P.r[j], base + n)) + qa;
-        g[j][m] = mul2(dr, a1[m] - mul2(qq, rb));
-        st2(P.r[j], base + n, mul2(mul2(qq, qq), rb));
+        const float2 qq = qpair(j, qx[m]);
+        const float2 r1 = rb[j][m] + qa;
+        g[j][m] = mul2(dr[m], a1[m] - mul2(qq, r1));
+        rb[j][m] = mul2(mul2(qq, qq), r1);
       }
     }
 #pragma unroll
-    for (int j = 0; j < D; ++j) r2c<N>(g[j], P.S[1 + j] + base, L, t, valid, tws);
-  } else if constexpr (K == R_ADJ_1) {
-    const bool first = (it == 0);
-    const bool last = (it == P.nt - 2);
-    float2 d[D][E];
+    for (int j = 0; j < D; ++j) io.st(P.r[j], rb[j]);
 #pragma unroll
-    for (int j = 0; j < D; ++j) c2r<N>(P.S[1 + j] + base, d[j], L, t, valid, tws);
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-#pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const int n = t + T * m;
-        if (!valid) {
-          d[j][m] = f2(0.f, 0.f);
-          continue;
-        }
-        const float2 qs = (j == 0) ? ld2(P.Qsg[0], n) : f2(qsrow[j], qsrow[j]);
-        const float2 b = ld2(P.B[j], base + n);
-        const float2 ub = (first ? f2(0.f, 0.f) : ld2(P.u[j], base + n)) - d[j][m];
-        const float2 bq = mul2(b, mul2(qs, ub));
-        if (last) {
-          d[j][m] = mul2(bq, f2(1.f - 0.5f * qs.x, 1.f - 0.5f * qs.y));
-        } else {
-          d[j][m] = bq;
-          st2(P.u[j], base + n, mul2(mul2(qs, qs), ub));
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < D; ++j) r2c<N>(d[j], P.S[1 + j] + base, L, t, valid, tws);
+    for (int j = 0; j < D; ++j) r2c<N>(g[j], P.S[1 + j] + io.base, L, t, valid, tws);
   } else if constexpr (K == R_ADJ_FINAL || K == R_ADJ_SCATTER_ONLY) {
-    float2 v[E];
+    float2 v[E], rs[E], ic[E];
     if constexpr (K == R_ADJ_FINAL) {
-      c2r<N>(P.S[0] + base, v, L, t, valid, tws);
-    } else {
+      io.ld(P.S[0], v);
+      io.ld(P.r[0], rs);
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = f2(0.f, 0.f);
+      for (int j = 1; j < D; ++j) {
+        float2 rj[E];
+        io.ld(P.r[j], rj);
+#pragma unroll
+        for (int m = 0; m < E; ++m) rs[m] = rs[m] + rj[m];
+      }
+      io.ld(P.inv_dc2, ic);
+    } else {
+      io.zero(v);
     }
+    __syncthreads();  // twiddles
+    if constexpr (K == R_ADJ_FINAL) c2r<N>(v, L, t, tws);
 #pragma unroll
     for (int m = 0; m < E; ++m) L[t + T * m] = v[m];
     scatter_row<N>(P, 0, Lf, rowc, t, valid);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int n = t + T * m;
-      float2 x = L[n];
-      if (valid) {
-        if constexpr (K == R_ADJ_FINAL) {
-          float2 rs = ld2(P.r[0], base + n);
-#pragma unroll
-          for (int j = 1; j < D; ++j) rs = rs + ld2(P.r[j], base + n);
-          x = x + mul2(rs, ld2(P.inv_dc2, base + n));
-        }
-        st2(P.out, base + n, x);
-      }
+      v[m] = L[t + T * m];
+      if constexpr (K == R_ADJ_FINAL) v[m] = v[m] + mul2(rs[m], ic[m]);
     }
+    io.st(P.out, v);
   }
 }
 
@@ -707,7 +749,9 @@ int row_tile_rows(int nx) {
 
 template <int N, int D>
 static hipError_t launch_row_nd(RowKind kind, const Launch& L, StepArg s) {
-  const dim3 grid(L.nblocks), block(RowGeo<N>::NTH);
+  // the velocity passes run one axis component per block row (grid.y)
+  const bool per_axis = (kind == R_FWD_1 || kind == R_ADJ_1);
+  const dim3 grid(L.nblocks, per_axis ? D : 1), block(RowGeo<N>::NTH);
 #define PAT_ROW_CASE(KK) \
   case KK: hipLaunchKernelGGL((k_row<N, D, KK>), grid, block, 0, L.stream, L.plans, L.table, s); break;
   switch (kind) {
