@@ -45,6 +45,37 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+KERNEL_SOURCES = ("paper_1603_02329_amd/csrc/passes.hip", "paper_1603_02329_amd/csrc/fft.h",
+                  "paper_1603_02329_amd/csrc/pat_internal.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when that summary was taken on different kernel
+    sources (or is missing)."""
+    path = os.path.join(ROOT, "profiles", "cfg4_counters_fetch_write.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].strip().split(": ", 1)
+            fields[k] = v.strip("` ")
+    if fields.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    key = f"traffic_bytes_per_launch[{kernel}]"
+    return float(fields[key]) if key in fields else None
+
+
 def cpu_baseline(insts, seconds_target=15.0):
     """The FP64 oracle on a bounded sample: one instance of each grid size,
     a shortened time axis, forward + adjoint."""
@@ -84,6 +115,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--time-pass", default="0:1", help="direction:pass_index timed with HIP events")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="counter probe: a 256 MiB device copy (calibration) and one eager batched "
+                         "forward + adjoint, nothing timed; run under rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver runs each instance on a single device "
@@ -95,9 +129,30 @@ def main():
     import paper_1603_02329_amd as pat
     dev = torch.device("cuda:0")
     insts, wl_name = workload(args.workload)
+    if args.pmc_probe:
+        # same instances and launch geometry, 9 time samples: the per-launch
+        # traffic of a pass does not depend on the length of the time axis
+        import synth
+        from dataclasses import replace
+        insts = [synth.Instance(replace(i.desc, nt=min(i.desc.nt, 9)), i.c0, i.rho0, i.alpha0_db, i.sensors,
+                                i.p0, i.name) for i in insts]
     log(f"workload: {wl_name} ({len(insts)} instances)")
     plans = [pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=dev) for i in insts]
     x_true = [torch.from_numpy(i.p0).to(dev) for i in insts]
+    if args.pmc_probe:
+        # counter calibration: an elementwise kernel that reads and writes
+        # exactly 1 GiB of data not resident in any cache (a second 1 GiB
+        # fill in between evicts it from L2 and the Infinity Cache)
+        a = torch.ones(256 * 1024 * 1024, device=dev)
+        flush = torch.zeros(256 * 1024 * 1024, device=dev)
+        b = torch.add(a, 1.0)
+        del flush, b
+        probe = pat.Batch(plans, chunk=1)
+        d = probe.forward(x_true)
+        probe.adjoint(d)
+        torch.cuda.synchronize()
+        log("pmc probe done")
+        return
     batch = pat.Batch(plans, chunk=args.chunk)
     targets = [d.clone() for d in batch.forward(x_true)]
     xs = [0.5 * x for x in x_true]
@@ -143,14 +198,15 @@ def main():
     # main timed region: batched executor; the selected pass is timed with
     # HIP events on its stream when the batch runs eagerly (chunk 1)
     tdir, tidx = (int(v) for v in args.time_pass.split(":"))
-    pat.timing_begin(tdir, tidx)
+    nx_dom = max(p.desc.n[0] for p in plans)  # time the largest grids' launches only
+    pat.timing_begin(tdir, tidx, nx_dom)
     ms = timed(batched, args.steps, args.warmup, f"batched(chunk={args.chunk})")
     k_ms, k_n, k_bytes = pat.timing_end()
     if k_n == 0:
         # graph-captured launches are not event-timed: time the same pass
         # over the same batch with an eager (chunk 1) batch right after
         b1 = pat.Batch(plans, chunk=1)
-        pat.timing_begin(tdir, tidx)
+        pat.timing_begin(tdir, tidx, nx_dom)
         step(b1.forward, b1.adjoint)
         torch.cuda.synchronize()
         k_ms, k_n, k_bytes = pat.timing_end()
@@ -195,7 +251,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": counter_traffic("k_row<512, 2, 1>") if (tdir, tidx) == (0, 1) else None,
             "launches": k_n,
             "avg_launch_us": (k_ms / k_n * 1e3) if k_n else None,
             "measured_in": kernel_note,

@@ -240,10 +240,11 @@ int pat_plan_sync(pat_plan* plan, void* stream);
  * Diagnostics: HIP-event timing of one pass of the time step.
  *
  * pat_timing_begin selects pass `pass_index` (0-based position in the step's
- * launch sequence) of direction 0 (forward) or 1 (adjoint); every later
- * eager launch of that pass -- by pat_forward, pat_adjoint, pat_forward_range
- * or a batch created with chunk = 1 -- is bracketed by HIP events on its
- * stream.  pat_timing_end waits for those events and returns their summed
+ * launch sequence) of direction 0 (forward) or 1 (adjoint), for grids with
+ * row length nx (0: any); every later eager launch of that pass -- by
+ * pat_forward, pat_adjoint, pat_forward_range, or the eager steps of a batch
+ * (all of them with chunk = 1, else the nt-1 mod chunk steps run before the
+ * graph-captured chunks) -- is bracketed by HIP events on its stream.  pat_timing_end waits for those events and returns their summed
  * duration [ms], the number of launches and the algorithmic bytes they moved
  * (full-grid float32 arrays each pass must read and write, per grid point,
  * times the points the launch covers).  Not thread-safe against concurrent
@@ -255,7 +256,7 @@ int pat_plan_sync(pat_plan* plan, void* stream);
  * (row), 1 absorption (column), 2 density (row), 3 gradient (column),
  * 4 velocity (row), 5 divergence sum (column).
  */
-int pat_timing_begin(int32_t direction, int32_t pass_index);
+int pat_timing_begin(int32_t direction, int32_t pass_index, int32_t nx);
 int pat_timing_end(double* total_ms, int64_t* launches, double* alg_bytes);
 
 /* Static description of a return code. */

@@ -89,7 +89,7 @@ def lib() -> ctypes.CDLL:
         "pat_residual_f64": (ctypes.c_int, [vp, vp, vp, i64, ctypes.POINTER(f64), vp]),
         "pat_plan_sync": (ctypes.c_int, [vp, vp]),
         "pat_strerror": (ctypes.c_char_p, [ctypes.c_int]),
-        "pat_timing_begin": (ctypes.c_int, [i32, i32]),
+        "pat_timing_begin": (ctypes.c_int, [i32, i32, i32]),
         "pat_timing_end": (ctypes.c_int, [ctypes.POINTER(f64), ctypes.POINTER(i64), ctypes.POINTER(f64)]),
     }
     for name, (res, args) in sig.items():
@@ -289,9 +289,9 @@ class Batch:
         return imgs
 
 
-def timing_begin(direction: int, pass_index: int) -> None:
+def timing_begin(direction: int, pass_index: int, nx: int = 0) -> None:
     """Start HIP-event timing of one pass of the time step (see pat.h)."""
-    _check(lib().pat_timing_begin(int(direction), int(pass_index)), "pat_timing_begin")
+    _check(lib().pat_timing_begin(int(direction), int(pass_index), int(nx)), "pat_timing_begin")
 
 
 def timing_end():

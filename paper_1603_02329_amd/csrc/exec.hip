@@ -19,9 +19,9 @@ namespace pat {
 // ------------------------------------------------------------------ pass sequences
 int step_ops(int dir, int ndim, int lossy, PassOp* ops) {
   int n = 0;
-  auto row = [&](RowKind k) { ops[n++] = PassOp{0, k, ColSpec{0, 0, {0, 0, 0}, 0}}; };
+  auto row = [&](RowKind k) { ops[n++] = PassOp{0, k, ColSpec{0, 0, {0, 0, 0}, 0, -1}}; };
   auto col = [&](int mode, int nf, int f0, int a, int b, int c) {
-    ops[n++] = PassOp{1, R_COUNT, ColSpec{mode, nf, {a, b, c}, f0}};
+    ops[n++] = PassOp{1, R_COUNT, ColSpec{mode, nf, {a, b, c}, f0, -1}};
   };
   // spectral operator on fields [f0, f0+nf) along the remaining axes: 2D one
   // column pass; 3D a y-transform pass, the z pass with the multipliers and
@@ -70,7 +70,7 @@ double pass_bytes_per_point(const PassOp& op, int ndim, int lossy) {
   if (op.is_col) {
     const int f = op.col.nfield;
     // packed spectra: 4 bytes per grid point and field
-    if (op.col.mode == 0) return 4.0 * (1 + f);
+    if (op.col.mode == 0 || (op.col.mode == 1 && op.col.src >= 0)) return 4.0 * (1 + f);  // algorithmic: input once
     if (op.col.mode == 2) return 4.0 * (f + 1);
     return 8.0 * f;  // modes 1, 3, 4: each field read and written
   }
@@ -79,7 +79,7 @@ double pass_bytes_per_point(const PassOp& op, int ndim, int lossy) {
     case R_FWD_1: return 20.0 * d;               // S_j, u_j, B_j -> u_j, S_j
     case R_FWD_2: return 4.0 * (3 * d + 3);      // S_j, rho_j, dt rho0 -> rho_j, S1, S2
     case R_FWD_2LL: return 4.0 * (3 * d + 3);    // S_j, rho_j, dt rho0, c0^2 -> rho_j, S0
-    case R_FWD_3: return 4.0 * (d + 6);          // S1, S2, rho_j, c0^2, c0^2 tau, c0^2 eta -> S0
+    case R_FWD_3: return 4.0 * (d + 6);          // S1, S2, rho_j, c0^2, c0^2 tau, c0^2 eta -> S0 (algorithmic)
     case R_ADJ_3: return 28.0;                   // S0, c0^2, c0^2 eta, c0^2 tau -> q, S1, S2
     case R_ADJ_32LL: return 4.0 * (3 * d + 3);   // S0, c0^2, rho_j, dt rho0 -> rho_j, S_j
     case R_ADJ_2: return 4.0 * (3 * d + 4);      // S1, S2, q, rho_j, dt rho0 -> rho_j, S_j
@@ -94,7 +94,7 @@ namespace {
 
 // ------------------------------------------------------------------ event timing
 struct Timing {
-  int dir = -1, index = -1;
+  int dir = -1, index = -1, nx = 0;
   std::vector<hipEvent_t> ev;
   size_t used = 0;
   double bytes = 0;
@@ -104,29 +104,26 @@ std::mutex g_tmu;
 Timing g_timing;
 bool g_timing_on = false;
 
+// Event pair for one launch of the timed pass (or none): the kernel launch
+// stamps the events at its own start and end (hipExtLaunchKernelGGL), so the
+// elapsed time is the kernel's duration alone.
 struct TimeScope {
-  bool on = false;
-  hipStream_t st;
-  hipEvent_t e1 = nullptr;
-  TimeScope(int dir, int idx, hipStream_t s, double bytes) : st(s) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  TimeScope(int dir, int idx, int nx, double bytes) {
     std::lock_guard<std::mutex> lk(g_tmu);
     if (!g_timing_on || g_timing.dir != dir || g_timing.index != idx) return;
+    if (g_timing.nx && g_timing.nx != nx) return;
     if (g_timing.used + 2 > g_timing.ev.size()) {
       hipEvent_t a, b;
       if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
       g_timing.ev.push_back(a);
       g_timing.ev.push_back(b);
     }
-    hipEvent_t e0 = g_timing.ev[g_timing.used];
+    e0 = g_timing.ev[g_timing.used];
     e1 = g_timing.ev[g_timing.used + 1];
     g_timing.used += 2;
     g_timing.bytes += bytes;
     g_timing.launches += 1;
-    hipEventRecord(e0, st);
-    on = true;
-  }
-  ~TimeScope() {
-    if (on) hipEventRecord(e1, st);
   }
 };
 
@@ -136,6 +133,7 @@ __global__ void k_set_io(DevPlan* p, const float* in, float* out) {
 }
 
 constexpr int kIoMax = 64;
+constexpr int kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
 struct IoArgs {
   const float* in[kIoMax];
   float* out[kIoMax];
@@ -160,19 +158,18 @@ struct Runner {
   double points;  // grid points covered by one launch (all instances)
 
   int op(int dir, int idx, const PassOp& o, StepArg sa, hipStream_t st, bool timed) const {
-    const double bytes = pass_bytes_per_point(o, ndim, lossy) * points;
     if (timed) {
-      TimeScope ts(dir, idx, st, bytes);
-      return launch1(o, sa, st);
+      const TimeScope ts(dir, idx, nx, pass_bytes_per_point(o, ndim, lossy) * points);
+      return launch1(o, sa, st, ts.e0, ts.e1);
     }
-    return launch1(o, sa, st);
+    return launch1(o, sa, st, nullptr, nullptr);
   }
-  int launch1(const PassOp& o, StepArg sa, hipStream_t st) const {
+  int launch1(const PassOp& o, StepArg sa, hipStream_t st, hipEvent_t e0, hipEvent_t e1) const {
     hipError_t e;
     if (o.is_col)
-      e = launch_col(o.col, ndim, nx, ny, nz, Launch{recs, col_tab, col_n, st});
+      e = launch_col(o.col, ndim, nx, ny, nz, Launch{recs, col_tab, col_n, st, e0, e1});
     else
-      e = launch_row(o.row, ndim, nx, Launch{recs, row_tab, row_n, st}, sa);
+      e = launch_row(o.row, ndim, nx, Launch{recs, row_tab, row_n, st, e0, e1}, sa);
     return e == hipSuccess ? PAT_OK : PAT_EHIP;
   }
   int row(RowKind k, StepArg sa, hipStream_t st) const {
@@ -274,11 +271,12 @@ extern "C" int pat_forward_range(pat_plan* p, const float* p0, float* data, int3
 }
 
 // ===================================================================== timing diagnostics
-extern "C" int pat_timing_begin(int32_t direction, int32_t pass_index) {
+extern "C" int pat_timing_begin(int32_t direction, int32_t pass_index, int32_t nx) {
   std::lock_guard<std::mutex> lk(g_tmu);
-  if (direction < 0 || direction > 1 || pass_index < 0 || pass_index >= kMaxOps) return PAT_EINVAL;
+  if (direction < 0 || direction > 1 || pass_index < 0 || pass_index >= kMaxOps || nx < 0) return PAT_EINVAL;
   g_timing.dir = direction;
   g_timing.index = pass_index;
+  g_timing.nx = nx;
   g_timing.used = 0;
   g_timing.bytes = 0;
   g_timing.launches = 0;
@@ -390,20 +388,32 @@ int capture(pat_batch* b, BatchClass& c, int dir) {
   return rc;
 }
 
-// steps [0, nsteps) of direction dir on the class stream: graph chunks, then
-// an eager remainder
+// steps [0, nsteps) of direction dir on the class stream: `full` graph chunks
+// with the nsteps mod chunk remaining steps run eagerly and spread evenly
+// between the chunks (the eager launches are the ones diagnostics can time,
+// so they sample the whole run); the device counter skips the eager steps
 int run_steps(pat_batch* b, BatchClass& c, int dir, int nsteps) {
   const Runner R = c.runner();
   const int full = b->chunk > 1 ? nsteps / b->chunk : 0;
+  const int rem = nsteps - full * b->chunk;
+  if (full == 0) return R.steps(dir, 0, nsteps, c.st);
   int rc = PAT_OK;
-  if (full > 0) {
-    if (!c.graph[dir] && (rc = capture(b, c, dir))) return rc;
-    hipLaunchKernelGGL(k_set_ctr, dim3(1), dim3(1), 0, c.st, c.ctr, 0);
-    if (hipGetLastError() != hipSuccess) return PAT_EHIP;
-    for (int i = 0; i < full && !rc; ++i)
-      if (hipGraphLaunch(c.graph[dir], c.st) != hipSuccess) rc = PAT_EHIP;
+  if (!c.graph[dir] && (rc = capture(b, c, dir))) return rc;
+  hipLaunchKernelGGL(k_set_ctr, dim3(1), dim3(1), 0, c.st, c.ctr, 0);
+  if (hipGetLastError() != hipSuccess) return PAT_EHIP;
+  int n = 0, done_eager = 0;
+  for (int g = 0; g < full && !rc; ++g) {
+    const int want = (int)((long)(g + 1) * rem / full);  // eager steps due by chunk g
+    for (; done_eager < want && !rc; ++done_eager, ++n) {
+      rc = R.steps(dir, n, n + 1, c.st);
+      if (!rc) {
+        hipLaunchKernelGGL(k_add_ctr, dim3(1), dim3(1), 0, c.st, c.ctr, 1);
+        if (hipGetLastError() != hipSuccess) rc = PAT_EHIP;
+      }
+    }
+    if (!rc && hipGraphLaunch(c.graph[dir], c.st) != hipSuccess) rc = PAT_EHIP;
+    n += b->chunk;
   }
-  if (!rc) rc = R.steps(dir, full * b->chunk, nsteps, c.st);
   return rc;
 }
 
@@ -511,9 +521,22 @@ extern "C" int pat_batch_create(pat_batch** out, pat_plan* const* plans, int32_t
     const int R = row_tile_rows(c.nx);
     const int rows_per = (c.ny * c.nz + R - 1) / R;
     const int cols_per = col_tiles(c.ndim, c.nx, c.ny, c.nz);
-    for (int i = 0; i < (int)c.plans.size(); ++i) {
-      for (int t = 0; t < rows_per; ++t) rt[k].push_back(make_int2(i, t));
-      for (int t = 0; t < cols_per; ++t) ct[k].push_back(make_int2(i, t));
+    // XCD-aware order: workgroups are dispatched round-robin over the eight
+    // XCDs (each with its own L2), so entry e runs on XCD e mod 8.  Entries
+    // interleave the instances of each group of eight, so that every pass of
+    // an instance runs on the same XCD and re-reads what the previous pass
+    // of that instance left in that XCD's L2.
+    const int ninst = (int)c.plans.size();
+    auto interleave = [&](std::vector<int2>& tab, int tiles) {
+      for (int g0 = 0; g0 < ninst; g0 += kXcds) {
+        const int gn = std::min(kXcds, ninst - g0);
+        for (int t = 0; t < tiles; ++t)
+          for (int l = 0; l < gn; ++l) tab.push_back(make_int2(g0 + l, t));
+      }
+    };
+    interleave(rt[k], rows_per);
+    interleave(ct[k], cols_per);
+    for (int i = 0; i < ninst; ++i) {
       const int rb = reduce_blocks(c.nt, c.plans[i]->desc.n_sensors);
       for (int t = 0; t < rb; ++t) dt[k].push_back(make_int2(i, t));
     }

@@ -23,6 +23,7 @@
 //   col  : S1 <- |k|^(y-2)/dt S1, S2 <- |k|^(y-1) S2            (absorption)
 //   row 3: p = c0^2 sum rho + c0^2 tau A1 - c0^2 eta A2; gather; S0 <- F_x p
 // and the adjoint runs the transposed passes in reverse order.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -151,6 +152,19 @@ __device__ __forceinline__ void scatter_row(const DevPlan& P, int n, float* Lf, 
     }
   }
   WaveSync::sync();
+}
+
+// c0^2 tau and c0^2 eta from c0^2 when alpha0 is uniform (equation Twelve:
+// tau = -2 a0 c0^(y-1), eta = 2 a0 c0^y tan(pi y / 2))
+template <int E>
+__device__ __forceinline__ void absorption_coefs(const DevPlan& P, const float2 (&c2)[E], float2 (&ct)[E],
+                                                 float2 (&ce)[E]) {
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const float lx = __builtin_amdgcn_logf(c2[m].x), ly = __builtin_amdgcn_logf(c2[m].y);
+    ct[m] = f2(P.ktau * __builtin_amdgcn_exp2f(P.etau * lx), P.ktau * __builtin_amdgcn_exp2f(P.etau * ly));
+    ce[m] = f2(P.keta * __builtin_amdgcn_exp2f(P.eeta * lx), P.keta * __builtin_amdgcn_exp2f(P.eeta * ly));
+  }
 }
 
 __device__ __forceinline__ void check_finite(const DevPlan& P, float2 v) {
@@ -330,8 +344,12 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
       for (int m = 0; m < E; ++m) rs[m] = rs[m] + rj[m];
     }
     io.ld(P.c2, c2);
-    io.ld(P.c2tau, ct);
-    io.ld(P.c2eta, ce);
+    if (P.alpha_uniform) {
+      absorption_coefs<E>(P, c2, ct, ce);
+    } else {
+      io.ld(P.c2tau, ct);
+      io.ld(P.c2eta, ce);
+    }
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const float2 p = mul2(c2[m], rs[m]) + mul2(ct[m], a1[m]) - mul2(ce[m], a2[m]);
@@ -348,8 +366,12 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
     if (first) io.zero(v); else io.ld(P.S[0], v);
     io.ld(P.c2, c2);
     if constexpr (K == R_ADJ_3) {
-      io.ld(P.c2eta, e1);
-      io.ld(P.c2tau, e2);
+      if (P.alpha_uniform) {
+        absorption_coefs<E>(P, c2, e2, e1);
+      } else {
+        io.ld(P.c2eta, e1);
+        io.ld(P.c2tau, e2);
+      }
     } else {
       io.ld(P.dtr0, dr);
       io.ldx(P.Q[0], qx);
@@ -495,16 +517,6 @@ __device__ __forceinline__ XBin xbin(const DevPlan& P, int kxi) {
 // fractional Laplacians |k|^(y-2)/dt, |k|^(y-1).
 enum ColFam : int { F_A = 0, F_B = 1, F_ABS = 2 };
 
-// Per-point multiplier factors, normalised by 1/(nx ny nz):
-//   derivative family: kap = kappa/N and the axis shift of `axis`
-//   absorption family: the two real Laplacian factors
-template <int FAM>
-__device__ __forceinline__ float2 axis_shift(const DevPlan& P, const XBin& xb, int axis, int ky, int kz) {
-  if (axis == 0) return FAM == F_A ? xb.sa : xb.sb;
-  if (axis == 1) return FAM == F_A ? P.shA[1][ky] : P.shB[1][ky];
-  return FAM == F_A ? P.shA[2][kz] : P.shB[2][kz];
-}
-
 // Column pass over a tile of TILE consecutive packed x-bins and all NA points
 // of one axis.
 //
@@ -639,13 +651,31 @@ __global__ void __launch_bounds__(ColGeo<NA>::NTH) k_col(const DevPlan* __restri
         return sinc_sqrt(P.kap2 * k2) * P.scale;
       }
     };
-    auto shift = [&](const XBin& x, int axis, int m) -> float2 {
-      const int a = t + TC * m;
-      return along_y ? axis_shift<FAM == F_ABS ? F_A : FAM>(P, x, axis, a, -1)
-                     : axis_shift<FAM == F_ABS ? F_A : FAM>(P, x, axis, kyf, a);
+    // shift factors of derivative axis `axis` for the E elements of this
+    // thread (the x shift is per column, the others per element or per block)
+    auto shifts = [&](int axis, float2 (&sh)[E], float2 (&shN)[E]) {
+      constexpr int SF = (FAM == F_ABS) ? F_A : FAM;
+      if (axis == 0) {
+        const float2 s0 = (SF == F_A) ? xb.sa : xb.sb, s1 = (SF == F_A) ? xbN.sa : xbN.sb;
+#pragma unroll
+        for (int m = 0; m < E; ++m) {
+          sh[m] = s0;
+          shN[m] = s1;
+        }
+      } else if (axis == 1 && !along_y) {
+        const float2 s0 = (SF == F_A) ? P.shA[1][kyf] : P.shB[1][kyf];
+#pragma unroll
+        for (int m = 0; m < E; ++m) sh[m] = shN[m] = s0;
+      } else {
+        const float2* tab = (SF == F_A) ? P.shA[axis] : P.shB[axis];
+#pragma unroll
+        for (int m = 0; m < E; ++m) sh[m] = shN[m] = tab[t + TC * m];
+      }
     };
     // acc += mult(kind/axis) * spectrum for one field
     auto apply = [&](int which, const float2 (&v)[E], const float2 (&vm)[E], float2 (&acc)[E]) {
+      float2 sh[E], shN[E];
+      if constexpr (FAM != F_ABS) shifts(which, sh, shN);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         float2 mv, mN;
@@ -653,14 +683,14 @@ __global__ void __launch_bounds__(ColGeo<NA>::NTH) k_col(const DevPlan* __restri
         if constexpr (FAM == F_ABS) {
           mv = f2(g, 0.f);
         } else {
-          mv = scl2(g, shift(xb, which, m));
+          mv = scl2(g, sh[m]);
         }
         if (col0 && selfpair) {
           const float gN = factor(k2fixN + k2v[m], which);
           if constexpr (FAM == F_ABS) {
             mN = f2(gN, 0.f);
           } else {
-            mN = scl2(gN, shift(xbN, which, m));
+            mN = scl2(gN, shN[m]);
           }
           acc[m] = acc[m] + cmul(0.5f * (mv + mN), v[m]) + cmul(0.5f * (mv - mN), vm[m]);
         } else {
@@ -689,7 +719,7 @@ __global__ void __launch_bounds__(ColGeo<NA>::NTH) k_col(const DevPlan* __restri
     } else if constexpr (MODE == 1) {
       const int i = (int)blockIdx.y;
       const int f = spec.f0 + i;
-      load(P.S[f], v);
+      load(P.S[spec.src >= 0 ? spec.src : f], v);
       fft<NA, E, -1>(v, Lc, t, tws);
       if (special) mirror(v, vm);
 #pragma unroll
@@ -753,7 +783,9 @@ static hipError_t launch_row_nd(RowKind kind, const Launch& L, StepArg s) {
   const bool per_axis = (kind == R_FWD_1 || kind == R_ADJ_1);
   const dim3 grid(L.nblocks, per_axis ? D : 1), block(RowGeo<N>::NTH);
 #define PAT_ROW_CASE(KK) \
-  case KK: hipLaunchKernelGGL((k_row<N, D, KK>), grid, block, 0, L.stream, L.plans, L.table, s); break;
+  case KK:                                                                                        \
+    hipExtLaunchKernelGGL((k_row<N, D, KK>), grid, block, 0, L.stream, L.ev0, L.ev1, 0, L.plans, L.table, s); \
+    break;
   switch (kind) {
     PAT_ROW_CASE(R_FWD_INIT)
     PAT_ROW_CASE(R_FWD_1)
@@ -837,7 +869,8 @@ static hipError_t launch_col_n(const ColSpec& spec, const Launch& L) {
   else
     fam = (spec.mult[0] >= M_BX) ? F_B : F_A;
 #define PAT_COL(MODE, NF, FAMV, GRID) \
-  hipLaunchKernelGGL((k_col<NA, MODE, NF, FAMV>), GRID, block, 0, L.stream, L.plans, L.table, spec)
+  hipExtLaunchKernelGGL((k_col<NA, MODE, NF, FAMV>), GRID, block, 0, L.stream, L.ev0, L.ev1, 0, L.plans, L.table, \
+                        spec)
 #define PAT_COL_FAM(MODE, NF, GRID)              \
   do {                                           \
     if (fam == F_A) PAT_COL(MODE, NF, F_A, GRID);     \

@@ -58,6 +58,9 @@ struct DevPlan {
   float ym2h, ym1h;  // (y - 2)/2 and (y - 1)/2: |k|^(y-2) = (|k|^2)^ym2h
   float inv_dt;
   float scale;       // 1 / (nx ny nz): normalisation of a forward+inverse pair
+  // spatially uniform alpha0: c0^2 tau = ktau (c0^2)^etau, c0^2 eta = keta (c0^2)^eeta
+  int32_t alpha_uniform;
+  float ktau, etau, keta, eeta;
 
   // medium coefficients (N each)
   const float* B[3];     // dt / rho0 at the staggered points of each axis
@@ -119,6 +122,8 @@ struct Launch {
   const int2* table;     // device work table (instance, tile) or nullptr
   int32_t nblocks;
   hipStream_t stream;
+  hipEvent_t ev0 = nullptr;  // optional: stamped at the kernel's start and end
+  hipEvent_t ev1 = nullptr;
 };
 
 enum RowKind : int32_t {
@@ -144,7 +149,8 @@ int row_tile_rows(int nx);
 // transform, k-space multiplier(s), inverse transform.  Modes 3-4 are the
 // forward / inverse transform along y alone (3D).
 // mode 0: S[1+i] = mult[i] S[0]                    (i < nfield)
-// mode 1: S[f]   = mult[i] S[f],  f = f0 + i       (blockIdx.y = i)
+// mode 1: S[f]   = mult[i] S[f],  f = f0 + i       (blockIdx.y = i; with
+//         src >= 0 the input is S[src] for every i)
 // mode 2: S[0]   = sum_i mult[i] S[f0 + i]
 // mode 3/4: S[f0 + i] <- F_y / F_y^-1 S[f0 + i]    (blockIdx.y = i)
 struct ColSpec {
@@ -152,6 +158,7 @@ struct ColSpec {
   int32_t nfield;
   int32_t mult[3];
   int32_t f0;
+  int32_t src = -1;  // mode 1: read S[src] instead of S[f] (one input, several outputs)
 };
 hipError_t launch_col(const ColSpec& spec, int ndim, int nx, int ny, int nz, const Launch& L);
 int col_tiles(int ndim, int nx, int ny, int nz);

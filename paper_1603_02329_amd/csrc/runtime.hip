@@ -359,6 +359,21 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
   h.ym2h = (float)((y - 2.0) / 2.0);
   h.ym1h = (float)((y - 1.0) / 2.0);
   h.inv_dt = (float)(1.0 / dt);
+  // uniform absorption coefficient: the state passes form c0^2 tau and
+  // c0^2 eta from c0^2 instead of reading them
+  h.alpha_uniform = 0;
+  if (lossy) {
+    bool uni = true;
+    for (int64_t i = 1; i < N && uni; ++i) uni = (a0db[i] == a0db[0]);
+    if (uni) {
+      const double a0 = (double)a0db[0] * a_conv;
+      h.alpha_uniform = 1;
+      h.ktau = (float)(-2.0 * a0);             // c0^2 tau = -2 a0 c0^(y+1)
+      h.etau = (float)((y + 1.0) / 2.0);
+      h.keta = (float)(2.0 * a0 * tan_y);      // c0^2 eta = 2 a0 tan(pi y/2) c0^(y+2)
+      h.eeta = (float)((y + 2.0) / 2.0);
+    }
+  }
   h.scale = (float)(1.0 / (double)N);
   for (int j = 0; j < nd; ++j) {
     h.B[j] = (const float*)(A + oB[j]);
