@@ -45,8 +45,8 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-KERNEL_SOURCES = ("paper_1603_02329_amd/csrc/passes.hip", "paper_1603_02329_amd/csrc/fft.h",
-                  "paper_1603_02329_amd/csrc/pat_internal.h")
+KERNEL_SOURCES = ("paper_1603_02329_amd/csrc/passes_row.hip", "paper_1603_02329_amd/csrc/passes_common.h",
+                  "paper_1603_02329_amd/csrc/fft.h", "paper_1603_02329_amd/csrc/pat_internal.h")
 
 
 def kernel_source_hash() -> str:
@@ -114,6 +114,7 @@ def main():
     ap.add_argument("--chunk", type=int, default=32, help="graph chunk (steps per captured graph; 1 = eager)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default column tile widths")
     ap.add_argument("--time-pass", default="0:1", help="direction:pass_index timed with HIP events")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="counter probe: a 256 MiB device copy (calibration) and one eager batched "
@@ -155,6 +156,14 @@ def main():
         return
     batch = pat.Batch(plans, chunk=args.chunk)
     targets = [d.clone() for d in batch.forward(x_true)]
+    tiles = []
+    if not args.no_autotune:
+        # untimed: pick the column tile widths on the batch's own buffers
+        # (the targets are already copied out)
+        t0 = time.perf_counter()
+        tiles = batch.autotune(reps=10)
+        log(f"autotune: {len(tiles)} passes in {time.perf_counter() - t0:.1f} s: " +
+            ", ".join(f"{e['n'][0]}:{e['dir']}:{e['pass']}->{e['tile']}" for e in tiles))
     xs = [0.5 * x for x in x_true]
     total_gps = sum(2.0 * p.npoints * p.nt for p in plans)
     tvw = [torch.empty(max(1, pat.lib().pat_tv_prox_work_bytes(2, pat._i32x3(list(reversed(x.shape))))),
@@ -206,6 +215,8 @@ def main():
         # graph-captured launches are not event-timed: time the same pass
         # over the same batch with an eager (chunk 1) batch right after
         b1 = pat.Batch(plans, chunk=1)
+        for e in tiles:
+            b1.set_tile(e)
         pat.timing_begin(tdir, tidx, nx_dom)
         step(b1.forward, b1.adjoint)
         torch.cuda.synchronize()
@@ -241,6 +252,7 @@ def main():
             "instances": len(plans),
             "gps_per_step": total_gps,
             "executor": f"batched, graph chunk {args.chunk}",
+            "col_tiles": {f"{e['n'][0]}x{e['n'][1]}x{e['n'][2]}:{e['dir']}:{e['pass']}": e["tile"] for e in tiles},
             "plain_ms_per_step": plain_ms,
             "batched_over_plain": (plain_ms / ms) if plain_ms else None,
         },

@@ -9,6 +9,7 @@ no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 from typing import Optional, Sequence
 
@@ -29,7 +30,7 @@ EXPORTED = [
     "pat_forward_range", "pat_batch_create", "pat_batch_destroy", "pat_batch_forward",
     "pat_batch_adjoint", "pat_tv_prox_work_bytes", "pat_tv_prox", "pat_restrict", "pat_prolong",
     "pat_dot_f64", "pat_residual_f64", "pat_plan_sync", "pat_strerror", "pat_timing_begin",
-    "pat_timing_end",
+    "pat_timing_end", "pat_batch_autotune", "pat_tuning_report", "pat_batch_set_tile",
 ]
 
 
@@ -91,6 +92,9 @@ def lib() -> ctypes.CDLL:
         "pat_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "pat_timing_begin": (ctypes.c_int, [i32, i32, i32]),
         "pat_timing_end": (ctypes.c_int, [ctypes.POINTER(f64), ctypes.POINTER(i64), ctypes.POINTER(f64)]),
+        "pat_batch_autotune": (ctypes.c_int, [vp, i32, vp]),
+        "pat_tuning_report": (ctypes.c_int, [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)]),
+        "pat_batch_set_tile": (ctypes.c_int, [vp, ctypes.POINTER(i32), i32, i32, i32, i32, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -287,6 +291,88 @@ class Batch:
         b = (ctypes.c_void_p * len(self.plans))(*[_dev_f32(x, "img", p.npoints).value for p, x in zip(self.plans, imgs)])
         _check(lib().pat_batch_adjoint(self._h, a, b, _stream()), "pat_batch_adjoint")
         return imgs
+
+    def tuning_report(self) -> list:
+        """The autotuner's choices (list of dicts, see pat_tuning_report)."""
+        need = ctypes.c_size_t()
+        _check(lib().pat_tuning_report(self._h, None, 0, ctypes.byref(need)), "pat_tuning_report")
+        buf = ctypes.create_string_buffer(need.value + 1)
+        _check(lib().pat_tuning_report(self._h, buf, need.value + 1, ctypes.byref(need)), "pat_tuning_report")
+        return json.loads(buf.value.decode())
+
+    def set_tile(self, entry: dict, tile: Optional[int] = None) -> None:
+        """Apply one stored choice: a report entry (keys n, nt, lossy, dir,
+        pass, tile); ``tile`` overrides the entry's width."""
+        t = entry["tile"] if tile is None else tile
+        _check(lib().pat_batch_set_tile(self._h, _i32x3(list(entry["n"])), int(entry["nt"]), int(entry["lossy"]),
+                                        int(entry["dir"]), int(entry["pass"]), int(t)), "pat_batch_set_tile")
+
+    def autotune(self, reps: int = 20, cache: Optional[str] = None) -> list:
+        """Pick the column tile widths by timing (pat_batch_autotune).
+
+        With ``cache`` (a JSON file), choices stored there for this device
+        architecture and every class of the batch are applied without timing;
+        otherwise the batch is timed and its report merged into the file.
+        Returns the report entries in force."""
+        arch = _arch()
+        entries = None
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                stored = json.load(f).get(arch, {})
+            entries = []
+            for key in self._class_keys():
+                if key not in stored:
+                    entries = None
+                    break
+                entries += stored[key]
+        if entries is not None:
+            for e in entries:
+                self.set_tile(e)
+            return entries
+        _check(lib().pat_batch_autotune(self._h, int(reps), _stream()), "pat_batch_autotune")
+        rep = self.tuning_report()
+        if cache:
+            data = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    data = json.load(f)
+            by = data.setdefault(arch, {})
+            for key in self._class_keys():
+                by[key] = [e for e in rep if self._entry_key(e) == key]
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(data, f, indent=1)
+            os.replace(tmp, cache)
+        return rep
+
+    def _key(self, n, nt, lossy) -> str:
+        """Cache key of one size class: grid, time samples, physics, and how
+        many instances of it the batch holds (the timing depends on it)."""
+        n = [int(v) for v in n]
+        count = sum(1 for p in self.plans if _grid3(p) == n and p.nt == nt and p.lossy == bool(lossy))
+        return f"{n[0]}x{n[1]}x{n[2]}/nt{nt}/{'lossy' if lossy else 'lossless'}/i{count}"
+
+    def _class_keys(self) -> list:
+        keys = []
+        for p in self.plans:
+            k = self._key(_grid3(p), p.nt, p.lossy)
+            if k not in keys:
+                keys.append(k)
+        return keys
+
+    def _entry_key(self, e) -> str:
+        return self._key(e["n"], e["nt"], e["lossy"])
+
+
+def _grid3(plan) -> list:
+    """(nx, ny, nz) of a plan, nz = 1 in 2D."""
+    n = list(reversed(plan.shape))
+    return n + [1] * (3 - len(n))
+
+
+def _arch() -> str:
+    torch = _torch()
+    return str(torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName).split(":")[0]
 
 
 def timing_begin(direction: int, pass_index: int, nx: int = 0) -> None:

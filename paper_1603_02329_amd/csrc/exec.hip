@@ -5,10 +5,13 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -150,26 +153,44 @@ __global__ void k_add_ctr(int32_t* c, int v) { *c += v; }
 
 // ------------------------------------------------------------------ runner
 // Launch geometry of one group of same-shape instances (one, for eager).
+constexpr int kColW = 4;  // column tile widths a batch holds work tables for
+
 struct Runner {
   int ndim, nx, ny, nz, nt, lossy;
   const DevPlan* recs;
-  const int2 *row_tab, *col_tab, *red_tab;
-  int row_n, col_n, red_n;
-  double points;  // grid points covered by one launch (all instances)
+  const int2 *row_tab, *red_tab;
+  int row_n, red_n;
+  // column work tables, one per tile width (none for eager: the block index
+  // is the tile of instance 0)
+  const int2* col_tabs[kColW];
+  int col_ns[kColW], col_ws[kColW], col_bpi[kColW], ncolw;
+  const int* tiles;  // chosen tile width of pass [dir * kMaxOps + idx] (0: default)
+  double points;     // grid points covered by one launch (all instances)
 
   int op(int dir, int idx, const PassOp& o, StepArg sa, hipStream_t st, bool timed) const {
     if (timed) {
       const TimeScope ts(dir, idx, nx, pass_bytes_per_point(o, ndim, lossy) * points);
-      return launch1(o, sa, st, ts.e0, ts.e1);
+      return launch1(dir, idx, o, sa, st, ts.e0, ts.e1);
     }
-    return launch1(o, sa, st, nullptr, nullptr);
+    return launch1(dir, idx, o, sa, st, nullptr, nullptr);
   }
-  int launch1(const PassOp& o, StepArg sa, hipStream_t st, hipEvent_t e0, hipEvent_t e1) const {
+  int launch_col_w(ColSpec s, int w, hipStream_t st, hipEvent_t e0, hipEvent_t e1) const {
+    s.tile = w;
+    w = col_tile_of(s, ndim, ny, nz);
+    s.tile = w;
+    const int2* tab = nullptr;
+    int n = col_blocks(s, ndim, nx, ny, nz);
+    for (int j = 0; j < ncolw; ++j)
+      if (col_ws[j] == w && col_bpi[j] == n) tab = col_tabs[j], n = col_ns[j];
+    if (ncolw && !tab) return PAT_EHIP;
+    return launch_col(s, ndim, nx, ny, nz, Launch{recs, tab, n, st, e0, e1}) == hipSuccess ? PAT_OK : PAT_EHIP;
+  }
+  int launch1(int dir, int idx, const PassOp& o, StepArg sa, hipStream_t st, hipEvent_t e0, hipEvent_t e1) const {
+    if (o.is_col) return launch_col_w(o.col, tiles ? tiles[dir * kMaxOps + idx] : 0, st, e0, e1);
     hipError_t e;
-    if (o.is_col)
-      e = launch_col(o.col, ndim, nx, ny, nz, Launch{recs, col_tab, col_n, st, e0, e1});
-    else
+    {
       e = launch_row(o.row, ndim, nx, Launch{recs, row_tab, row_n, st, e0, e1}, sa);
+    }
     return e == hipSuccess ? PAT_OK : PAT_EHIP;
   }
   int row(RowKind k, StepArg sa, hipStream_t st) const {
@@ -198,11 +219,12 @@ Runner eager_runner(const pat_plan* p) {
   r.nt = p->desc.nt;
   r.lossy = p->lossy;
   r.recs = p->dp;
-  r.row_tab = r.col_tab = r.red_tab = nullptr;
+  r.row_tab = r.red_tab = nullptr;
   const int R = row_tile_rows(r.nx);
   r.row_n = (p->hp.nrows + R - 1) / R;
-  r.col_n = col_tiles(r.ndim, r.nx, r.ny, r.nz);
   r.red_n = 0;
+  r.ncolw = 0;
+  r.tiles = nullptr;
   r.points = (double)p->npoints;
   return r;
 }
@@ -311,9 +333,17 @@ struct BatchClass {
   std::vector<int> index;  // position of each plan in the caller's list
   DevPlan* recs = nullptr;
   int2* row_tab = nullptr;
-  int2* col_tab = nullptr;
   int2* red_tab = nullptr;
-  int row_n = 0, col_n = 0, red_n = 0;
+  int row_n = 0, red_n = 0;
+  int2* col_tabs[kColW] = {};
+  int col_ns[kColW] = {}, col_ws[kColW] = {}, col_bpi[kColW] = {}, ncolw = 0;
+  int tiles[2 * kMaxOps] = {};
+  // autotuner record: candidate widths and their mean durations per pass
+  struct Tuned {
+    int dir, idx, ncand, cand[kColW];
+    float us[kColW];
+  };
+  std::vector<Tuned> tuned;
   int32_t* ctr = nullptr;
   hipStream_t st = nullptr;
   hipEvent_t done = nullptr;
@@ -328,11 +358,17 @@ struct BatchClass {
     r.lossy = lossy;
     r.recs = recs;
     r.row_tab = row_tab;
-    r.col_tab = col_tab;
     r.red_tab = red_tab;
     r.row_n = row_n;
-    r.col_n = col_n;
     r.red_n = red_n;
+    r.ncolw = ncolw;
+    for (int j = 0; j < kColW; ++j) {
+      r.col_tabs[j] = col_tabs[j];
+      r.col_ns[j] = col_ns[j];
+      r.col_ws[j] = col_ws[j];
+      r.col_bpi[j] = col_bpi[j];
+    }
+    r.tiles = tiles;
     double pts = 0;
     for (auto* p : plans) pts += (double)p->npoints;
     r.points = pts;
@@ -512,15 +548,38 @@ extern "C" int pat_batch_create(pat_batch** out, pat_plan* const* plans, int32_t
     return at;
   };
   struct Lay {
-    size_t rec, row, col, red, ctr;
+    size_t rec, row, col[kColW], red, ctr;
   };
   std::vector<Lay> lay;
-  std::vector<std::vector<int2>> rt(b->cls.size()), ct(b->cls.size()), dt(b->cls.size());
+  std::vector<std::vector<int2>> rt(b->cls.size()), dt(b->cls.size());
+  std::vector<std::vector<std::vector<int2>>> ct(b->cls.size(), std::vector<std::vector<int2>>(kColW));
   for (size_t k = 0; k < b->cls.size(); ++k) {
     BatchClass& c = b->cls[k];
     const int R = row_tile_rows(c.nx);
     const int rows_per = (c.ny * c.nz + R - 1) / R;
-    const int cols_per = col_tiles(c.ndim, c.nx, c.ny, c.nz);
+    // every tile width some column pass of the class can run with; a y-axis
+    // and a z-axis pass of one width tile the same number of columns only
+    // when ny == nz, so the table is per (width, axis)
+    std::vector<std::pair<int, int>> widths;  // (width, blocks per instance)
+    for (int dir = 0; dir < 2; ++dir) {
+      PassOp ops[kMaxOps];
+      const int nops = step_ops(dir, c.ndim, c.lossy, ops);
+      for (int i = 0; i < nops; ++i) {
+        if (!ops[i].is_col) continue;
+        int cand[kColW];
+        const int nc = col_tile_candidates(col_axis_len(ops[i].col, c.ndim, c.ny, c.nz), ops[i].col.mode, ops[i].col.nfield, cand);
+        for (int j = 0; j < nc; ++j) {
+          ColSpec s = ops[i].col;
+          s.tile = cand[j];
+          const std::pair<int, int> wb(cand[j], col_blocks(s, c.ndim, c.nx, c.ny, c.nz));
+          if (std::find(widths.begin(), widths.end(), wb) == widths.end()) widths.push_back(wb);
+        }
+      }
+    }
+    if ((int)widths.size() > kColW) {
+      destroy_batch(b);
+      return PAT_EINVAL;
+    }
     // XCD-aware order: workgroups are dispatched round-robin over the eight
     // XCDs (each with its own L2), so entry e runs on XCD e mod 8.  Entries
     // interleave the instances of each group of eight, so that every pass of
@@ -535,18 +594,23 @@ extern "C" int pat_batch_create(pat_batch** out, pat_plan* const* plans, int32_t
       }
     };
     interleave(rt[k], rows_per);
-    interleave(ct[k], cols_per);
+    c.ncolw = (int)widths.size();
+    for (int j = 0; j < c.ncolw; ++j) {
+      interleave(ct[k][j], widths[j].second);
+      c.col_ws[j] = widths[j].first;
+      c.col_bpi[j] = widths[j].second;
+      c.col_ns[j] = (int)ct[k][j].size();
+    }
     for (int i = 0; i < ninst; ++i) {
       const int rb = reduce_blocks(c.nt, c.plans[i]->desc.n_sensors);
       for (int t = 0; t < rb; ++t) dt[k].push_back(make_int2(i, t));
     }
     c.row_n = (int)rt[k].size();
-    c.col_n = (int)ct[k].size();
     c.red_n = (int)dt[k].size();
     Lay l;
     l.rec = take(sizeof(DevPlan) * c.plans.size());
     l.row = take(sizeof(int2) * rt[k].size());
-    l.col = take(sizeof(int2) * ct[k].size());
+    for (int j = 0; j < c.ncolw; ++j) l.col[j] = take(sizeof(int2) * ct[k][j].size());
     l.red = take(sizeof(int2) * dt[k].size());
     l.ctr = take(sizeof(int32_t));
     lay.push_back(l);
@@ -561,16 +625,20 @@ extern "C" int pat_batch_create(pat_batch** out, pat_plan* const* plans, int32_t
     BatchClass& c = b->cls[k];
     c.recs = (DevPlan*)(A + lay[k].rec);
     c.row_tab = (int2*)(A + lay[k].row);
-    c.col_tab = (int2*)(A + lay[k].col);
     c.red_tab = (int2*)(A + lay[k].red);
     c.ctr = (int32_t*)(A + lay[k].ctr);
     std::vector<DevPlan> recs;
     for (auto* p : c.plans) recs.push_back(p->hp);
     if (hipMemcpy(c.recs, recs.data(), sizeof(DevPlan) * recs.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c.row_tab, rt[k].data(), sizeof(int2) * rt[k].size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c.col_tab, ct[k].data(), sizeof(int2) * ct[k].size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(c.red_tab, dt[k].data(), sizeof(int2) * dt[k].size(), hipMemcpyHostToDevice) != hipSuccess)
       rc = PAT_EHIP;
+    for (int j = 0; j < c.ncolw && !rc; ++j) {
+      c.col_tabs[j] = (int2*)(A + lay[k].col[j]);
+      if (hipMemcpy(c.col_tabs[j], ct[k][j].data(), sizeof(int2) * ct[k][j].size(), hipMemcpyHostToDevice) !=
+          hipSuccess)
+        rc = PAT_EHIP;
+    }
     if (!rc && (hipStreamCreateWithFlags(&c.st, hipStreamNonBlocking) != hipSuccess ||
                 hipEventCreateWithFlags(&c.done, hipEventDisableTiming) != hipSuccess))
       rc = PAT_EHIP;
@@ -594,4 +662,131 @@ extern "C" int pat_batch_forward(pat_batch* b, const float* const* p0, float* co
 
 extern "C" int pat_batch_adjoint(pat_batch* b, const float* const* data, float* const* img, void* stream) {
   return batch_run(b, 1, data, img, (hipStream_t)stream);
+}
+
+// ===================================================================== column tile autotuner
+// For every column pass of every class that has more than one instantiated
+// tile width, each candidate is launched `reps` times over the class's own
+// buffers (after one untimed launch) and timed with a pair of events; the
+// fastest mean is kept.  The passes run on whatever the state buffers hold:
+// their duration does not depend on the values, and every forward and
+// adjoint run rewrites the state from its input before reading it.  Captured
+// graphs are dropped so that the next run captures the chosen widths.
+extern "C" int pat_batch_autotune(pat_batch* b, int32_t reps, void* stream) {
+  if (!b || reps < 1) return PAT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (hipStreamSynchronize(st) != hipSuccess) return PAT_EHIP;
+  for (auto& c : b->cls)
+    if (hipStreamSynchronize(c.st) != hipSuccess) return PAT_EHIP;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) hipEventDestroy(e0);
+    return PAT_EHIP;
+  }
+  int rc = PAT_OK;
+  for (auto& c : b->cls) {
+    c.tuned.clear();
+    for (int dir = 0; dir < 2 && !rc; ++dir) {
+      PassOp ops[kMaxOps];
+      const int nops = step_ops(dir, c.ndim, c.lossy, ops);
+      for (int i = 0; i < nops && !rc; ++i) {
+        if (!ops[i].is_col) continue;
+        BatchClass::Tuned t{};
+        t.dir = dir;
+        t.idx = i;
+        t.ncand = col_tile_candidates(col_axis_len(ops[i].col, c.ndim, c.ny, c.nz), ops[i].col.mode, ops[i].col.nfield, t.cand);
+        if (t.ncand < 2) continue;
+        const Runner R = c.runner();
+        int best = 0;
+        for (int j = 0; j < t.ncand && !rc; ++j) {
+          rc = R.launch_col_w(ops[i].col, t.cand[j], st, nullptr, nullptr);
+          if (!rc && hipEventRecord(e0, st) != hipSuccess) rc = PAT_EHIP;
+          for (int r = 0; r < reps && !rc; ++r) rc = R.launch_col_w(ops[i].col, t.cand[j], st, nullptr, nullptr);
+          if (!rc && hipEventRecord(e1, st) != hipSuccess) rc = PAT_EHIP;
+          float ms = 0;
+          if (!rc && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = PAT_EHIP;
+          t.us[j] = 1e3f * ms / (float)reps;
+          if (t.us[j] < t.us[best]) best = j;
+        }
+        if (rc) break;
+        c.tiles[dir * kMaxOps + i] = t.cand[best];
+        c.tuned.push_back(t);
+      }
+    }
+    for (auto& g : c.graph)
+      if (g) {
+        hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+    if (rc) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return rc;
+}
+
+// JSON list of the chosen widths: one object per tuned pass with the class
+// shape, direction, pass index, mode, field count, axis length, candidates
+// with their mean microseconds and the choice.  Writes at most cap bytes
+// (NUL-terminated) and the full length (without the NUL) to *needed.
+extern "C" int pat_tuning_report(const pat_batch* b, char* buf, size_t cap, size_t* needed) {
+  if (!b || !needed || (cap && !buf)) return PAT_EINVAL;
+  std::string s = "[";
+  char tmp[256];
+  bool firsto = true;
+  for (const auto& c : b->cls) {
+    for (const auto& t : c.tuned) {
+      PassOp ops[kMaxOps];
+      step_ops(t.dir, c.ndim, c.lossy, ops);
+      const ColSpec& cs = ops[t.idx].col;
+      std::snprintf(tmp, sizeof tmp,
+                    "%s{\"n\":[%d,%d,%d],\"nt\":%d,\"lossy\":%d,\"instances\":%d,\"dir\":%d,\"pass\":%d,"
+                    "\"mode\":%d,\"nfield\":%d,\"axis_len\":%d,\"candidates\":[",
+                    firsto ? "" : ",", c.nx, c.ny, c.nz, c.nt, c.lossy, (int)c.plans.size(), t.dir, t.idx, cs.mode,
+                    cs.nfield, col_axis_len(cs, c.ndim, c.ny, c.nz));
+      s += tmp;
+      firsto = false;
+      for (int j = 0; j < t.ncand; ++j) {
+        std::snprintf(tmp, sizeof tmp, "%s{\"tile\":%d,\"us\":%.3f}", j ? "," : "", t.cand[j], (double)t.us[j]);
+        s += tmp;
+      }
+      std::snprintf(tmp, sizeof tmp, "],\"tile\":%d}", c.tiles[t.dir * kMaxOps + t.idx]);
+      s += tmp;
+    }
+  }
+  s += "]";
+  *needed = s.size();
+  if (cap) {
+    const size_t n = std::min(cap - 1, s.size());
+    std::memcpy(buf, s.data(), n);
+    buf[n] = 0;
+  }
+  return PAT_OK;
+}
+
+extern "C" int pat_batch_set_tile(pat_batch* b, const int32_t n[3], int32_t nt, int32_t lossy, int32_t dir,
+                                  int32_t pass, int32_t tile) {
+  if (!b || !n || dir < 0 || dir > 1 || pass < 0 || pass >= kMaxOps || tile < 0) return PAT_EINVAL;
+  bool found = false;
+  for (auto& c : b->cls) {
+    if (c.nx != n[0] || c.ny != n[1] || c.nz != n[2] || c.nt != nt || c.lossy != (lossy != 0)) continue;
+    PassOp ops[kMaxOps];
+    const int nops = step_ops(dir, c.ndim, c.lossy, ops);
+    if (pass >= nops || !ops[pass].is_col) return PAT_EINVAL;
+    if (tile) {
+      int cand[kColW];
+      const int nc = col_tile_candidates(col_axis_len(ops[pass].col, c.ndim, c.ny, c.nz), ops[pass].col.mode, ops[pass].col.nfield, cand);
+      if (std::find(cand, cand + nc, tile) == cand + nc) return PAT_EINVAL;
+    }
+    if (hipStreamSynchronize(c.st) != hipSuccess) return PAT_EHIP;
+    c.tiles[dir * kMaxOps + pass] = tile;
+    for (auto& g : c.graph)
+      if (g) {
+        hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+    found = true;
+  }
+  return found ? PAT_OK : PAT_EINVAL;
 }

@@ -159,9 +159,13 @@ struct ColSpec {
   int32_t mult[3];
   int32_t f0;
   int32_t src = -1;  // mode 1: read S[src] instead of S[f] (one input, several outputs)
+  int32_t tile = 0;  // columns per block (0: the default)
 };
 hipError_t launch_col(const ColSpec& spec, int ndim, int nx, int ny, int nz, const Launch& L);
-int col_tiles(int ndim, int nx, int ny, int nz);
+int col_blocks(const ColSpec& spec, int ndim, int nx, int ny, int nz);
+int col_tile_of(const ColSpec& spec, int ndim, int ny, int nz);
+int col_tile_candidates(int na, int mode, int nfield, int* out);
+int col_axis_len(const ColSpec& spec, int ndim, int ny, int nz);
 
 hipError_t launch_reduce(const Launch& L, int n0, int n1);
 

@@ -23,7 +23,8 @@
 #include "pat_internal.h"
 
 namespace pat {
-hipError_t upload_twiddles(const Tw* host);
+hipError_t upload_twiddles_rows(const Tw* host);
+hipError_t upload_twiddles_cols(const Tw* host);
 }
 
 using namespace pat;
@@ -55,7 +56,8 @@ int ensure_twiddles() {
     const float ch = (float)c, sh = (float)s;
     tw[q] = Tw{ch, sh, (float)(c - (double)ch), (float)(s - (double)sh)};
   }
-  if (upload_twiddles(tw.data()) != hipSuccess) return PAT_EHIP;
+  if (upload_twiddles_rows(tw.data()) != hipSuccess || upload_twiddles_cols(tw.data()) != hipSuccess)
+    return PAT_EHIP;
   g_tw_ready[dev] = 1;
   return PAT_OK;
 }

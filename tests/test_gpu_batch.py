@@ -73,3 +73,101 @@ def test_check_finite_flag():
     assert e.value.code == pat.PAT_ENONFINITE
     plan.forward(p0)
     plan.sync()  # flag cleared
+
+
+def _tunable_instances(ndim):
+    """Sizes whose column passes have several compiled tile widths: 2D
+    columns of 128 and 256 points; a 3D grid whose z axis (128) differs from
+    its y axis (32), so y- and z-axis passes need separate tables.  (A batch
+    holds one dimensionality.)"""
+    if ndim == 2:
+        specs = [
+            dict(n=(128, 128), nt=13, ns=6, pml=6, lossy=True),
+            dict(n=(128, 128), nt=13, ns=5, pml=5, lossy=True),
+            dict(n=(64, 256), nt=11, ns=4, pml=4, lossy=False),
+        ]
+    else:
+        specs = [
+            dict(n=(32, 32, 128), nt=7, ns=5, pml=3, lossy=True),
+            dict(n=(32, 32, 128), nt=5, ns=4, pml=3, lossy=False),
+        ]
+    return [synth.small_instance(700 + 10 * ndim + i, **s) for i, s in enumerate(specs)]
+
+
+def _run_tune_case(insts, tune):
+    plans = [pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=DEV) for i in insts]
+    p0 = [torch.from_numpy(i.p0).to(DEV) for i in insts]
+    ref_d = [p.forward(x).clone() for p, x in zip(plans, p0)]
+    rng = np.random.default_rng(5)
+    hs = [torch.from_numpy(rng.standard_normal((i.desc.nt, i.ns)).astype(np.float32)).to(DEV) for i in insts]
+    ref_i = [p.adjoint(h).clone() for p, h in zip(plans, hs)]
+    b = pat.Batch(plans, chunk=4)
+    b.forward(p0)  # captures graphs that the tuning must drop
+    rep = tune(b)
+    for _ in range(2):
+        d = b.forward(p0)
+        im = b.adjoint(hs)
+        torch.cuda.synchronize()
+        for k in range(len(insts)):
+            assert torch.equal(d[k], ref_d[k]), k
+            assert torch.equal(im[k], ref_i[k]), k
+    return b, rep
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_autotune_keeps_results_bitwise(ndim):
+    insts = _tunable_instances(ndim)
+    b, rep = _run_tune_case(insts, lambda b: b.autotune(reps=3))
+    assert rep == b.tuning_report()
+    assert rep, "no pass was tuned"
+    for e in rep:
+        tiles = [c["tile"] for c in e["candidates"]]
+        assert len(tiles) >= 2 and e["tile"] in tiles
+        assert all(c["us"] > 0 for c in e["candidates"])
+        assert e["axis_len"] in (128, 256, 512)
+    if ndim == 3:
+        assert all(e["n"] == [32, 32, 128] and e["mode"] <= 2 for e in rep)
+    b.close()
+
+
+@pytest.mark.parametrize("ndim,tile", [(2, 4), (2, 8), (3, 4), (3, 8)])
+def test_forced_tile_widths_bitwise(ndim, tile):
+    """Every compiled width, forced on every tunable pass, equals eager."""
+    insts = _tunable_instances(ndim)
+
+    def force(b):
+        rep = b.autotune(reps=1)
+        for e in rep:
+            b.set_tile(e, tile)
+        return rep
+    b, _ = _run_tune_case(insts, force)
+    if ndim == 3:
+        b.close()
+        return
+    e = dict(n=[128, 128, 1], nt=13, lossy=1, dir=0, tile=4)
+    with pytest.raises(pat.PatError):
+        b.set_tile(dict(e, **{"pass": 1}))            # pass 1 of the forward is a row pass
+    with pytest.raises(pat.PatError):
+        b.set_tile(dict(e, **{"pass": 0}), 2)         # width 2 is not compiled
+    with pytest.raises(pat.PatError):
+        b.set_tile(dict(e, n=[96, 96, 1], **{"pass": 0}))  # no such class
+    with pytest.raises(pat.PatError):
+        b.set_tile(dict(e, nt=12, **{"pass": 0}))     # no class with that time axis
+    b.set_tile(dict(e, **{"pass": 0}), 0)             # back to the default
+    b.close()
+
+
+def test_autotune_cache_roundtrip(tmp_path):
+    insts = _tunable_instances(2)[:2]
+    cache = str(tmp_path / "tiles.json")
+    b, rep = _run_tune_case(insts, lambda b: b.autotune(reps=2, cache=cache))
+    b.close()
+    import json
+    stored = json.load(open(cache))
+    assert len(stored) == 1
+    (arch, by_key), = stored.items()
+    assert arch.startswith("gfx")
+    b2, rep2 = _run_tune_case(insts, lambda b: b.autotune(reps=2, cache=cache))
+    assert [(e["dir"], e["pass"], e["tile"]) for e in rep2] == [(e["dir"], e["pass"], e["tile"]) for e in rep]
+    assert b2.tuning_report() == []  # applied from the cache, nothing timed
+    b2.close()
