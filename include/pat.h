@@ -187,13 +187,15 @@ int pat_batch_adjoint(pat_batch* batch, const float* const* data, float* const* 
  * Tile-shape autotuner of the batched executor: how many columns of the
  * column FFTs inside the k-space derivative and fractional-Laplacian
  * operators (section Forward Problem, lossless and lossy media) one
- * workgroup transforms.  For every column pass of the batch that has
- * several compiled tile widths (multiplier passes over one or two fields per
- * launch with columns of 128, 256 or 512 points: 16, 8 or 4 columns per
- * workgroup), each width is launched reps times on the batch's own device
- * buffers and timed with HIP events; the fastest is used from then on.
- * Results stay bitwise equal to pat_forward / pat_adjoint: the width only
- * changes how columns are grouped into workgroups.
+ * workgroup transforms, and whether a workgroup takes one or both fields
+ * of a two-field pass.  For every column pass of the batch that has several
+ * compiled variants (multiplier passes over one or two fields per launch
+ * with columns of 128, 256 or 512 points: 16, 8 or 4 columns per
+ * workgroup; 2D passes applying one multiplier per field: one or two fields
+ * per workgroup), each variant is launched reps times on the batch's own
+ * device buffers and timed with HIP events; the fastest is used from then
+ * on.  Results stay bitwise equal to pat_forward / pat_adjoint: a variant
+ * only changes how columns and fields are grouped into workgroups.
  *
  *  pat_batch_autotune  reps >= 1 timed launches per candidate.  Waits for the
  *                      batch and `stream` to be idle, runs on `stream`,
@@ -202,8 +204,9 @@ int pat_batch_adjoint(pat_batch* batch, const float* const* data, float* const* 
  *                      drops its captured graphs (re-captured on next use).
  *  pat_tuning_report   JSON array, one object per tuned pass: class shape
  *                      n, nt, lossy, instances, direction (0 forward, 1 adjoint), pass
- *                      index, mode, nfield, axis_len, candidates [{tile, us}]
- *                      and the chosen tile.  Writes at most cap bytes
+ *                      index, mode, nfield, axis_len, candidates
+ *                      [{tile, fpb, us}] (fpb: fields per workgroup) and the
+ *                      chosen tile and fpb.  Writes at most cap bytes
  *                      including a terminating NUL into buf (buf may be NULL
  *                      when cap is 0) and the full length without the NUL to
  *                      *needed.  Empty array "[]" before any autotune.
@@ -215,12 +218,13 @@ int pat_tuning_report(const pat_batch* batch, char* buf, size_t cap, size_t* nee
  * pat_batch_set_tile  applies a stored choice (as reported above) without
  * timing: every class of grid n (nx, ny, nz; nz = 1 in 2D) with nt time
  * samples and physics `lossy` (0/1), direction dir, pass index `pass`, tile
- * width `tile` (0 restores the default).  Returns PAT_EINVAL when no class
- * matches, the pass is not a column pass or the width is not compiled for
- * it.  Drops the matching classes' captured graphs.
+ * width `tile` and fields per workgroup (tile 0 with 1 restores the
+ * default).  Returns PAT_EINVAL when no class matches, the pass is not a
+ * column pass or the variant is not compiled for it.  Drops the matching
+ * classes' captured graphs.
  */
 int pat_batch_set_tile(pat_batch* batch, const int32_t n[3], int32_t nt, int32_t lossy, int32_t dir, int32_t pass,
-                       int32_t tile);
+                       int32_t tile, int32_t fields_per_block);
 
 /*
  * pat_tv_prox -- the proximal map of equation proxmal for

@@ -94,7 +94,7 @@ def lib() -> ctypes.CDLL:
         "pat_timing_end": (ctypes.c_int, [ctypes.POINTER(f64), ctypes.POINTER(i64), ctypes.POINTER(f64)]),
         "pat_batch_autotune": (ctypes.c_int, [vp, i32, vp]),
         "pat_tuning_report": (ctypes.c_int, [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)]),
-        "pat_batch_set_tile": (ctypes.c_int, [vp, ctypes.POINTER(i32), i32, i32, i32, i32, i32]),
+        "pat_batch_set_tile": (ctypes.c_int, [vp, ctypes.POINTER(i32), i32, i32, i32, i32, i32, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -300,12 +300,14 @@ class Batch:
         _check(lib().pat_tuning_report(self._h, buf, need.value + 1, ctypes.byref(need)), "pat_tuning_report")
         return json.loads(buf.value.decode())
 
-    def set_tile(self, entry: dict, tile: Optional[int] = None) -> None:
+    def set_tile(self, entry: dict, tile: Optional[int] = None, fpb: Optional[int] = None) -> None:
         """Apply one stored choice: a report entry (keys n, nt, lossy, dir,
-        pass, tile); ``tile`` overrides the entry's width."""
+        pass, tile, fpb); ``tile`` / ``fpb`` override the entry's."""
         t = entry["tile"] if tile is None else tile
+        f = entry.get("fpb", 1) if fpb is None else fpb
         _check(lib().pat_batch_set_tile(self._h, _i32x3(list(entry["n"])), int(entry["nt"]), int(entry["lossy"]),
-                                        int(entry["dir"]), int(entry["pass"]), int(t)), "pat_batch_set_tile")
+                                        int(entry["dir"]), int(entry["pass"]), int(t), int(f)),
+               "pat_batch_set_tile")
 
     def autotune(self, reps: int = 20, cache: Optional[str] = None) -> list:
         """Pick the column tile widths by timing (pat_batch_autotune).

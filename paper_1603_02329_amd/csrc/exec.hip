@@ -22,9 +22,9 @@ namespace pat {
 // ------------------------------------------------------------------ pass sequences
 int step_ops(int dir, int ndim, int lossy, PassOp* ops) {
   int n = 0;
-  auto row = [&](RowKind k) { ops[n++] = PassOp{0, k, ColSpec{0, 0, {0, 0, 0}, 0, -1}}; };
+  auto row = [&](RowKind k) { ops[n++] = PassOp{0, k, ColSpec{0, 0, {0, 0, 0}, 0}}; };
   auto col = [&](int mode, int nf, int f0, int a, int b, int c) {
-    ops[n++] = PassOp{1, R_COUNT, ColSpec{mode, nf, {a, b, c}, f0, -1}};
+    ops[n++] = PassOp{1, R_COUNT, ColSpec{mode, nf, {a, b, c}, f0}};
   };
   // spectral operator on fields [f0, f0+nf) along the remaining axes: 2D one
   // column pass; 3D a y-transform pass, the z pass with the multipliers and
@@ -73,7 +73,7 @@ double pass_bytes_per_point(const PassOp& op, int ndim, int lossy) {
   if (op.is_col) {
     const int f = op.col.nfield;
     // packed spectra: 4 bytes per grid point and field
-    if (op.col.mode == 0 || (op.col.mode == 1 && op.col.src >= 0)) return 4.0 * (1 + f);  // algorithmic: input once
+    if (op.col.mode == 0) return 4.0 * (1 + f);  // one input, f outputs
     if (op.col.mode == 2) return 4.0 * (f + 1);
     return 8.0 * f;  // modes 1, 3, 4: each field read and written
   }
@@ -164,7 +164,7 @@ struct Runner {
   // is the tile of instance 0)
   const int2* col_tabs[kColW];
   int col_ns[kColW], col_ws[kColW], col_bpi[kColW], ncolw;
-  const int* tiles;  // chosen tile width of pass [dir * kMaxOps + idx] (0: default)
+  const ColVariant* vars;  // chosen variant of pass [dir * kMaxOps + idx] (tile 0: default)
   double points;     // grid points covered by one launch (all instances)
 
   int op(int dir, int idx, const PassOp& o, StepArg sa, hipStream_t st, bool timed) const {
@@ -174,10 +174,13 @@ struct Runner {
     }
     return launch1(dir, idx, o, sa, st, nullptr, nullptr);
   }
-  int launch_col_w(ColSpec s, int w, hipStream_t st, hipEvent_t e0, hipEvent_t e1) const {
-    s.tile = w;
-    w = col_tile_of(s, ndim, ny, nz);
-    s.tile = w;
+  int launch_col_w(ColSpec s, ColVariant v, hipStream_t st, hipEvent_t e0, hipEvent_t e1) const {
+    s.tile = v.tile;
+    s.fpb = v.fpb;
+    v = col_variant_of(s, ndim, ny, nz);
+    s.tile = v.tile;
+    s.fpb = v.fpb;
+    const int w = v.tile;
     const int2* tab = nullptr;
     int n = col_blocks(s, ndim, nx, ny, nz);
     for (int j = 0; j < ncolw; ++j)
@@ -186,7 +189,7 @@ struct Runner {
     return launch_col(s, ndim, nx, ny, nz, Launch{recs, tab, n, st, e0, e1}) == hipSuccess ? PAT_OK : PAT_EHIP;
   }
   int launch1(int dir, int idx, const PassOp& o, StepArg sa, hipStream_t st, hipEvent_t e0, hipEvent_t e1) const {
-    if (o.is_col) return launch_col_w(o.col, tiles ? tiles[dir * kMaxOps + idx] : 0, st, e0, e1);
+    if (o.is_col) return launch_col_w(o.col, vars ? vars[dir * kMaxOps + idx] : ColVariant{0, 1}, st, e0, e1);
     hipError_t e;
     {
       e = launch_row(o.row, ndim, nx, Launch{recs, row_tab, row_n, st, e0, e1}, sa);
@@ -224,7 +227,7 @@ Runner eager_runner(const pat_plan* p) {
   r.row_n = (p->hp.nrows + R - 1) / R;
   r.red_n = 0;
   r.ncolw = 0;
-  r.tiles = nullptr;
+  r.vars = nullptr;
   r.points = (double)p->npoints;
   return r;
 }
@@ -337,12 +340,16 @@ struct BatchClass {
   int row_n = 0, red_n = 0;
   int2* col_tabs[kColW] = {};
   int col_ns[kColW] = {}, col_ws[kColW] = {}, col_bpi[kColW] = {}, ncolw = 0;
-  int tiles[2 * kMaxOps] = {};
-  // autotuner record: candidate widths and their mean durations per pass
+  ColVariant vars[2 * kMaxOps];
+  // autotuner record: candidate variants and their mean durations per pass
   struct Tuned {
-    int dir, idx, ncand, cand[kColW];
-    float us[kColW];
+    int dir, idx, ncand;
+    ColVariant cand[kMaxColVar];
+    float us[kMaxColVar];
   };
+  BatchClass() {
+    for (auto& v : vars) v = ColVariant{0, 1};
+  }
   std::vector<Tuned> tuned;
   int32_t* ctr = nullptr;
   hipStream_t st = nullptr;
@@ -368,7 +375,7 @@ struct BatchClass {
       r.col_ws[j] = col_ws[j];
       r.col_bpi[j] = col_bpi[j];
     }
-    r.tiles = tiles;
+    r.vars = vars;
     double pts = 0;
     for (auto* p : plans) pts += (double)p->npoints;
     r.points = pts;
@@ -566,12 +573,13 @@ extern "C" int pat_batch_create(pat_batch** out, pat_plan* const* plans, int32_t
       const int nops = step_ops(dir, c.ndim, c.lossy, ops);
       for (int i = 0; i < nops; ++i) {
         if (!ops[i].is_col) continue;
-        int cand[kColW];
-        const int nc = col_tile_candidates(col_axis_len(ops[i].col, c.ndim, c.ny, c.nz), ops[i].col.mode, ops[i].col.nfield, cand);
+        ColVariant cand[kMaxColVar];
+        const int nc = col_variants(ops[i].col, c.ndim, c.ny, c.nz, cand);
         for (int j = 0; j < nc; ++j) {
           ColSpec s = ops[i].col;
-          s.tile = cand[j];
-          const std::pair<int, int> wb(cand[j], col_blocks(s, c.ndim, c.nx, c.ny, c.nz));
+          s.tile = cand[j].tile;
+          s.fpb = cand[j].fpb;
+          const std::pair<int, int> wb(cand[j].tile, col_blocks(s, c.ndim, c.nx, c.ny, c.nz));
           if (std::find(widths.begin(), widths.end(), wb) == widths.end()) widths.push_back(wb);
         }
       }
@@ -694,7 +702,7 @@ extern "C" int pat_batch_autotune(pat_batch* b, int32_t reps, void* stream) {
         BatchClass::Tuned t{};
         t.dir = dir;
         t.idx = i;
-        t.ncand = col_tile_candidates(col_axis_len(ops[i].col, c.ndim, c.ny, c.nz), ops[i].col.mode, ops[i].col.nfield, t.cand);
+        t.ncand = col_variants(ops[i].col, c.ndim, c.ny, c.nz, t.cand);
         if (t.ncand < 2) continue;
         const Runner R = c.runner();
         int best = 0;
@@ -710,7 +718,7 @@ extern "C" int pat_batch_autotune(pat_batch* b, int32_t reps, void* stream) {
           if (t.us[j] < t.us[best]) best = j;
         }
         if (rc) break;
-        c.tiles[dir * kMaxOps + i] = t.cand[best];
+        c.vars[dir * kMaxOps + i] = t.cand[best];
         c.tuned.push_back(t);
       }
     }
@@ -748,10 +756,12 @@ extern "C" int pat_tuning_report(const pat_batch* b, char* buf, size_t cap, size
       s += tmp;
       firsto = false;
       for (int j = 0; j < t.ncand; ++j) {
-        std::snprintf(tmp, sizeof tmp, "%s{\"tile\":%d,\"us\":%.3f}", j ? "," : "", t.cand[j], (double)t.us[j]);
+        std::snprintf(tmp, sizeof tmp, "%s{\"tile\":%d,\"fpb\":%d,\"us\":%.3f}", j ? "," : "", t.cand[j].tile,
+                      t.cand[j].fpb, (double)t.us[j]);
         s += tmp;
       }
-      std::snprintf(tmp, sizeof tmp, "],\"tile\":%d}", c.tiles[t.dir * kMaxOps + t.idx]);
+      const ColVariant& ch = c.vars[t.dir * kMaxOps + t.idx];
+      std::snprintf(tmp, sizeof tmp, "],\"tile\":%d,\"fpb\":%d}", ch.tile, ch.fpb);
       s += tmp;
     }
   }
@@ -766,21 +776,27 @@ extern "C" int pat_tuning_report(const pat_batch* b, char* buf, size_t cap, size
 }
 
 extern "C" int pat_batch_set_tile(pat_batch* b, const int32_t n[3], int32_t nt, int32_t lossy, int32_t dir,
-                                  int32_t pass, int32_t tile) {
-  if (!b || !n || dir < 0 || dir > 1 || pass < 0 || pass >= kMaxOps || tile < 0) return PAT_EINVAL;
+                                  int32_t pass, int32_t tile, int32_t fields_per_block) {
+  if (!b || !n || dir < 0 || dir > 1 || pass < 0 || pass >= kMaxOps || tile < 0 || fields_per_block < 1)
+    return PAT_EINVAL;
   bool found = false;
   for (auto& c : b->cls) {
     if (c.nx != n[0] || c.ny != n[1] || c.nz != n[2] || c.nt != nt || c.lossy != (lossy != 0)) continue;
     PassOp ops[kMaxOps];
     const int nops = step_ops(dir, c.ndim, c.lossy, ops);
     if (pass >= nops || !ops[pass].is_col) return PAT_EINVAL;
+    ColVariant v{tile, fields_per_block};
     if (tile) {
-      int cand[kColW];
-      const int nc = col_tile_candidates(col_axis_len(ops[pass].col, c.ndim, c.ny, c.nz), ops[pass].col.mode, ops[pass].col.nfield, cand);
-      if (std::find(cand, cand + nc, tile) == cand + nc) return PAT_EINVAL;
+      ColVariant cand[kMaxColVar];
+      const int nc = col_variants(ops[pass].col, c.ndim, c.ny, c.nz, cand);
+      bool ok = false;
+      for (int j = 0; j < nc; ++j) ok |= (cand[j].tile == tile && cand[j].fpb == fields_per_block);
+      if (!ok) return PAT_EINVAL;
+    } else if (fields_per_block != 1) {
+      return PAT_EINVAL;
     }
     if (hipStreamSynchronize(c.st) != hipSuccess) return PAT_EHIP;
-    c.tiles[dir * kMaxOps + pass] = tile;
+    c.vars[dir * kMaxOps + pass] = v;
     for (auto& g : c.graph)
       if (g) {
         hipGraphExecDestroy(g);

@@ -133,15 +133,40 @@ struct WaveSync {
   }
 };
 
+// Twiddle layouts of a transform:
+//   TwStrided   one table tw[q] = exp(-2 pi i q / TL), TL = TWS * M; stage
+//               (L, R) reads tw[(i j) TL / (L R)].  Suited to the column
+//               passes, where the lanes of a wavefront share j (broadcast).
+//   TwStaged    per stage (L, R) a table of (R - 1) L entries, entry
+//               [(i - 1) L + j] = exp(-2 pi i (i j) / (L R)), the stages one
+//               after another: lanes with consecutive j read consecutive
+//               entries (no LDS bank conflicts in the row passes, where
+//               consecutive lanes carry consecutive j).
+// Exchange layouts: plain (element a at a) or padded (at a + a / 8): the
+// padded layout spreads the radix-8 write patterns (stride 8 and blocks of 8
+// at stride 64) over all LDS banks; the region then needs M + M / 8 slots.
+enum TwLayout : int { TwStrided = 0, TwStaged = 1 };
+
+__host__ __device__ constexpr int fft_radix(int M, int E, int L) { return (M / L) < E ? (M / L) : E; }
+// offset of stage L's entries in a TwStaged table, and the table's length
+__host__ __device__ constexpr int staged_off(int M, int E, int L) {
+  int off = 0;
+  for (int l = 1; l < L; l *= fft_radix(M, E, l)) off += (fft_radix(M, E, l) - 1) * l;
+  return off;
+}
+__host__ __device__ constexpr int staged_len(int M, int E) { return staged_off(M, E, M); }
+__device__ __forceinline__ constexpr int pad8(int a) { return a + (a >> 3); }
+
 // One Stockham stage of span L (product of the radices already applied).
-// `tw` is the twiddle table of this transform length: tw[q] = exp(-2 pi i q / TL)
-// with TL = TWS * M (TWS = 1 for a table of length M, 2 for length 2M).
-template <int M, int E, int SIGN, int L, class Sync, int TWS>
+// TWS: TwStrided table length TWS * M (1 or 2); PAD: padded exchange layout.
+template <int M, int E, int SIGN, int L, class Sync, int TWS, int LAY = TwStrided, bool PAD = false>
 struct FftStage {
   static constexpr int T = M / E;
-  static constexpr int R = (M / L) < E ? (M / L) : E;
+  static constexpr int R = fft_radix(M, E, L);
   static constexpr int NB = E / R;
   static constexpr bool LAST = (L * R == M);
+
+  __device__ __forceinline__ static int at(int a) { return PAD ? pad8(a) : a; }
 
   __device__ __forceinline__ static void run(float2 (&v)[E], float2* lds, int t, const Tw* tw) {
 #pragma unroll
@@ -153,7 +178,12 @@ struct FftStage {
       for (int i = 0; i < R; ++i) x[i] = v[b + i * NB];
       if constexpr (L > 1) {
 #pragma unroll
-        for (int i = 1; i < R; ++i) x[i] = twmul<SIGN>(x[i], tw[(i * j) * (TWS * M / (L * R))]);
+        for (int i = 1; i < R; ++i) {
+          if constexpr (LAY == TwStaged)
+            x[i] = twmul<SIGN>(x[i], tw[staged_off(M, E, L) + (i - 1) * L + j]);
+          else
+            x[i] = twmul<SIGN>(x[i], tw[(i * j) * (TWS * M / (L * R))]);
+        }
       }
       Dft<R, SIGN>::run(x);
       if constexpr (LAST) {
@@ -162,27 +192,44 @@ struct FftStage {
       } else {
         const int base = (k - j) * R + j;
 #pragma unroll
-        for (int i = 0; i < R; ++i) lds[base + i * L] = x[i];
+        for (int i = 0; i < R; ++i) lds[at(base + i * L)] = x[i];
       }
     }
     if constexpr (!LAST) {
       Sync::sync();
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = lds[t + T * m];
+      for (int m = 0; m < E; ++m) v[m] = lds[at(t + T * m)];
       Sync::sync();
-      FftStage<M, E, SIGN, L * R, Sync, TWS>::run(v, lds, t, tw);
+      FftStage<M, E, SIGN, L * R, Sync, TWS, LAY, PAD>::run(v, lds, t, tw);
     }
   }
 };
 
 // Unnormalised DFT of length M (SIGN = -1 forward, +1 inverse) of the values
 // v[m] = x[t + T m] held by the T threads of one transform; `lds` is that
-// transform's region of M complex values and `tw` a twiddle table of length
-// TWS*M.  With BlockSync every thread of the block must call it.
-template <int M, int E, int SIGN, class Sync = BlockSync, int TWS = 1>
+// transform's region of M complex values (M + M / 8 when PAD) and `tw` its
+// twiddle table in layout LAY.  With BlockSync every thread of the block
+// must call it.
+template <int M, int E, int SIGN, class Sync = BlockSync, int TWS = 1, int LAY = TwStrided, bool PAD = false>
 __device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, int t, const Tw* tw) {
   static_assert((M & (M - 1)) == 0 && M >= E && M <= TWN, "unsupported FFT length");
-  FftStage<M, E, SIGN, 1, Sync, TWS>::run(v, lds, t, tw);
+  FftStage<M, E, SIGN, 1, Sync, TWS, LAY, PAD>::run(v, lds, t, tw);
+}
+
+// Fill a TwStaged table for transforms of length M (E values per thread)
+// from the global length-TWN table; NTH threads of the block take part.
+template <int M, int E, int NTH, int L = 1>
+__device__ __forceinline__ void load_staged_twiddles(Tw* dst, const Tw* __restrict__ g) {
+  constexpr int R = fft_radix(M, E, L);
+  if constexpr (L > 1) {
+    constexpr int OFF = staged_off(M, E, L), STRIDE = TWN / (L * R);
+    static_assert(TWN % (L * R) == 0, "stage longer than the global table");
+    for (int q = threadIdx.x; q < (R - 1) * L; q += NTH) {
+      const int i = q / L + 1, j = q % L;
+      dst[OFF + q] = g[(i * j) * STRIDE];
+    }
+  }
+  if constexpr (L * R < M) load_staged_twiddles<M, E, NTH, L * R>(dst, g);
 }
 
 // Copy the length-TL twiddle table (from the global length-TWN one) into LDS.

@@ -37,14 +37,30 @@ struct RowGeo {
   static constexpr int T = M / E;             // threads per row
   static constexpr int ROWS = (256 / T) < 16 ? (256 / T) : 16;
   static constexpr int NTH = ROWS * T;
+  static constexpr int LDR = M + M / 8;       // LDS slots per row (padded FFT exchange)
+  static constexpr int TWS = staged_len(M, E);  // staged FFT twiddles
 };
+
+// LDS twiddles of a row pass: the untangling factors exp(-2 pi i k / N),
+// k < M, then the staged FFT tables
+template <int N>
+struct RowTw {
+  Tw u[N / 2];
+  Tw s[RowGeo<N>::TWS > 0 ? RowGeo<N>::TWS : 1];
+};
+template <int N>
+__device__ __forceinline__ void load_row_twiddles(RowTw<N>& tw, const Tw* __restrict__ g) {
+  using G = RowGeo<N>;
+  for (int q = threadIdx.x; q < G::M; q += G::NTH) tw.u[q] = g[q * (TWN / N)];
+  load_staged_twiddles<G::M, G::E, G::NTH>(tw.s, g);
+}
 
 // Packed half spectrum of one row -> real row, as pairs (x[2n], x[2n+1]) at
 // n = t + T m.  Unnormalised inverse real DFT.
 // r holds the packed bins X[t + T m] on entry (already loaded) and the real
 // pairs on exit.
 template <int N>
-__device__ __forceinline__ void c2r(float2 (&r)[RowGeo<N>::E], float2* L, int t, const Tw* tw) {
+__device__ __forceinline__ void c2r(float2 (&r)[RowGeo<N>::E], float2* L, int t, const RowTw<N>& tw) {
   using G = RowGeo<N>;
   constexpr int M = G::M, E = G::E, T = G::T;
 #pragma unroll
@@ -59,21 +75,21 @@ __device__ __forceinline__ void c2r(float2 (&r)[RowGeo<N>::E], float2* L, int t,
     } else {
       const float2 Y = conjf2(L[M - k]);
       const float2 A = X + Y;
-      const float2 B = twmul<+1>(X - Y, tw[k]);
+      const float2 B = twmul<+1>(X - Y, tw.u[k]);
       r[m] = A + mul_si<+1>(B);
     }
   }
   WaveSync::sync();
-  fft<M, E, +1, WaveSync, 2>(r, L, t, tw);
+  fft<M, E, +1, WaveSync, 1, TwStaged, true>(r, L, t, tw.s);
 }
 
 // Real row held as pairs (x[2n], x[2n+1]) -> packed half spectrum stored at dst.
 template <int N>
 __device__ __forceinline__ void r2c(float2 (&r)[RowGeo<N>::E], float2* __restrict__ dst, float2* L, int t,
-                                    bool valid, const Tw* tw) {
+                                    bool valid, const RowTw<N>& tw) {
   using G = RowGeo<N>;
   constexpr int M = G::M, E = G::E, T = G::T;
-  fft<M, E, -1, WaveSync, 2>(r, L, t, tw);
+  fft<M, E, -1, WaveSync, 1, TwStaged, true>(r, L, t, tw.s);
 #pragma unroll
   for (int m = 0; m < E; ++m) L[t + T * m] = r[m];
   WaveSync::sync();
@@ -87,10 +103,10 @@ __device__ __forceinline__ void r2c(float2 (&r)[RowGeo<N>::E], float2* __restric
     } else {
       const float2 Y = conjf2(L[M - k]);
       const float2 A = Z + Y;
-      const float2 B = twmul<-1>(Z - Y, tw[k]);
+      const float2 B = twmul<-1>(Z - Y, tw.u[k]);
       X = 0.5f * (A + mul_si<-1>(B));
     }
-    if (valid) dst[k] = X;
+    if (valid) gst(dst, k, X);
   }
   WaveSync::sync();
 }
@@ -101,11 +117,11 @@ __device__ __forceinline__ void gather_row(const DevPlan& P, int n, const float*
   using G = RowGeo<N>;
   WaveSync::sync();
   if (valid) {
-    const int e1 = P.g_ptr[row + 1];
+    const int e1 = gld(P.g_ptr, row + 1);
     float* out = P.partial + (long)n * P.nslots;
-    for (int e = P.g_ptr[row] + t; e < e1; e += G::T) {
-      const GTap tap = P.g_tap[e];
-      out[tap.slot] = fmaf(tap.w0, Lf[tap.x0], tap.w1 * Lf[tap.x0 + 1]);
+    for (int e = gld(P.g_ptr, row) + t; e < e1; e += G::T) {
+      const GTap tap = gld(P.g_tap, e);
+      gst(out, tap.slot, fmaf(tap.w0, Lf[tap.x0], tap.w1 * Lf[tap.x0 + 1]));
     }
   }
   WaveSync::sync();
@@ -117,14 +133,14 @@ __device__ __forceinline__ void scatter_row(const DevPlan& P, int n, float* Lf, 
   using G = RowGeo<N>;
   WaveSync::sync();
   if (valid) {
-    const int g1 = P.s_ptr[row + 1];
+    const int g1 = gld(P.s_ptr, row + 1);
     const float* h = P.in + (long)n * P.ns;
-    for (int g = P.s_ptr[row] + t; g < g1; g += G::T) {
-      const SGroup grp = P.s_grp[g];
+    for (int g = gld(P.s_ptr, row) + t; g < g1; g += G::T) {
+      const SGroup grp = gld(P.s_grp, g);
       float acc = 0.f;
       for (int e = grp.beg; e < grp.end; ++e) {
-        const STap tp = P.s_tap[e];
-        acc = fmaf(tp.w, h[tp.s], acc);
+        const STap tp = gld(P.s_tap, e);
+        acc = fmaf(tp.w, gld(h, tp.s), acc);
       }
       Lf[grp.x] += acc;
     }
@@ -168,7 +184,7 @@ struct RowIo {
   }
   __device__ __forceinline__ void ld(const float2* a, float2 (&v)[E]) const {
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = valid ? a[base + t + T * m] : f2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) v[m] = valid ? gld(a, base + t + T * m) : f2(0.f, 0.f);
   }
   // 1-D x table (PML factor along x), pairs at n = t + T m
   __device__ __forceinline__ void ldx(const float* a, float2 (&v)[E]) const {
@@ -191,9 +207,9 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
                                                         const int2* __restrict__ table, StepArg sa) {
   using G = RowGeo<N>;
   constexpr int M = G::M, E = G::E, T = G::T;
-  __shared__ float2 lds[G::ROWS * M];
-  __shared__ Tw tws[N];
-  load_twiddles<N, G::NTH>(tws, g_tw);
+  __shared__ float2 lds[G::ROWS * G::LDR];
+  __shared__ RowTw<N> tws;
+  load_row_twiddles<N>(tws, g_tw);
   const int2 job = table ? table[blockIdx.x] : make_int2(0, (int)blockIdx.x);
   const DevPlan& P = plans[job.x];
   const int rl = threadIdx.x / T, t = threadIdx.x % T;
@@ -202,17 +218,17 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
   const int rowc = valid ? row : 0;
   const int ny = P.n[1];
   const int yy = rowc % ny, zz = rowc / ny;
-  float2* L = lds + rl * M;
+  float2* L = lds + rl * G::LDR;
   float* Lf = reinterpret_cast<float*>(L);
   const RowIo<N> io{(long)rowc * M, t, valid};
   const int it = step_of(sa);  // forward step n / adjoint iteration i
 
   // per-row PML factors of the y and z axes
-  float qrow[3] = {1.f, P.Q[1][yy], 1.f};
-  float qsrow[3] = {1.f, P.Qsg[1][yy], 1.f};
+  float qrow[3] = {1.f, gld(P.Q[1], yy), 1.f};
+  float qsrow[3] = {1.f, gld(P.Qsg[1], yy), 1.f};
   if constexpr (D == 3) {
-    qrow[2] = P.Q[2][zz];
-    qsrow[2] = P.Qsg[2][zz];
+    qrow[2] = gld(P.Q[2], zz);
+    qsrow[2] = gld(P.Qsg[2], zz);
   }
   auto qpair = [&](int j, const float2& qx) { return j == 0 ? qx : f2(qrow[j], qrow[j]); };
   auto qspair = [&](int j, const float2& qx) { return j == 0 ? qx : f2(qsrow[j], qsrow[j]); };
@@ -473,10 +489,10 @@ __global__ void __launch_bounds__(256) k_reduce(const DevPlan* __restrict__ plan
   const int n = (int)(idx / P.ns);
   const int s = (int)(idx - (long)n * P.ns);
   const float* part = P.partial + (long)n * P.nslots;
-  const int k0 = P.slot_ptr[s], k1 = P.slot_ptr[s + 1];
-  float acc = part[k0];
-  for (int k = k0 + 1; k < k1; ++k) acc += part[k];
-  P.out[idx] = acc;
+  const int k0 = gld(P.slot_ptr, s), k1 = gld(P.slot_ptr, s + 1);
+  float acc = gld(part, k0);
+  for (int k = k0 + 1; k < k1; ++k) acc += gld(part, k);
+  gst(P.out, idx, acc);
 }
 
 // ------------------------------------------------------------------ launchers

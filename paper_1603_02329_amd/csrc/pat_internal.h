@@ -149,8 +149,8 @@ int row_tile_rows(int nx);
 // transform, k-space multiplier(s), inverse transform.  Modes 3-4 are the
 // forward / inverse transform along y alone (3D).
 // mode 0: S[1+i] = mult[i] S[0]                    (i < nfield)
-// mode 1: S[f]   = mult[i] S[f],  f = f0 + i       (blockIdx.y = i; with
-//         src >= 0 the input is S[src] for every i)
+// mode 1: S[f]   = mult[i] S[f],  f = f0 + i       (fields split over
+//         blockIdx.y, `fpb` fields per block)
 // mode 2: S[0]   = sum_i mult[i] S[f0 + i]
 // mode 3/4: S[f0 + i] <- F_y / F_y^-1 S[f0 + i]    (blockIdx.y = i)
 struct ColSpec {
@@ -158,13 +158,21 @@ struct ColSpec {
   int32_t nfield;
   int32_t mult[3];
   int32_t f0;
-  int32_t src = -1;  // mode 1: read S[src] instead of S[f] (one input, several outputs)
   int32_t tile = 0;  // columns per block (0: the default)
+  int32_t fpb = 1;   // mode 1: fields per block, 1 or nfield
 };
+// a compiled launch shape of a column pass: columns per block and (mode 1)
+// fields per block
+struct ColVariant {
+  int32_t tile, fpb;
+};
+constexpr int kMaxColVar = 8;
 hipError_t launch_col(const ColSpec& spec, int ndim, int nx, int ny, int nz, const Launch& L);
 int col_blocks(const ColSpec& spec, int ndim, int nx, int ny, int nz);
-int col_tile_of(const ColSpec& spec, int ndim, int ny, int nz);
-int col_tile_candidates(int na, int mode, int nfield, int* out);
+// the compiled variants of a pass (the default first); returns their count
+int col_variants(const ColSpec& spec, int ndim, int ny, int nz, ColVariant* out);
+// the variant spec.tile / spec.fpb name, or the default when not compiled
+ColVariant col_variant_of(const ColSpec& spec, int ndim, int ny, int nz);
 int col_axis_len(const ColSpec& spec, int ndim, int ny, int nz);
 
 hipError_t launch_reduce(const Launch& L, int n0, int n1);

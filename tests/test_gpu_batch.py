@@ -121,8 +121,8 @@ def test_autotune_keeps_results_bitwise(ndim):
     assert rep == b.tuning_report()
     assert rep, "no pass was tuned"
     for e in rep:
-        tiles = [c["tile"] for c in e["candidates"]]
-        assert len(tiles) >= 2 and e["tile"] in tiles
+        cands = [(c["tile"], c["fpb"]) for c in e["candidates"]]
+        assert len(cands) >= 2 and (e["tile"], e["fpb"]) in cands
         assert all(c["us"] > 0 for c in e["candidates"])
         assert e["axis_len"] in (128, 256, 512)
     if ndim == 3:
@@ -130,17 +130,21 @@ def test_autotune_keeps_results_bitwise(ndim):
     b.close()
 
 
-@pytest.mark.parametrize("ndim,tile", [(2, 4), (2, 8), (3, 4), (3, 8)])
-def test_forced_tile_widths_bitwise(ndim, tile):
-    """Every compiled width, forced on every tunable pass, equals eager."""
+@pytest.mark.parametrize("ndim,tile,fpb", [(2, 4, 1), (2, 8, 1), (2, 16, 2), (2, 4, 2), (3, 4, 1), (3, 8, 1)])
+def test_forced_tile_widths_bitwise(ndim, tile, fpb):
+    """Every compiled variant, forced on every pass that has it, equals eager."""
     insts = _tunable_instances(ndim)
+    applied = []
 
     def force(b):
         rep = b.autotune(reps=1)
         for e in rep:
-            b.set_tile(e, tile)
+            if any(v["tile"] == tile and v["fpb"] == fpb for v in e["candidates"]):
+                b.set_tile(e, tile, fpb)
+                applied.append(e["pass"])
         return rep
     b, _ = _run_tune_case(insts, force)
+    assert applied
     if ndim == 3:
         b.close()
         return
@@ -153,7 +157,9 @@ def test_forced_tile_widths_bitwise(ndim, tile):
         b.set_tile(dict(e, n=[96, 96, 1], **{"pass": 0}))  # no such class
     with pytest.raises(pat.PatError):
         b.set_tile(dict(e, nt=12, **{"pass": 0}))     # no class with that time axis
-    b.set_tile(dict(e, **{"pass": 0}), 0)             # back to the default
+    with pytest.raises(pat.PatError):
+        b.set_tile(dict(e, **{"pass": 0}), 8, 2)      # the gradient pass has one input field
+    b.set_tile(dict(e, **{"pass": 0}), 0, 1)          # back to the default
     b.close()
 
 
@@ -168,6 +174,7 @@ def test_autotune_cache_roundtrip(tmp_path):
     (arch, by_key), = stored.items()
     assert arch.startswith("gfx")
     b2, rep2 = _run_tune_case(insts, lambda b: b.autotune(reps=2, cache=cache))
-    assert [(e["dir"], e["pass"], e["tile"]) for e in rep2] == [(e["dir"], e["pass"], e["tile"]) for e in rep]
+    key = [(e["dir"], e["pass"], e["tile"], e["fpb"]) for e in rep]
+    assert [(e["dir"], e["pass"], e["tile"], e["fpb"]) for e in rep2] == key
     assert b2.tuning_report() == []  # applied from the cache, nothing timed
     b2.close()
