@@ -115,10 +115,12 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default column tile widths")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="run only the isolated kernel-timing phase (for profiling it); no JSON line")
     ap.add_argument("--time-pass", default="0:1", help="direction:pass_index timed with HIP events")
     ap.add_argument("--pmc-probe", action="store_true",
-                    help="counter probe: a 256 MiB device copy (calibration) and one eager batched "
-                         "forward + adjoint, nothing timed; run under rocprofv3 --pmc")
+                    help="counter probe: a 1 GiB device copy (calibration) and a burst of the roofline "
+                         "phase's launches; run under rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver runs each instance on a single device "
@@ -148,11 +150,32 @@ def main():
         flush = torch.zeros(256 * 1024 * 1024, device=dev)
         b = torch.add(a, 1.0)
         del flush, b
-        probe = pat.Batch(plans, chunk=1)
-        d = probe.forward(x_true)
-        probe.adjoint(d)
+        probe = pat.Batch(plans, chunk=1, parts=1, lanes=1)
+        tdir, tidx = (int(v) for v in args.time_pass.split(":"))
+        probe.time_pass(tdir, tidx, max(p.desc.n[0] for p in plans), 20)  # the roofline phase's launches
         torch.cuda.synchronize()
         log("pmc probe done")
+        return
+    tdir, tidx = (int(v) for v in args.time_pass.split(":"))
+    nx_dom = max(p.desc.n[0] for p in plans)  # time the largest grids' launches only
+
+    def isolated_kernel(reps=200):
+        """The selected pass on its own: `reps` back-to-back launches over a
+        one-stream batch with one group per size class (each launch covers
+        every instance of the largest size and has the GPU to itself), timed
+        with HIP events around the burst.  Returns (ms total, launches,
+        algorithmic bytes total)."""
+        b1 = pat.Batch(plans, chunk=1, parts=1, lanes=1)
+        us, by = b1.time_pass(tdir, tidx, nx_dom, reps)
+        b1.close()
+        return us * reps / 1e3, reps, by * reps
+
+    # the roofline phase runs first, on the GPU as a fresh process finds it,
+    # so that `--roofline-only` (the profiled command) repeats it exactly
+    k_ms, k_n, k_bytes = isolated_kernel()
+    log(f"isolated pass {tdir}:{tidx}: {k_n} launches, {k_ms / k_n * 1e3:.2f} us/launch, "
+        f"{k_bytes / (k_ms / 1e3) / 1e9:.0f} GB/s")
+    if args.roofline_only:
         return
     batch = pat.Batch(plans, chunk=args.chunk)
     targets = [d.clone() for d in batch.forward(x_true)]
@@ -204,27 +227,13 @@ def main():
             f"{total_gps / (ms / 1e3) / 1e9:.2f} G gps/s")
         return ms
 
-    # main timed region: batched executor; the selected pass is timed with
-    # HIP events on its stream when the batch runs eagerly (chunk 1)
-    tdir, tidx = (int(v) for v in args.time_pass.split(":"))
-    nx_dom = max(p.desc.n[0] for p in plans)  # time the largest grids' launches only
+
+    # main timed region: the batched executor (graph-captured chunks; the
+    # steps left over by the chunking run eagerly between the chunks and
+    # are event-timed there, sharing the GPU with the other streams)
     pat.timing_begin(tdir, tidx, nx_dom)
     ms = timed(batched, args.steps, args.warmup, f"batched(chunk={args.chunk})")
-    k_ms, k_n, k_bytes = pat.timing_end()
-    if k_n == 0:
-        # graph-captured launches are not event-timed: time the same pass
-        # over the same batch with an eager (chunk 1) batch right after
-        b1 = pat.Batch(plans, chunk=1)
-        for e in tiles:
-            b1.set_tile(e)
-        pat.timing_begin(tdir, tidx, nx_dom)
-        step(b1.forward, b1.adjoint)
-        torch.cuda.synchronize()
-        k_ms, k_n, k_bytes = pat.timing_end()
-        b1.close()
-        kernel_note = "eager batch run right after the timed region"
-    else:
-        kernel_note = "timed region"
+    s_ms, s_n, s_bytes = pat.timing_end()
     plain_ms = None
     if not args.no_plain:
         plain_ms = timed(plain, 1, 0, "plain (one instance at a time, eager)")
@@ -266,7 +275,14 @@ def main():
             "traffic": counter_traffic("k_row<512, 2, 1>") if (tdir, tidx) == (0, 1) else None,
             "launches": k_n,
             "avg_launch_us": (k_ms / k_n * 1e3) if k_n else None,
-            "measured_in": kernel_note,
+            "measured_in": "back-to-back launches of the pass over a one-stream batch before the timed "
+                           "region (each launch: every instance of the largest size, GPU to itself)",
+            "in_timed_region": {
+                "launches": s_n,
+                "avg_launch_us": (s_ms / s_n * 1e3) if s_n else None,
+                "achieved": (s_bytes / (s_ms / 1e3) / 1e9) if s_ms > 0 else None,
+                "note": "eager steps between graph chunks, concurrent with the other streams' passes",
+            },
             "step_frac": value * 152.0 / (HBM_PEAK_GBS * 1e9),
         },
     }

@@ -179,6 +179,18 @@ int pat_forward_range(pat_plan* plan, const float* p0, float* data, int32_t n_be
  * Results equal pat_forward / pat_adjoint per instance bitwise.
  */
 int pat_batch_create(pat_batch** out, pat_plan* const* plans, int32_t nb, int32_t chunk);
+/*
+ * pat_batch_create_ex  as pat_batch_create, with the grouping explicit: the
+ *   instances of one size class (same grid, nt and physics) are split into
+ *   `parts` equal groups (0: the default, 2), each launched as its own work
+ *   tables, and the groups run on `lanes` streams (0: one per group; group k
+ *   on stream k mod lanes).  Groups on different streams overlap on the GPU.
+ *   pat_batch_create(out, plans, nb, chunk) is pat_batch_create_ex(out,
+ *   plans, nb, chunk, 0, 0).  parts = 1, lanes = 1 runs one launch per pass
+ *   and size class over all its instances, one launch at a time.
+ */
+int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int32_t nb, int32_t chunk, int32_t parts,
+                        int32_t lanes);
 void pat_batch_destroy(pat_batch* batch);
 int pat_batch_forward(pat_batch* batch, const float* const* p0, float* const* data, void* stream);
 int pat_batch_adjoint(pat_batch* batch, const float* const* data, float* const* img, void* stream);
@@ -213,6 +225,22 @@ int pat_batch_adjoint(pat_batch* batch, const float* const* data, float* const* 
  */
 int pat_batch_autotune(pat_batch* batch, int32_t reps, void* stream);
 int pat_tuning_report(const pat_batch* batch, char* buf, size_t cap, size_t* needed);
+
+/*
+ * pat_batch_time_pass  diagnostics: `reps` back-to-back launches of pass
+ *   `pass` of direction dir (0 forward, 1 adjoint; the pass order of one
+ *   time step) over every class of the batch with grid width nx (0: every
+ *   class), one class at a time, each burst timed with HIP events on
+ *   `stream` after one untimed launch.  Writes the mean microseconds per
+ *   launch and the mean algorithmic bytes per launch (the full-grid arrays
+ *   the pass must read and write, float32).  The launches run a generic time
+ *   step on whatever the batch's state holds and clobber it, like
+ *   pat_batch_autotune.  PAT_EINVAL when no class matches, the pass index
+ *   is out of range, or the pass reads the caller's arrays (the first pass
+ *   of the adjoint, which scatters the data).
+ */
+int pat_batch_time_pass(pat_batch* batch, int32_t dir, int32_t pass, int32_t nx, int32_t reps, void* stream,
+                        double* us_per_launch, double* bytes_per_launch);
 
 /*
  * pat_batch_set_tile  applies a stored choice (as reported above) without

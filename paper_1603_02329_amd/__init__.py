@@ -27,10 +27,10 @@ PAT_CHECK_FINITE = 0x2
 #: every symbol include/pat.h declares
 EXPORTED = [
     "pat_plan_create", "pat_plan_destroy", "pat_plan_info", "pat_forward", "pat_adjoint",
-    "pat_forward_range", "pat_batch_create", "pat_batch_destroy", "pat_batch_forward",
+    "pat_forward_range", "pat_batch_create", "pat_batch_create_ex", "pat_batch_destroy", "pat_batch_forward",
     "pat_batch_adjoint", "pat_tv_prox_work_bytes", "pat_tv_prox", "pat_restrict", "pat_prolong",
     "pat_dot_f64", "pat_residual_f64", "pat_plan_sync", "pat_strerror", "pat_timing_begin",
-    "pat_timing_end", "pat_batch_autotune", "pat_tuning_report", "pat_batch_set_tile",
+    "pat_timing_end", "pat_batch_autotune", "pat_tuning_report", "pat_batch_set_tile", "pat_batch_time_pass",
 ]
 
 
@@ -79,6 +79,7 @@ def lib() -> ctypes.CDLL:
         "pat_adjoint": (ctypes.c_int, [vp, vp, vp, vp]),
         "pat_forward_range": (ctypes.c_int, [vp, vp, vp, i32, i32, vp, vp]),
         "pat_batch_create": (ctypes.c_int, [pp, pp, i32, i32]),
+        "pat_batch_create_ex": (ctypes.c_int, [pp, pp, i32, i32, i32, i32]),
         "pat_batch_destroy": (None, [vp]),
         "pat_batch_forward": (ctypes.c_int, [vp, pp, pp, vp]),
         "pat_batch_adjoint": (ctypes.c_int, [vp, pp, pp, vp]),
@@ -93,6 +94,7 @@ def lib() -> ctypes.CDLL:
         "pat_timing_begin": (ctypes.c_int, [i32, i32, i32]),
         "pat_timing_end": (ctypes.c_int, [ctypes.POINTER(f64), ctypes.POINTER(i64), ctypes.POINTER(f64)]),
         "pat_batch_autotune": (ctypes.c_int, [vp, i32, vp]),
+        "pat_batch_time_pass": (ctypes.c_int, [vp, i32, i32, i32, i32, vp, ctypes.POINTER(f64), ctypes.POINTER(f64)]),
         "pat_tuning_report": (ctypes.c_int, [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)]),
         "pat_batch_set_tile": (ctypes.c_int, [vp, ctypes.POINTER(i32), i32, i32, i32, i32, i32, i32]),
     }
@@ -254,11 +256,14 @@ class Plan:
 class Batch:
     """Many plans run together (one launch per pass over all instances)."""
 
-    def __init__(self, plans: Sequence[Plan], chunk: int = 0):
+    def __init__(self, plans: Sequence[Plan], chunk: int = 0, parts: int = 0, lanes: int = 0):
+        """chunk: steps per captured graph (0: 32; 1: eager); parts: groups
+        per size class (0: 2); lanes: streams (0: one per group)."""
         self.plans = list(plans)
         arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
         h = ctypes.c_void_p()
-        _check(lib().pat_batch_create(ctypes.byref(h), arr, len(self.plans), int(chunk)), "pat_batch_create")
+        _check(lib().pat_batch_create_ex(ctypes.byref(h), arr, len(self.plans), int(chunk), int(parts), int(lanes)),
+               "pat_batch_create_ex")
         self._h = h
 
     def close(self):
@@ -291,6 +296,14 @@ class Batch:
         b = (ctypes.c_void_p * len(self.plans))(*[_dev_f32(x, "img", p.npoints).value for p, x in zip(self.plans, imgs)])
         _check(lib().pat_batch_adjoint(self._h, a, b, _stream()), "pat_batch_adjoint")
         return imgs
+
+    def time_pass(self, direction: int, pass_index: int, nx: int = 0, reps: int = 100):
+        """(microseconds, algorithmic bytes) per launch of one pass, from
+        back-to-back launches (pat_batch_time_pass)."""
+        us, by = ctypes.c_double(), ctypes.c_double()
+        _check(lib().pat_batch_time_pass(self._h, int(direction), int(pass_index), int(nx), int(reps), _stream(),
+                                         ctypes.byref(us), ctypes.byref(by)), "pat_batch_time_pass")
+        return us.value, by.value
 
     def tuning_report(self) -> list:
         """The autotuner's choices (list of dicts, see pat_tuning_report)."""

@@ -94,3 +94,23 @@ def test_null_plan_calls_are_rejected():
     out = ctypes.c_double(7.0)
     assert L.pat_dot_f64(None, None, 0, ctypes.byref(out), None) == pat.PAT_OK and out.value == 0.0
     assert L.pat_dot_f64(None, None, 5, ctypes.byref(out), None) == pat.PAT_EINVAL
+
+
+def test_batch_entry_points_validate_on_host():
+    """Argument checks that return before any plan or device access."""
+    L = pat.lib()
+    h = ctypes.c_void_p()
+    one = (ctypes.c_void_p * 1)(None)
+    assert L.pat_batch_create(None, one, 1, 0) == pat.PAT_EINVAL
+    assert L.pat_batch_create(ctypes.byref(h), None, 1, 0) == pat.PAT_EINVAL
+    assert L.pat_batch_create(ctypes.byref(h), one, 0, 0) == pat.PAT_EINVAL
+    assert L.pat_batch_create(ctypes.byref(h), one, 1, -1) == pat.PAT_EINVAL
+    assert L.pat_batch_create_ex(ctypes.byref(h), one, 1, 0, -1, 0) == pat.PAT_EINVAL
+    assert L.pat_batch_create_ex(ctypes.byref(h), one, 1, 0, 0, -1) == pat.PAT_EINVAL
+    assert L.pat_batch_create(ctypes.byref(h), one, 1, 0) == pat.PAT_EINVAL  # null plan pointer
+    assert h.value is None
+    assert L.pat_batch_autotune(None, 1, None) == pat.PAT_EINVAL
+    need = ctypes.c_size_t()
+    assert L.pat_tuning_report(None, None, 0, ctypes.byref(need)) == pat.PAT_EINVAL
+    n = (ctypes.c_int32 * 3)(16, 16, 1)
+    assert L.pat_batch_set_tile(None, n, 1, 1, 0, 0, 16, 1) == pat.PAT_EINVAL

@@ -25,8 +25,8 @@ def _instances():
     return [synth.small_instance(500 + i, **s) for i, s in enumerate(specs)]
 
 
-@pytest.mark.parametrize("chunk", [1, 4])
-def test_batch_matches_eager_bitwise(chunk):
+@pytest.mark.parametrize("chunk,parts,lanes", [(1, 0, 0), (4, 0, 0), (4, 1, 1), (3, 3, 2)])
+def test_batch_matches_eager_bitwise(chunk, parts, lanes):
     insts = _instances()
     plans = [pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=DEV) for i in insts]
     p0 = [torch.from_numpy(i.p0).to(DEV) for i in insts]
@@ -34,7 +34,7 @@ def test_batch_matches_eager_bitwise(chunk):
     rng = np.random.default_rng(3)
     hs = [torch.from_numpy(rng.standard_normal((i.desc.nt, i.ns)).astype(np.float32)).to(DEV) for i in insts]
     ref_i = [p.adjoint(h).clone() for p, h in zip(plans, hs)]
-    b = pat.Batch(plans, chunk=chunk)
+    b = pat.Batch(plans, chunk=chunk, parts=parts, lanes=lanes)
     for rep in range(2):  # graph replays across calls
         d = b.forward(p0)
         im = b.adjoint(hs)
