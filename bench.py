@@ -115,6 +115,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default column tile widths")
+    ap.add_argument("--parts", type=int, default=0, help="groups per size class (0: the library default)")
+    ap.add_argument("--lanes", type=int, default=0, help="streams for the groups (0: one per group)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="run only the isolated kernel-timing phase (for profiling it); no JSON line")
     ap.add_argument("--time-pass", default="0:1", help="direction:pass_index timed with HIP events")
@@ -177,7 +179,7 @@ def main():
         f"{k_bytes / (k_ms / 1e3) / 1e9:.0f} GB/s")
     if args.roofline_only:
         return
-    batch = pat.Batch(plans, chunk=args.chunk)
+    batch = pat.Batch(plans, chunk=args.chunk, parts=args.parts, lanes=args.lanes)
     targets = [d.clone() for d in batch.forward(x_true)]
     tiles = []
     if not args.no_autotune:
