@@ -100,9 +100,20 @@ def cpu_baseline(insts, seconds_target=15.0):
         t_total += time.perf_counter() - t0
         gps += 2.0 * inst.desc.npoints * nts
     sizes = "+".join(f"{i.desc.n[0]}^2" for i in sample)
+    # the same oracle on one core, on the smallest instance of the sample
+    K.WORKERS = 1
+    small = min(sample, key=lambda i: i.desc.npoints)
+    d = replace(small.desc, nt=nts)
+    op = K.make_plan(d, small.c0, small.rho0, small.alpha0_db, small.sensors)
+    t0 = time.perf_counter()
+    K.adjoint(op, K.forward(op, small.p0))
+    t1 = time.perf_counter() - t0
+    K.WORKERS = cores
     return {"value": gps / t_total, "unit": "grid-point-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"FP64 oracle forward+adjoint of one instance per size ({sizes}) with N_t={nts} "
-                      f"instead of the full time axis; {t_total:.1f} s on {cores} threads (scipy.fft workers)"}
+                      f"instead of the full time axis; {t_total:.1f} s on {cores} threads (scipy.fft workers)",
+            "single_core": {"value": 2.0 * small.desc.npoints * nts / t1, "unit": "grid-point-steps/s",
+                            "sample": f"{small.desc.n[0]}^2 instance, N_t={nts}, {t1:.1f} s on 1 thread"}}
 
 
 def main():

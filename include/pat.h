@@ -301,6 +301,39 @@ int pat_residual_f64(const float* a, const float* b, float* r, int64_t n, double
                      void* stream);
 
 /*
+ * Operators of the two-level iteration (section V, Alg. FISTAMG).
+ *
+ * pat_tv_smooth -- the smoothed TV of equation Thirty-two,
+ *   J_rho(x) = sum_j sqrt(|D x|_j^2 + rho^2) - rho,
+ * D x the forward differences of pat_tv_prox (zero across each axis' last
+ * face), and its gradient D^T (D x / sqrt(|D x|^2 + rho^2)), the TV term of
+ * equation Twentyone.  rho = 0 gives the isotropic TV (the gradient then
+ * takes 0 where D x = 0).
+ *   ndim, n    grid (2 or 3 axes, physical order x, y, z).
+ *   x          device, N floats.
+ *   grad       device, N floats, or NULL: grad += scale * grad J_rho(x)
+ *              (may not alias x).
+ *   value_host host double, or NULL: J_rho(x), accumulated in float64 with a
+ *              fixed partition (deterministic); the call then synchronizes
+ *              `stream`.  At least one of grad, value_host.
+ *
+ * pat_restrict_lower -- the restricted bound constraint of equation
+ *   constraint: lower[I] = (R y)[I] - min over the 2^d block of I of y, so
+ *   that y + P(x_c - R y) >= 0 for every coarse x_c >= lower (R, P as in
+ *   pat_restrict / pat_prolong).  n_fine as in pat_restrict.
+ *
+ * pat_axpby -- out = a x + b y over n floats (device; out may alias x or y):
+ *   the extrapolation and correction steps of Alg. FISTA / FISTAMG.
+ * pat_project -- out = max(x, lower) over n floats, lower NULL meaning 0:
+ *   the coarse level's proximal map, a projection (section V-E).
+ */
+int pat_tv_smooth(int32_t ndim, const int32_t n[3], const float* x, double rho, double scale, float* grad,
+                  double* value_host, void* stream);
+int pat_restrict_lower(int32_t ndim, const int32_t n_fine[3], const float* fine, float* lower, void* stream);
+int pat_axpby(int64_t n, double a, const float* x, double b, const float* y, float* out, void* stream);
+int pat_project(int64_t n, const float* x, const float* lower, float* out, void* stream);
+
+/*
  * pat_plan_sync -- wait for `plan`'s work on `stream` and report deferred
  * device errors: PAT_ENONFINITE if PAT_CHECK_FINITE was set and a non-finite
  * pressure value was produced since the last sync (the flag is then cleared).

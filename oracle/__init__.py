@@ -11,13 +11,14 @@ Modules
 kspace    forward operator H and its exact transpose (sections II-A, III)
 prox      FGP dual solver of the bound-constrained TV prox (section IV)
 transfer  restriction / prolongation (section V) and FP64 reductions
+solver    ISTA / FISTA and the two-level MG-FISTA (sections IV and V)
 
 Parity status: every function is pinned by tests in ``tests/test_oracle_*.py``
 against closed forms, invariants, brute force or library routines, except
 the PML's profile and placement and heterogeneous lossy propagation, which
 are pinned only structurally (transpose, linearity, lossless limit).
 """
-from . import kspace, prox, transfer  # noqa: F401
+from . import kspace, prox, solver, transfer  # noqa: F401
 from .kspace import make_plan, forward, adjoint  # noqa: F401
 from .prox import tv_prox  # noqa: F401
 from .transfer import restrict, prolong, dot  # noqa: F401

@@ -26,7 +26,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Lt", "L", "tv_prox", "tv_value"]
+__all__ = ["Lt", "L", "tv_prox", "tv_value", "tv_smooth"]
 
 
 def Lt(x: np.ndarray):
@@ -104,3 +104,21 @@ def tv_value(x: np.ndarray) -> float:
     """Isotropic TV with the same forward differences (zero across the last face)."""
     g = Lt(np.asarray(x, dtype=np.float64))
     return float(np.sqrt(sum(ga * ga for ga in g)).sum())
+
+
+def tv_smooth(x: np.ndarray, rho: float):
+    """Smoothed TV of equation Thirty-two and its gradient (section V-B):
+
+        J_rho(x) = sum_j sqrt(|Lt x|_j^2 + rho^2) - rho,
+        grad J_rho(x) = L w,  w = Lt x / sqrt(|Lt x|^2 + rho^2)
+
+    (L = Lt^T; with rho = 0, w is taken as 0 where Lt x = 0).  The gradient is
+    the TV term of equation Twentyone, -div(grad x / sqrt(|grad x|^2 +
+    rho^2)) in the differences used by the prox.  Returns (J, grad)."""
+    x = np.asarray(x, dtype=np.float64)
+    g = Lt(x)
+    s = np.sqrt(sum(ga * ga for ga in g) + rho * rho)
+    value = float((s - rho).sum())
+    with np.errstate(invalid="ignore", divide="ignore"):
+        w = [np.where(s > 0, ga / s, 0.0) for ga in g]
+    return value, L(w)

@@ -16,7 +16,7 @@ import math
 
 import numpy as np
 
-__all__ = ["restrict", "prolong", "dot", "norm2"]
+__all__ = ["restrict", "prolong", "restrict_lower", "dot", "norm2"]
 
 
 def restrict(fine: np.ndarray) -> np.ndarray:
@@ -35,6 +35,18 @@ def prolong(coarse: np.ndarray) -> np.ndarray:
     for ax in range(c.ndim):
         c = np.repeat(c, 2, axis=ax)
     return c
+
+
+def restrict_lower(fine: np.ndarray) -> np.ndarray:
+    """The restricted bound of equation constraint (section V-C):
+    lower[I] = (R y)[I] - min_{j in block I} y_j, the index set I_{h,i} of the
+    paper being the 2^d fine points averaged into coarse point i."""
+    f = np.asarray(fine, dtype=np.float64)
+    nd = f.ndim
+    mn = np.full(tuple(s // 2 for s in f.shape), np.inf)
+    for corner in np.ndindex(*([2] * nd)):
+        mn = np.minimum(mn, f[tuple(slice(c, None, 2) for c in corner)])
+    return restrict(f) - mn
 
 
 def dot(a: np.ndarray, b: np.ndarray) -> float:

@@ -16,6 +16,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 __all__ = ["lib", "PatError", "Plan", "Batch", "tv_prox", "restrict", "prolong", "dot_f64", "residual_f64",
+           "tv_smooth", "restrict_lower", "axpby", "project",
            "LIB_PATH", "EXPORTED"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpat.so")
@@ -31,6 +32,7 @@ EXPORTED = [
     "pat_batch_adjoint", "pat_tv_prox_work_bytes", "pat_tv_prox", "pat_restrict", "pat_prolong",
     "pat_dot_f64", "pat_residual_f64", "pat_plan_sync", "pat_strerror", "pat_timing_begin",
     "pat_timing_end", "pat_batch_autotune", "pat_tuning_report", "pat_batch_set_tile", "pat_batch_time_pass",
+    "pat_tv_smooth", "pat_restrict_lower", "pat_axpby", "pat_project",
 ]
 
 
@@ -94,6 +96,10 @@ def lib() -> ctypes.CDLL:
         "pat_timing_begin": (ctypes.c_int, [i32, i32, i32]),
         "pat_timing_end": (ctypes.c_int, [ctypes.POINTER(f64), ctypes.POINTER(i64), ctypes.POINTER(f64)]),
         "pat_batch_autotune": (ctypes.c_int, [vp, i32, vp]),
+        "pat_tv_smooth": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, f64, f64, vp, ctypes.POINTER(f64), vp]),
+        "pat_restrict_lower": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, vp]),
+        "pat_axpby": (ctypes.c_int, [i64, f64, vp, f64, vp, vp, vp]),
+        "pat_project": (ctypes.c_int, [i64, vp, vp, vp, vp]),
         "pat_batch_time_pass": (ctypes.c_int, [vp, i32, i32, i32, i32, vp, ctypes.POINTER(f64), ctypes.POINTER(f64)]),
         "pat_tuning_report": (ctypes.c_int, [vp, ctypes.c_char_p, sz, ctypes.POINTER(sz)]),
         "pat_batch_set_tile": (ctypes.c_int, [vp, ctypes.POINTER(i32), i32, i32, i32, i32, i32, i32]),
@@ -457,3 +463,47 @@ def residual_f64(a, b, r=None):
     _check(lib().pat_residual_f64(_dev_f32(a, "a"), _dev_f32(b, "b", a.numel()), _dev_f32(r, "r", a.numel()),
                                   a.numel(), ctypes.byref(out), _stream()), "pat_residual_f64")
     return r, out.value
+
+
+def tv_smooth(x, rho: float, grad=None, scale: float = 1.0, value: bool = True):
+    """Smoothed TV J_rho(x) (float64, or None with value=False); with `grad`
+    given, grad += scale * grad J_rho(x) in place."""
+    out = ctypes.c_double()
+    _check(lib().pat_tv_smooth(x.dim(), _i32x3(list(reversed(x.shape))), _dev_f32(x, "x"), float(rho), float(scale),
+                               None if grad is None else _dev_f32(grad, "grad", x.numel()),
+                               ctypes.byref(out) if value else None, _stream()), "pat_tv_smooth")
+    return out.value if value else None
+
+
+def restrict_lower(fine, out=None):
+    """R(y) - blockmin(y): the coarse bound that keeps a prolonged correction
+    of y feasible."""
+    torch = _torch()
+    nd = fine.dim()
+    if out is None:
+        out = torch.empty(tuple(s // 2 for s in fine.shape), device=fine.device, dtype=torch.float32)
+    _check(lib().pat_restrict_lower(nd, _i32x3(list(reversed(fine.shape))), _dev_f32(fine, "fine"),
+                                    _dev_f32(out, "lower", fine.numel() >> nd), _stream()), "pat_restrict_lower")
+    return out
+
+
+def axpby(a: float, x, b: float, y, out=None):
+    """out = a x + b y."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(x)
+    n = x.numel()
+    _check(lib().pat_axpby(n, float(a), _dev_f32(x, "x"), float(b), _dev_f32(y, "y", n), _dev_f32(out, "out", n),
+                           _stream()), "pat_axpby")
+    return out
+
+
+def project(x, lower=None, out=None):
+    """out = max(x, lower) (lower None: 0)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(x)
+    n = x.numel()
+    _check(lib().pat_project(n, _dev_f32(x, "x"), None if lower is None else _dev_f32(lower, "lower", n),
+                             _dev_f32(out, "out", n), _stream()), "pat_project")
+    return out

@@ -131,6 +131,81 @@ __global__ void k_prolong(Grid3 f, int ndim, const float* __restrict__ coarse, f
   fine[i] = coarse[c];
 }
 
+// ------------------------------------------------------------------ smoothed TV
+// The smoothed TV of equation Thirty-two, J_rho(x) = sum_j sqrt(|Lt x|_j^2 +
+// rho^2) - rho, with Lt x the forward differences of the prox (zero across
+// each axis' last face), and its gradient L w, w = Lt x / sqrt(|Lt x|^2 +
+// rho^2) (for rho = 0, w = 0 where Lt x = 0).
+struct TvPoint {
+  float d[3];
+  float s;  // sqrt(|Lt x|^2 + rho^2)
+};
+__device__ __forceinline__ TvPoint tv_point(const Grid3& g, int ndim, const float* __restrict__ x, long j,
+                                            const int* idx, float rho2) {
+  TvPoint p{{0.f, 0.f, 0.f}, 0.f};
+  float q = rho2;
+  for (int a = 0; a < ndim; ++a) {
+    p.d[a] = (idx[a] < g.n[a] - 1) ? x[j] - x[j + g.stride[a]] : 0.f;
+    q += p.d[a] * p.d[a];
+  }
+  p.s = sqrtf(q);
+  return p;
+}
+__device__ __forceinline__ float tv_w(const TvPoint& p, int a) { return p.s > 0.f ? p.d[a] / p.s : 0.f; }
+
+// grad += scale * (L w)_i, (L w)_i = sum_a w_a[i] - w_a[i - e_a]
+__global__ void k_tv_grad(Grid3 g, int ndim, const float* __restrict__ x, float rho2, float scale,
+                          float* __restrict__ grad) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.N) return;
+  long rem = i;
+  int idx[3];
+  for (int j = 0; j < 3; ++j) {
+    idx[j] = (int)(rem % g.n[j]);
+    rem /= g.n[j];
+  }
+  const TvPoint pi = tv_point(g, ndim, x, i, idx, rho2);
+  float acc = 0.f;
+  for (int a = 0; a < ndim; ++a) {
+    acc += tv_w(pi, a);
+    if (idx[a] > 0) {
+      int jdx[3] = {idx[0], idx[1], idx[2]};
+      jdx[a] -= 1;
+      const TvPoint pj = tv_point(g, ndim, x, i - g.stride[a], jdx, rho2);
+      acc -= tv_w(pj, a);
+    }
+  }
+  grad[i] += scale * acc;
+}
+
+// ------------------------------------------------------------------ bound restriction
+// lower_c[I] = (R y)[I] - min over the block {2I + delta} of y: for every
+// coarse x_c >= lower_c, y + P(x_c - R y) >= 0 on the block.
+__global__ void k_restrict_lower(Grid3 c, int ndim, const float* __restrict__ fine, float* __restrict__ lower) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.N) return;
+  const int cx = (int)(i % c.n[0]);
+  const int cy = (int)((i / c.n[0]) % c.n[1]);
+  const int cz = (int)(i / ((long)c.n[0] * c.n[1]));
+  const long fx = 2L * c.n[0], fy = 2L * c.n[1];
+  float acc = 0.f, mn = INFINITY;
+  const int nzc = ndim == 3 ? 2 : 1;
+  for (int dz = 0; dz < nzc; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        const long f = (2L * cx + dx) + fx * ((2L * cy + dy) + fy * (ndim == 3 ? (2L * cz + dz) : 0));
+        acc += fine[f];
+        mn = fminf(mn, fine[f]);
+      }
+  lower[i] = acc * (ndim == 3 ? 0.125f : 0.25f) - mn;
+}
+
+// ------------------------------------------------------------------ vector updates
+__global__ void k_axpby(long n, float a, const float* x, float b, const float* y, float* out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a * x[i] + b * y[i];
+}
+
 // ------------------------------------------------------------------ float64 reductions
 constexpr int kRedBlocks = 512;
 constexpr int kRedThreads = 256;
@@ -174,6 +249,37 @@ __global__ void __launch_bounds__(kRedThreads) k_red2(const double* __restrict__
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// sum_j sqrt(|Lt x|_j^2 + rho^2) - rho, same fixed partition as k_red1
+__global__ void __launch_bounds__(kRedThreads) k_red_tv(Grid3 g, int ndim, const float* __restrict__ x, double rho,
+                                                        double* __restrict__ part) {
+  __shared__ double sh[kRedThreads];
+  const long chunk = (g.N + kRedBlocks - 1) / kRedBlocks;
+  const long beg = (long)blockIdx.x * chunk;
+  const long end = beg + chunk < g.N ? beg + chunk : g.N;
+  double acc = 0.0;
+  for (long i = beg + threadIdx.x; i < end; i += kRedThreads) {
+    long rem = i;
+    int idx[3];
+    for (int j = 0; j < 3; ++j) {
+      idx[j] = (int)(rem % g.n[j]);
+      rem /= g.n[j];
+    }
+    double q = rho * rho;
+    for (int a = 0; a < ndim; ++a) {
+      const double d = (idx[a] < g.n[a] - 1) ? (double)x[i] - (double)x[i + g.stride[a]] : 0.0;
+      q += d * d;
+    }
+    acc += sqrt(q) - rho;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
 std::mutex g_red_mu;
@@ -286,4 +392,60 @@ extern "C" int pat_dot_f64(const float* a, const float* b, int64_t n, double* ou
 extern "C" int pat_residual_f64(const float* a, const float* b, float* r, int64_t n, double* half_sq_host,
                                 void* stream) {
   return reduce_common(1, a, b, r, n, half_sq_host, (hipStream_t)stream);
+}
+
+extern "C" int pat_tv_smooth(int32_t ndim, const int32_t n[3], const float* x, double rho, double scale, float* grad,
+                             double* value_host, void* stream) {
+  Grid3 g;
+  if (make_grid(ndim, n, g) || !x || !(rho >= 0) || !std::isfinite(rho) || !std::isfinite(scale) ||
+      (!grad && !value_host) || (const float*)grad == x)
+    return PAT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (grad) {
+    hipLaunchKernelGGL(k_tv_grad, dim3(blocks_for(g.N)), dim3(256), 0, st, g, ndim, x, (float)(rho * rho),
+                       (float)scale, grad);
+    PAT_TRY_HIP(hipGetLastError());
+  }
+  if (value_host) {
+    double* buf = nullptr;
+    int rc = red_buffer(&buf);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_red_tv, dim3(kRedBlocks), dim3(kRedThreads), 0, st, g, ndim, x, rho, buf);
+    hipLaunchKernelGGL(k_red2, dim3(1), dim3(kRedThreads), 0, st, buf, buf + kRedBlocks);
+    PAT_TRY_HIP(hipGetLastError());
+    PAT_TRY_HIP(hipMemcpyAsync(value_host, buf + kRedBlocks, sizeof(double), hipMemcpyDeviceToHost, st));
+    PAT_TRY_HIP(hipStreamSynchronize(st));
+  }
+  return PAT_OK;
+}
+
+extern "C" int pat_restrict_lower(int32_t ndim, const int32_t n_fine[3], const float* fine, float* lower,
+                                  void* stream) {
+  Grid3 f;
+  if (make_grid(ndim, n_fine, f) || !fine || !lower) return PAT_EINVAL;
+  int32_t nc[3];
+  for (int j = 0; j < 3; ++j) {
+    if (j < ndim && (f.n[j] % 2)) return PAT_EINVAL;
+    nc[j] = j < ndim ? f.n[j] / 2 : 1;
+  }
+  Grid3 c;
+  make_grid(ndim, nc, c);
+  hipLaunchKernelGGL(k_restrict_lower, dim3(blocks_for(c.N)), dim3(256), 0, (hipStream_t)stream, c, ndim, fine,
+                     lower);
+  return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
+}
+
+extern "C" int pat_axpby(int64_t n, double a, const float* x, double b, const float* y, float* out, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !y || !out))) return PAT_EINVAL;
+  if (n == 0) return PAT_OK;
+  hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, (long)n, (float)a, x, (float)b,
+                     y, out);
+  return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
+}
+
+extern "C" int pat_project(int64_t n, const float* x, const float* lower, float* out, void* stream) {
+  if (n < 0 || (n > 0 && (!x || !out))) return PAT_EINVAL;
+  if (n == 0) return PAT_OK;
+  hipLaunchKernelGGL(k_proj, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, (long)n, x, lower, out);
+  return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
 }

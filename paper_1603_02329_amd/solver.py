@@ -1,0 +1,200 @@
+"""Reconstruction iterations of sections IV and V on libpat.
+
+ISTA / FISTA (Alg. ISTA, Alg. FISTA) and the two-level MG-FISTA
+(Alg. FISTAMG) for
+
+    min_x  F(x) = 1/2 ||H x - p_hat||^2 + lam TV(x)   subject to x >= 0
+
+(equation two, gradient equation Six).  The host loop keeps only scalars
+(step sizes, momentum, the decision rule's norms); every vector operation is
+a libpat call on device tensors: H and H^T (``Plan.forward/adjoint``), the
+float64 residual and inner products, the FGP prox, the smoothed TV and its
+gradient (equations Thirty-two and Twentyone), the level transfers, the
+restricted bound (equation constraint), the extrapolation ``axpby`` and the
+projection.
+
+The iteration follows the paper's algorithms; where it is silent: the coarse
+level has its own plan (grid halved, time step doubled) with the fine data
+at even sample indices, the coarse step size and lambda are the caller's,
+the coarse loop stops after the update with
+phi_k - phi_{k+1} < eps_c max(|phi_k|, |phi_{k+1}|) or after q_c updates,
+and the fine loop (optionally) when F_{k-1} - F_k < eps_d max(F_{k-1}, F_k).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import List, Optional
+
+from . import Plan, axpby, dot_f64, project, prolong, residual_f64, restrict, restrict_lower, tv_prox, tv_smooth
+
+__all__ = ["Level", "MGParams", "MGRecord", "power_iteration", "fista", "coarse_fista", "mg_fista"]
+
+
+@dataclass
+class Level:
+    """One grid level: plan, measured data (device, (nt, ns) float32),
+    lambda and step size."""
+    plan: Plan
+    data: object
+    lam: float
+    alpha: float
+
+    def grad_f(self, x):
+        """(f(x), grad f(x)) with f = 1/2 ||H x - p_hat||^2."""
+        r, half = residual_f64(self.plan.forward(x), self.data)
+        return half, self.plan.adjoint(r)
+
+    def objective(self, x) -> float:
+        """F(x) = f(x) + lam TV(x)."""
+        _, half = residual_f64(self.plan.forward(x), self.data)
+        return half + self.lam * tv_smooth(x, 0.0)
+
+    def smoothed(self, x, rho: float):
+        """(F_rho(x), grad F_rho(x)) = (f + lam J_rho, grad f + lam grad J_rho)."""
+        half, g = self.grad_f(x)
+        j = tv_smooth(x, rho, grad=g, scale=self.lam)
+        return half + self.lam * j, g
+
+
+def power_iteration(plan: Plan, v0, n_iter: int = 30) -> float:
+    """Largest eigenvalue of H^T H by the power method from the start v0
+    (device tensor of the grid's shape)."""
+    v = axpby(1.0 / math.sqrt(dot_f64(v0)), v0, 0.0, v0)
+    lam = 0.0
+    for _ in range(n_iter):
+        w = plan.adjoint(plan.forward(v))
+        lam = math.sqrt(dot_f64(w))
+        v = axpby(1.0 / lam, w, 0.0, w)
+    return lam
+
+
+def _t_next(t: float) -> float:
+    return (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
+
+
+def _direct(level: Level, y, prox_iter: int):
+    """P_L(y) = prox_{alpha g}(y - alpha grad f(y))."""
+    _, g = level.grad_f(y)
+    z = axpby(1.0, y, -level.alpha, g)
+    return tv_prox(z, level.alpha * level.lam, prox_iter)
+
+
+def fista(level: Level, x0, n_iter: int, momentum: bool = True, prox_iter: int = 20,
+          eps_d: Optional[float] = None):
+    """Alg. FISTA (Alg. ISTA without momentum); returns (x, [F(x_k)])."""
+    x_prev = x0.clone()
+    y = x0.clone()
+    t = 1.0
+    hist: List[float] = []
+    for _ in range(n_iter):
+        x = _direct(level, y, prox_iter)
+        hist.append(level.objective(x))
+        tn = _t_next(t)
+        theta = (t - 1.0) / tn if momentum else 0.0
+        y = axpby(1.0 + theta, x, -theta, x_prev)
+        x_prev, t = x, tn
+        if eps_d is not None and len(hist) > 1 and hist[-2] - hist[-1] < eps_d * max(hist[-2], hist[-1]):
+            break
+    return x_prev, hist
+
+
+def coarse_fista(level: Level, x0, v, lower, rho: float, q_c: int, eps_c: float, momentum: bool = True):
+    """FISTA on phi = F_rho + <v, .> over x >= lower (the coarse proximal map
+    is the projection, section V-E); returns (x, number of updates)."""
+    def phi(x, want_grad):
+        fv, g = level.smoothed(x, rho)
+        val = fv + dot_f64(v, x)
+        if want_grad:
+            g = axpby(1.0, g, 1.0, v, out=g)
+        return val, g
+
+    x_prev = x0.clone()
+    y = x0.clone()
+    t = 1.0
+    phi_prev = phi(x_prev, False)[0]
+    k = 0
+    while k < q_c:
+        _, g = phi(y, True)
+        x = project(axpby(1.0, y, -level.alpha, g), lower)
+        k += 1
+        phi_x = phi(x, False)[0]
+        tn = _t_next(t)
+        theta = (t - 1.0) / tn if momentum else 0.0
+        y = axpby(1.0 + theta, x, -theta, x_prev)
+        x_prev, t = x, tn
+        if phi_prev - phi_x < eps_c * max(abs(phi_prev), abs(phi_x)):
+            break
+        phi_prev = phi_x
+    return x_prev, k
+
+
+@dataclass
+class MGParams:
+    """Parameters of Alg. FISTAMG and the decision rule (the paper's 2D values)."""
+    kappa: float = 0.25
+    vartheta: float = 0.1
+    q_d: int = 3
+    q_c: int = 8
+    eps_c: float = 1e-2
+    rho: float = 1e-2
+    eps_d: Optional[float] = None
+    momentum: bool = True
+    prox_iter: int = 20
+
+
+@dataclass
+class MGRecord:
+    kind: str                 # "direct" or "recursive"
+    F: float                  # F_h(x_k)
+    coarse_updates: int = 0
+    grad_ratio: float = 0.0   # ||R grad F_rho(y)|| / ||grad F_rho(y)|| at the decision
+
+
+def mg_fista(fine: Level, coarse: Level, x0, n_iter: int, params: MGParams = MGParams()):
+    """Alg. FISTAMG on two levels; returns (x, [MGRecord])."""
+    p = params
+    x_prev = x0.clone()
+    y = x0.clone()
+    t = 1.0
+    k_d = k_r = 0
+    y_tilde = None
+    hist: List[MGRecord] = []
+    for k in range(1, n_iter + 1):
+        recursive = False
+        ratio = 0.0
+        rg = None
+        if k > 1:
+            _, gF = fine.smoothed(y, p.rho)
+            rg = restrict(gF)
+            ratio = math.sqrt(dot_f64(rg)) / max(math.sqrt(dot_f64(gF)), 1e-300)
+            cond1 = ratio > p.kappa
+            far = False
+            if y_tilde is not None:
+                d = axpby(1.0, y, -1.0, y_tilde)
+                far = math.sqrt(dot_f64(d)) > p.vartheta * math.sqrt(dot_f64(y_tilde))
+            recursive = cond1 and (far or k_r == 0 or k_d > p.q_d)
+        if recursive:
+            k_d, k_r = 0, k_r + 1
+            xc0 = restrict(y)
+            _, gc = coarse.smoothed(xc0, p.rho)
+            v = axpby(1.0, rg, -1.0, gc)
+            lower = restrict_lower(y)
+            xc, nup = coarse_fista(coarse, xc0, v, lower, p.rho, p.q_c, p.eps_c, p.momentum)
+            x = axpby(1.0, y, 1.0, prolong(axpby(1.0, xc, -1.0, xc0)))
+            y_tilde = y.clone()
+            rec = MGRecord("recursive", 0.0, nup, ratio)
+        else:
+            k_d += 1
+            x = _direct(fine, y, p.prox_iter)
+            rec = MGRecord("direct", 0.0, 0, ratio)
+        rec.F = fine.objective(x)
+        hist.append(rec)
+        tn = _t_next(t)
+        theta = (t - 1.0) / tn if p.momentum else 0.0
+        y = axpby(1.0 + theta, x, -theta, x_prev)
+        x_prev, t = x, tn
+        if p.eps_d is not None and len(hist) > 1 and \
+                hist[-2].F - hist[-1].F < p.eps_d * max(hist[-2].F, hist[-1].F):
+            break
+    return x_prev, hist

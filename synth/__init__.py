@@ -333,29 +333,35 @@ def config2(instance: int = 0) -> Instance:
     return _hetero2d(2, instance, 256, 1200)
 
 
-def config3(instance: int = 0) -> Tuple[Instance, Instance]:
-    """Two multi-grid levels of one problem: 512^2 fine (dx 0.1 mm, 20-pt
-    PML, Nt 2400) and its 256^2 cell-centred coarse level (dx 0.2 mm, 10-pt
-    PML, Nt 1200, dt doubled).  Medium and phantom are continuous functions
-    drawn once and sampled on both grids; the sensors share physical
-    positions.  Both time steps are fixed here: the fine one at CFL 0.3 of the
-    fine grid's maximum sound speed, the coarse one at twice that."""
-    rng = rng_for(3, instance)
-    n, dx, pml, nt = 512, 1e-4, 20, 2400
+def two_level(cfg: int, instance: int, n: int, dx: float, pml: int, nt: int, ns: int) -> Tuple[Instance, Instance]:
+    """Two multi-grid levels of one 2D problem: an n^2 fine level and its
+    (n/2)^2 cell-centred coarse level (dx doubled, PML points halved, N_t
+    halved, dt doubled).  Medium and phantom are continuous functions drawn
+    once and sampled on both grids; the ns sensors (left half-circle of
+    radius n/2 - pml - 8 points) share physical positions.  The fine time
+    step is CFL 0.3 of the fine grid's maximum sound speed."""
+    rng = rng_for(cfg, instance)
     shape = (n, n)
     lv = ((1.0, 0.0), (2.0, 0.5))
     (c0, rho0, a0), (c0c, rho0c, a0c) = blob_medium(rng, shape, pml, levels=lv)
     radius = n / 2 - pml - 8
     p0, p0c = vessel_phantom(rng, shape, radius, levels=lv)
-    sens = half_circle_sensors(n, dx, 0.0, radius, 256)
+    sens = half_circle_sensors(n, dx, 0.0, radius, ns)
     dt_f = 0.3 * dx / float(np.max(c0))
-    fine = Instance(_desc2(n, dx, pml, nt, dt=dt_f), c0, rho0, a0, sens, p0, name="cfg3.fine")
+    fine = Instance(_desc2(n, dx, pml, nt, dt=dt_f), c0, rho0, a0, sens, p0, name=f"cfg{cfg}.fine")
     nc = n // 2
     coarse_desc = GridDesc(ndim=2, n=(nc, nc), dx=(2 * dx, 2 * dx), origin=(dx / 2, dx / 2),
                            nt=nt // 2, dt=2.0 * dt_f, cfl=0.3, pml_size=(pml // 2, pml // 2, 0),
                            pml_alpha=2.0, alpha_power=1.5, pml=True)
-    coarse = Instance(coarse_desc, c0c, rho0c, a0c, sens.copy(), p0c, name="cfg3.coarse")
+    coarse = Instance(coarse_desc, c0c, rho0c, a0c, sens.copy(), p0c, name=f"cfg{cfg}.coarse")
     return fine, coarse
+
+
+def config3(instance: int = 0) -> Tuple[Instance, Instance]:
+    """Two multi-grid levels of one problem: 512^2 fine (dx 0.1 mm, 20-pt
+    PML, Nt 2400) and its 256^2 cell-centred coarse level (dx 0.2 mm, 10-pt
+    PML, Nt 1200, dt doubled), 256 sensors."""
+    return two_level(3, instance, 512, 1e-4, 20, 2400, 256)
 
 
 def config4(instance_count: int = 48) -> List[Instance]:

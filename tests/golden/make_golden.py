@@ -13,7 +13,10 @@ comes from the GPU library.  For each case the file holds:
   img_idx    flat voxel indices kept
 
 Usage:  python tests/golden/make_golden.py [case ...]   (default: all)
-Cases: cfg2, cfg3f, cfg3c, cfg4_<i> (i = 0, 1, 16, 17, 32, 33), cfg5.
+Cases: cfg2, cfg3f, cfg3c, cfg4_<i> (i = 0, 1, 16, 17, 32, 33), cfg5, and
+cfg4_short: all 48 instances of the batch workload with the time axis cut to
+a tenth (60 / 120 / 240 samples), one file with arrays per instance
+(``data_<i>``, ``img_<i>``; sensors every 8th, voxels on a stride-8 lattice).
 """
 from __future__ import annotations
 
@@ -79,11 +82,44 @@ def make(case: str, workers: int) -> None:
     print(f"{case}: {time.time() - t0:.1f} s -> {out} ({os.path.getsize(out) / 1e6:.2f} MB)", flush=True)
 
 
+def short_instances():
+    """The 48 batch instances with N_t cut to a tenth."""
+    from dataclasses import replace
+    return [synth.Instance(replace(i.desc, nt=i.desc.nt // 10), i.c0, i.rho0, i.alpha0_db, i.sensors, i.p0, i.name)
+            for i in synth.config4()]
+
+
+def make_short(workers: int) -> None:
+    K.WORKERS = workers
+    t0 = time.time()
+    out = {}
+    for k, inst in enumerate(short_instances()):
+        op = K.make_plan(inst.desc, inst.c0, inst.rho0, inst.alpha0_db, inst.sensors)
+        data = K.forward(op, inst.p0)
+        seed, h = h_for(f"cfg4_short_{k}", inst)
+        img = K.adjoint(op, h)
+        sidx = np.arange(0, inst.ns, 8)
+        iidx = np.arange(int(np.prod(inst.desc.shape))).reshape(inst.desc.shape)[::8, ::8].ravel()
+        out[f"data_{k}"] = data[:, sidx].astype(np.float32)
+        out[f"sensor_idx_{k}"] = sidx.astype(np.int32)
+        out[f"h_seed_{k}"] = np.int64(seed)
+        out[f"img_{k}"] = img.ravel()[iidx].astype(np.float32)
+        out[f"img_idx_{k}"] = iidx.astype(np.int64)
+        out[f"nt_{k}"] = np.int64(inst.desc.nt)
+        print(f"cfg4_short {k}: {time.time() - t0:.1f} s", flush=True)
+    path = os.path.join(HERE, "cfg4_short.npz")
+    np.savez_compressed(path, **out)
+    print(f"cfg4_short -> {path} ({os.path.getsize(path) / 1e6:.2f} MB)", flush=True)
+
+
 def main():
-    cases = sys.argv[1:] or (["cfg2", "cfg3c", "cfg3f"] + [f"cfg4_{i}" for i in CFG4_IDS] + ["cfg5"])
+    cases = sys.argv[1:] or (["cfg2", "cfg3c", "cfg3f"] + [f"cfg4_{i}" for i in CFG4_IDS] + ["cfg5", "cfg4_short"])
     workers = int(os.environ.get("ORACLE_WORKERS", os.cpu_count() or 1))
     for c in cases:
-        make(c, workers)
+        if c == "cfg4_short":
+            make_short(workers)
+        else:
+            make(c, workers)
 
 
 if __name__ == "__main__":

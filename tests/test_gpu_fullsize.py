@@ -87,3 +87,48 @@ def test_fullsize_batch48():
     for k in ids:
         _check(f"cfg4_{k}", insts[k], datas[k].cpu().numpy(), imgs[k].cpu().numpy(), gold[k])
     batch.close()
+
+
+def test_batch48_short_all_instances():
+    """All 48 instances with the time axis cut to a tenth, through the
+    batched executor (default grouping, graph chunks of 32 steps, autotuned
+    column variants), each checked against the oracle.
+
+    With a tenth of the time axis the wave from many phantoms has not yet
+    reached the sampled sensors (most 512^2 instances: 240 steps carry a wave
+    about 72 points, the sensor arc is 228 points from the centre): their
+    reference data are dispersion tails up to a thousand times weaker than
+    the records where the wave has arrived (norms 1e-3 against 0.5-1.5).  The
+    GPU's error is float32 rounding of the whole wave field, about 2e-6 in
+    norm whatever the record's own strength, so a record's relative error
+    measures how early its sensors are rather than the operator.  The
+    forward error is therefore taken relative to the largest record of the
+    instance's size class (the data scale of the workload); every adjoint
+    image (a full-field quantity) is checked relative to itself."""
+    from dataclasses import replace
+    g = _load("cfg4_short")
+    insts = [synth.Instance(replace(i.desc, nt=i.desc.nt // 10), i.c0, i.rho0, i.alpha0_db, i.sensors, i.p0, i.name)
+             for i in synth.config4()]
+    plans = [pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=DEV) for i in insts]
+    batch = pat.Batch(plans)
+    p0 = [torch.from_numpy(i.p0).to(DEV) for i in insts]
+    batch.forward(p0)
+    batch.autotune(reps=2)
+    datas = batch.forward(p0)
+    hs = [torch.from_numpy(np.random.default_rng(int(g[f"h_seed_{k}"])).standard_normal(
+        (inst.desc.nt, inst.ns)).astype(np.float32)).to(DEV) for k, inst in enumerate(insts)]
+    imgs = batch.adjoint(hs)
+    torch.cuda.synchronize()
+    worst = 0.0
+    norms = [float(np.linalg.norm(g[f"data_{k}"])) for k in range(len(insts))]
+    for k, inst in enumerate(insts):
+        assert int(g[f"nt_{k}"]) == inst.desc.nt
+        ref = g[f"data_{k}"]
+        big = max(norms[j] for j in range(len(insts)) if insts[j].desc.n == inst.desc.n)
+        err = np.linalg.norm(datas[k].cpu().numpy()[:, g[f"sensor_idx_{k}"]].astype(np.float64) - ref)
+        ed = float(err / big)
+        ei = _rel(imgs[k].cpu().numpy().ravel()[g[f"img_idx_{k}"]], g[f"img_{k}"])
+        worst = max(worst, ed, ei)
+        assert ed <= TOL and ei <= TOL, (k, ed, ei)
+    print(f"cfg4_short: worst rel-L2 over 48 instances {worst:.3e}", flush=True)
+    batch.close()

@@ -1,0 +1,106 @@
+"""GPU: the operators of the two-level iteration and the ISTA / FISTA /
+MG-FISTA loops on libpat against the FP64 oracle (oracle/solver.py), on the
+same seeded inputs."""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1603_02329_amd as pat  # noqa: E402
+from paper_1603_02329_amd import solver as gsolver  # noqa: E402
+from oracle import kspace as K  # noqa: E402
+from oracle import prox, solver, transfer  # noqa: E402
+
+DEV = "cuda"
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("shape", [(37, 50), (12, 10, 8)])
+def test_tv_smooth_matches_oracle(shape):
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal(shape).astype(np.float32)
+    g0 = rng.standard_normal(shape).astype(np.float32)
+    for rho in (0.0, 0.05):
+        v_ref, g_ref = prox.tv_smooth(x.astype(np.float64), rho)
+        g = _t(g0)
+        v = pat.tv_smooth(_t(x), rho, grad=g, scale=0.7)
+        assert abs(v - v_ref) <= 1e-10 * abs(v_ref), (rho, v, v_ref)
+        assert _rel(g.cpu().numpy(), g0 + 0.7 * g_ref) <= 1e-5, rho
+    assert pat.tv_smooth(_t(x), 0.0) == pytest.approx(prox.tv_value(x), rel=1e-10)
+
+
+@pytest.mark.parametrize("shape", [(64, 48), (16, 12, 8)])
+def test_restrict_lower_axpby_project_match_oracle(shape):
+    rng = np.random.default_rng(32)
+    y = rng.standard_normal(shape).astype(np.float32)
+    lo = pat.restrict_lower(_t(y)).cpu().numpy()
+    assert np.max(np.abs(lo - transfer.restrict_lower(y))) <= 1e-6
+    a, b = rng.standard_normal(shape).astype(np.float32), rng.standard_normal(shape).astype(np.float32)
+    out = pat.axpby(1.5, _t(a), -0.25, _t(b)).cpu().numpy()
+    assert np.max(np.abs(out - (np.float32(1.5) * a - np.float32(0.25) * b))) <= 1e-6
+    lower = rng.standard_normal(shape).astype(np.float32)
+    assert np.array_equal(pat.project(_t(a), _t(lower)).cpu().numpy(), np.maximum(a, lower))
+    assert np.array_equal(pat.project(_t(a)).cpu().numpy(), np.maximum(a, 0))
+
+
+def _levels(lam=2e-3):
+    f, c = synth.two_level(90, 0, 64, 1e-4, 6, 60, 16)
+    opf = K.make_plan(f.desc, f.c0, f.rho0, f.alpha0_db, f.sensors)
+    opc = K.make_plan(c.desc, c.c0, c.rho0, c.alpha0_db, c.sensors)
+    data = K.forward(opf, f.p0.astype(np.float64)).astype(np.float32)  # FP32 data for both sides
+    v0 = np.random.default_rng(7).standard_normal(opf.shape)
+    Lf = solver.power_iteration(opf, n_iter=40, v0=v0)
+    Lc = solver.power_iteration(opc, n_iter=40, v0=transfer.restrict(v0))
+    o_f = solver.Level(opf, data.astype(np.float64), lam, 1.0 / Lf)
+    o_c = solver.Level(opc, data[::2].astype(np.float64), lam, 1.0 / Lc)
+    pf = pat.Plan(f.desc, f.c0, f.rho0, f.alpha0_db, f.sensors, device=DEV)
+    pc = pat.Plan(c.desc, c.c0, c.rho0, c.alpha0_db, c.sensors, device=DEV)
+    g_f = gsolver.Level(pf, _t(data), lam, 1.0 / Lf)
+    g_c = gsolver.Level(pc, _t(np.ascontiguousarray(data[::2])), lam, 1.0 / Lc)
+    return o_f, o_c, g_f, g_c, v0, Lf
+
+
+def test_power_iteration_matches_oracle():
+    o_f, o_c, g_f, g_c, v0, Lf = _levels()
+    est = gsolver.power_iteration(g_f.plan, _t(v0), n_iter=40)
+    assert abs(est - Lf) <= 1e-5 * Lf
+
+
+@pytest.mark.parametrize("momentum", [True, False])
+def test_fista_matches_oracle(momentum):
+    o_f, o_c, g_f, g_c, v0, Lf = _levels()
+    x0 = np.zeros(o_f.shape)
+    xo, ho = solver.fista(o_f, x0, 5, momentum=momentum)
+    xg, hg = gsolver.fista(g_f, _t(x0), 5, momentum=momentum)
+    torch.cuda.synchronize()
+    assert _rel(xg.cpu().numpy(), xo) <= 1e-4
+    assert np.allclose(hg, ho, rtol=1e-5, atol=0)
+
+
+def test_mg_fista_matches_oracle():
+    o_f, o_c, g_f, g_c, v0, Lf = _levels()
+    x0 = np.zeros(o_f.shape)
+    xo, ho = solver.mg_fista(o_f, o_c, x0, 6)
+    xg, hg = gsolver.mg_fista(g_f, g_c, _t(x0), 6)
+    torch.cuda.synchronize()
+    print("oracle:", [(r.kind, r.coarse_updates, round(r.grad_ratio, 4)) for r in ho], flush=True)
+    print("gpu:   ", [(r.kind, r.coarse_updates, round(r.grad_ratio, 4)) for r in hg], flush=True)
+    assert [r.kind for r in hg] == [r.kind for r in ho]
+    assert [r.coarse_updates for r in hg] == [r.coarse_updates for r in ho]
+    assert "recursive" in [r.kind for r in ho]
+    assert np.allclose([r.F for r in hg], [r.F for r in ho], rtol=1e-5, atol=0)
+    assert _rel(xg.cpu().numpy(), xo) <= 1e-4
+    # feasible up to the float32 rounding of y + P(x_c - R y) on the bound
+    assert xg.min().item() >= -1e-6 * xg.abs().max().item()
