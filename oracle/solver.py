@@ -45,8 +45,8 @@ import numpy as np
 
 from . import kspace, prox, transfer
 
-__all__ = ["Level", "power_iteration", "grad_f", "objective", "smoothed", "fista", "coarse_fista", "mg_fista",
-           "MGParams"]
+__all__ = ["Level", "power_iteration", "grad_f", "value_f", "objective", "smoothed", "fista", "coarse_fista",
+           "mg_fista", "MGParams"]
 
 
 @dataclass
@@ -66,6 +66,12 @@ def grad_f(level: Level, x: np.ndarray):
     """(f(x), grad f(x)) = (1/2 ||H x - p_hat||^2, H^T (H x - p_hat))."""
     r = kspace.forward(level.op, x) - level.data
     return 0.5 * float(np.sum(r * r)), kspace.adjoint(level.op, r)
+
+
+def value_f(level: Level, x: np.ndarray) -> float:
+    """f(x) alone (one forward solve)."""
+    r = kspace.forward(level.op, x) - level.data
+    return 0.5 * float(np.sum(r * r))
 
 
 def objective(level: Level, x: np.ndarray) -> float:
@@ -99,9 +105,10 @@ def _t_next(t: float) -> float:
     return (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
 
 
-def _direct(level: Level, y: np.ndarray, prox_iter: int) -> np.ndarray:
-    """P_L(y) = prox_{alpha g}(y - alpha grad f(y))."""
-    _, g = grad_f(level, y)
+def _direct(level: Level, y: np.ndarray, prox_iter: int, g: Optional[np.ndarray] = None) -> np.ndarray:
+    """P_L(y) = prox_{alpha g}(y - alpha grad f(y)) (grad f(y) given or computed)."""
+    if g is None:
+        _, g = grad_f(level, y)
     return prox.tv_prox(y - level.alpha * g, level.alpha * level.lam, prox_iter)
 
 
@@ -129,20 +136,19 @@ def coarse_fista(level: Level, x0: np.ndarray, v: np.ndarray, lower: np.ndarray,
     """FISTA on phi(x) = F_rho(x) + <v, x> over x >= lower: the proximal map
     of the smooth coarse objective is the projection (section V-E).
     Returns (x, number of updates)."""
-    def phi(x):
-        fv, g = smoothed(level, x, rho)
-        return fv + transfer.dot(v, x), g + v
+    def phi_value(x):
+        return value_f(level, x) + level.lam * prox.tv_smooth(x, rho)[0] + transfer.dot(v, x)
 
     x_prev = np.asarray(x0, dtype=np.float64)
     y = x_prev.copy()
     t = 1.0
-    phi_prev = phi(x_prev)[0]
+    phi_prev = phi_value(x_prev)
     k = 0
     while k < q_c:
-        _, g = phi(y)
-        x = np.maximum(y - level.alpha * g, lower)
+        _, g = smoothed(level, y, rho)
+        x = np.maximum(y - level.alpha * (g + v), lower)
         k += 1
-        phi_x = phi(x)[0]
+        phi_x = phi_value(x)
         tn = _t_next(t)
         theta = (t - 1.0) / tn if momentum else 0.0
         y = x + theta * (x - x_prev)
@@ -188,8 +194,11 @@ def mg_fista(fine: Level, coarse: Level, x0: np.ndarray, n_iter: int, params: MG
     for k in range(1, n_iter + 1):
         recursive = False
         ratio = 0.0
+        gf = None
         if k > 1:
-            _, gF = smoothed(fine, y, p.rho)
+            # grad f(y) serves the decision (through grad F_rho) and a direct step
+            _, gf = grad_f(fine, y)
+            gF = gf + fine.lam * prox.tv_smooth(y, p.rho)[1]
             rg = transfer.restrict(gF)
             ratio = math.sqrt(transfer.norm2(rg)) / max(math.sqrt(transfer.norm2(gF)), 1e-300)
             cond1 = ratio > p.kappa
@@ -209,7 +218,7 @@ def mg_fista(fine: Level, coarse: Level, x0: np.ndarray, n_iter: int, params: MG
             rec = MGRecord("recursive", 0.0, nup, ratio)
         else:
             k_d += 1
-            x = _direct(fine, y, p.prox_iter)
+            x = _direct(fine, y, p.prox_iter, gf)
             rec = MGRecord("direct", 0.0, 0, ratio)
         rec.F = objective(fine, x)
         hist.append(rec)

@@ -26,29 +26,40 @@ import math
 from dataclasses import dataclass
 from typing import List, Optional
 
-from . import Plan, axpby, dot_f64, project, prolong, residual_f64, restrict, restrict_lower, tv_prox, tv_smooth
+from . import Batch, Plan, axpby, dot_f64, project, prolong, residual_f64, restrict, restrict_lower, tv_prox, tv_smooth
 
 __all__ = ["Level", "MGParams", "MGRecord", "power_iteration", "fista", "coarse_fista", "mg_fista"]
 
 
-@dataclass
 class Level:
     """One grid level: plan, measured data (device, (nt, ns) float32),
-    lambda and step size."""
-    plan: Plan
-    data: object
-    lam: float
-    alpha: float
+    lambda and step size.  H and H^T run eagerly on the plan, or with
+    ``graphs`` through a one-instance batch whose time loop is replayed from
+    captured graphs (measured at 512^2: no faster; a single grid's passes
+    are bound by their own duration, not by the host's launches)."""
+
+    def __init__(self, plan: Plan, data, lam: float, alpha: float, graphs: bool = False):
+        self.plan, self.data, self.lam, self.alpha = plan, data, lam, alpha
+        self._batch = Batch([plan]) if graphs else None
+
+    def forward(self, x):
+        return self._batch.forward([x])[0] if self._batch is not None else self.plan.forward(x)
+
+    def adjoint(self, r):
+        return self._batch.adjoint([r])[0] if self._batch is not None else self.plan.adjoint(r)
 
     def grad_f(self, x):
         """(f(x), grad f(x)) with f = 1/2 ||H x - p_hat||^2."""
-        r, half = residual_f64(self.plan.forward(x), self.data)
-        return half, self.plan.adjoint(r)
+        r, half = residual_f64(self.forward(x), self.data)
+        return half, self.adjoint(r)
+
+    def value_f(self, x) -> float:
+        """f(x) alone (one forward solve)."""
+        return residual_f64(self.forward(x), self.data)[1]
 
     def objective(self, x) -> float:
         """F(x) = f(x) + lam TV(x)."""
-        _, half = residual_f64(self.plan.forward(x), self.data)
-        return half + self.lam * tv_smooth(x, 0.0)
+        return self.value_f(x) + self.lam * tv_smooth(x, 0.0)
 
     def smoothed(self, x, rho: float):
         """(F_rho(x), grad F_rho(x)) = (f + lam J_rho, grad f + lam grad J_rho)."""
@@ -73,16 +84,18 @@ def _t_next(t: float) -> float:
     return (1.0 + math.sqrt(1.0 + 4.0 * t * t)) / 2.0
 
 
-def _direct(level: Level, y, prox_iter: int):
-    """P_L(y) = prox_{alpha g}(y - alpha grad f(y))."""
-    _, g = level.grad_f(y)
+def _direct(level: Level, y, prox_iter: int, g=None):
+    """P_L(y) = prox_{alpha g}(y - alpha grad f(y)) (grad f(y) given or computed)."""
+    if g is None:
+        _, g = level.grad_f(y)
     z = axpby(1.0, y, -level.alpha, g)
     return tv_prox(z, level.alpha * level.lam, prox_iter)
 
 
 def fista(level: Level, x0, n_iter: int, momentum: bool = True, prox_iter: int = 20,
-          eps_d: Optional[float] = None):
-    """Alg. FISTA (Alg. ISTA without momentum); returns (x, [F(x_k)])."""
+          eps_d: Optional[float] = None, callback=None):
+    """Alg. FISTA (Alg. ISTA without momentum); returns (x, [F(x_k)]).
+    ``callback(k, x_k, F(x_k))`` runs after every iteration."""
     x_prev = x0.clone()
     y = x0.clone()
     t = 1.0
@@ -90,6 +103,8 @@ def fista(level: Level, x0, n_iter: int, momentum: bool = True, prox_iter: int =
     for _ in range(n_iter):
         x = _direct(level, y, prox_iter)
         hist.append(level.objective(x))
+        if callback is not None:
+            callback(len(hist), x, hist[-1])
         tn = _t_next(t)
         theta = (t - 1.0) / tn if momentum else 0.0
         y = axpby(1.0 + theta, x, -theta, x_prev)
@@ -102,23 +117,20 @@ def fista(level: Level, x0, n_iter: int, momentum: bool = True, prox_iter: int =
 def coarse_fista(level: Level, x0, v, lower, rho: float, q_c: int, eps_c: float, momentum: bool = True):
     """FISTA on phi = F_rho + <v, .> over x >= lower (the coarse proximal map
     is the projection, section V-E); returns (x, number of updates)."""
-    def phi(x, want_grad):
-        fv, g = level.smoothed(x, rho)
-        val = fv + dot_f64(v, x)
-        if want_grad:
-            g = axpby(1.0, g, 1.0, v, out=g)
-        return val, g
+    def phi_value(x):
+        return level.value_f(x) + level.lam * tv_smooth(x, rho) + dot_f64(v, x)
 
     x_prev = x0.clone()
     y = x0.clone()
     t = 1.0
-    phi_prev = phi(x_prev, False)[0]
+    phi_prev = phi_value(x_prev)
     k = 0
     while k < q_c:
-        _, g = phi(y, True)
+        _, g = level.smoothed(y, rho)
+        g = axpby(1.0, g, 1.0, v, out=g)
         x = project(axpby(1.0, y, -level.alpha, g), lower)
         k += 1
-        phi_x = phi(x, False)[0]
+        phi_x = phi_value(x)
         tn = _t_next(t)
         theta = (t - 1.0) / tn if momentum else 0.0
         y = axpby(1.0 + theta, x, -theta, x_prev)
@@ -151,8 +163,9 @@ class MGRecord:
     grad_ratio: float = 0.0   # ||R grad F_rho(y)|| / ||grad F_rho(y)|| at the decision
 
 
-def mg_fista(fine: Level, coarse: Level, x0, n_iter: int, params: MGParams = MGParams()):
-    """Alg. FISTAMG on two levels; returns (x, [MGRecord])."""
+def mg_fista(fine: Level, coarse: Level, x0, n_iter: int, params: MGParams = MGParams(), callback=None):
+    """Alg. FISTAMG on two levels; returns (x, [MGRecord]).
+    ``callback(k, x_k, record)`` runs after every iteration."""
     p = params
     x_prev = x0.clone()
     y = x0.clone()
@@ -163,9 +176,12 @@ def mg_fista(fine: Level, coarse: Level, x0, n_iter: int, params: MGParams = MGP
     for k in range(1, n_iter + 1):
         recursive = False
         ratio = 0.0
-        rg = None
+        rg = gf = None
         if k > 1:
-            _, gF = fine.smoothed(y, p.rho)
+            # grad f(y) serves the decision (through grad F_rho) and a direct step
+            _, gf = fine.grad_f(y)
+            gF = gf.clone()
+            tv_smooth(y, p.rho, grad=gF, scale=fine.lam, value=False)
             rg = restrict(gF)
             ratio = math.sqrt(dot_f64(rg)) / max(math.sqrt(dot_f64(gF)), 1e-300)
             cond1 = ratio > p.kappa
@@ -186,10 +202,12 @@ def mg_fista(fine: Level, coarse: Level, x0, n_iter: int, params: MGParams = MGP
             rec = MGRecord("recursive", 0.0, nup, ratio)
         else:
             k_d += 1
-            x = _direct(fine, y, p.prox_iter)
+            x = _direct(fine, y, p.prox_iter, gf)
             rec = MGRecord("direct", 0.0, 0, ratio)
         rec.F = fine.objective(x)
         hist.append(rec)
+        if callback is not None:
+            callback(k, x, rec)
         tn = _t_next(t)
         theta = (t - 1.0) / tn if p.momentum else 0.0
         y = axpby(1.0 + theta, x, -theta, x_prev)
