@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
   } else if constexpr (K == R_FWD_3) {
     // the spectra first; the pointwise operands after the transforms (loading
     // all of them up front would double the registers held across the FFTs)
-    float2 a1[E], a2[E], rs[E], c2[E], ct[E], ce[E];
+    float2 a1[E], a2[E], rs[E], c2[E];
     io.ld(P.S[1], a1);
     io.ld(P.S[2], a2);
     __syncthreads();  // twiddles
@@ -338,18 +338,29 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
       for (int m = 0; m < E; ++m) rs[m] = rs[m] + rj[m];
     }
     io.ld(P.c2, c2);
+    // p = c0^2 sum rho + c0^2 tau A1 - c0^2 eta A2, term by term so that no
+    // more than one coefficient array is live at a time
     if (P.alpha_uniform) {
-      absorption_coefs<E>(P, c2, ct, ce);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        float2 ct[1], ce[1];
+        const float2 cm[1] = {c2[m]};
+        absorption_coefs<1>(P, cm, ct, ce);
+        a1[m] = mul2(c2[m], rs[m]) + mul2(ct[0], a1[m]) - mul2(ce[0], a2[m]);
+      }
     } else {
-      io.ld(P.c2tau, ct);
-      io.ld(P.c2eta, ce);
+      float2 cf[E];
+      io.ld(P.c2tau, cf);
+#pragma unroll
+      for (int m = 0; m < E; ++m) a1[m] = mul2(c2[m], rs[m]) + mul2(cf[m], a1[m]);
+      io.ld(P.c2eta, cf);
+#pragma unroll
+      for (int m = 0; m < E; ++m) a1[m] = a1[m] - mul2(cf[m], a2[m]);
     }
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const float2 p = mul2(c2[m], rs[m]) + mul2(ct[m], a1[m]) - mul2(ce[m], a2[m]);
-      if (valid) check_finite(P, p);
-      a1[m] = p;
-      L[t + T * m] = p;
+      if (valid) check_finite(P, a1[m]);
+      L[t + T * m] = a1[m];
     }
     gather_row<N>(P, it + 1, Lf, rowc, t, valid);
     r2c<N>(a1, P.S[0] + io.base, L, t, valid, tws);
@@ -416,7 +427,7 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
     }
   } else if constexpr (K == R_ADJ_2) {
     const bool first = (it == 0);
-    float2 a2[E], a1[E], q[E], dr[E], qx[E], rb[D][E];
+    float2 a2[E], a1[E], q[E], dr[E], qx[E];
     io.ld(P.S[1], a2);
     io.ld(P.S[2], a1);
     __syncthreads();  // twiddles
@@ -426,25 +437,22 @@ __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restric
     io.ld(P.dtr0, dr);
     io.ldx(P.Q[0], qx);
 #pragma unroll
+    for (int m = 0; m < E; ++m) a2[m] = q[m] - a2[m];  // q - A2, shared by every axis
+    // one axis component at a time: its density, then its transform
+#pragma unroll
     for (int j = 0; j < D; ++j) {
-      if (first) io.zero(rb[j]); else io.ld(P.r[j], rb[j]);
-    }
-    float2 g[D][E];
+      float2 rb[E], g[E];
+      if (first) io.zero(rb); else io.ld(P.r[j], rb);
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const float2 qa = q[m] - a2[m];
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
+      for (int m = 0; m < E; ++m) {
         const float2 qq = qpair(j, qx[m]);
-        const float2 r1 = rb[j][m] + qa;
-        g[j][m] = mul2(dr[m], a1[m] - mul2(qq, r1));
-        rb[j][m] = mul2(mul2(qq, qq), r1);
+        const float2 r1 = rb[m] + a2[m];
+        g[m] = mul2(dr[m], a1[m] - mul2(qq, r1));
+        rb[m] = mul2(mul2(qq, qq), r1);
       }
+      io.st(P.r[j], rb);
+      r2c<N>(g, P.S[1 + j] + io.base, L, t, valid, tws);
     }
-#pragma unroll
-    for (int j = 0; j < D; ++j) io.st(P.r[j], rb[j]);
-#pragma unroll
-    for (int j = 0; j < D; ++j) r2c<N>(g[j], P.S[1 + j] + io.base, L, t, valid, tws);
   } else if constexpr (K == R_ADJ_FINAL || K == R_ADJ_SCATTER_ONLY) {
     float2 v[E], rs[E], ic[E];
     if constexpr (K == R_ADJ_FINAL) {
