@@ -207,31 +207,34 @@ def main():
     alpha = 1e-3
     lam = 1e-3
 
-    def step(run_forward, run_adjoint):
-        datas = run_forward(xs)
-        res, loss = [], 0.0
-        for d, t in zip(datas, targets):
-            r, half = pat.residual_f64(d, t)
-            res.append(r)
-            loss += half
-        grads = run_adjoint(res)
-        for k, (x, g) in enumerate(zip(xs, grads)):
-            xs[k] = pat.tv_prox(x - alpha * g, alpha * lam, 20, work=tvw[k])
+    from paper_1603_02329_amd.autograd import PatBatchLeastSquares, PatLeastSquares
+
+    def step(loss_fn):
+        """One gradient-and-prox iteration: the least-squares loss through
+        torch.autograd (forward in the Function, the adjoint as its
+        backward), then x <- prox(x - alpha grad)."""
+        leaves = [x.detach().requires_grad_(True) for x in xs]
+        loss = loss_fn(leaves)
+        loss.backward()
+        for k, x in enumerate(leaves):
+            xs[k] = pat.tv_prox(x.detach() - alpha * x.grad, alpha * lam, 20, work=tvw[k])
         return loss
 
-    batched = (batch.forward, batch.adjoint)
-    plain = (lambda X: [p.forward(x) for p, x in zip(plans, X)],
-             lambda R: [p.adjoint(r) for p, r in zip(plans, R)])
+    def batched(leaves):
+        return PatBatchLeastSquares.apply(batch, targets, *leaves)
+
+    def plain(leaves):
+        return sum(PatLeastSquares.apply(x, t, p) for x, t, p in zip(leaves, targets, plans))
 
     def timed(fns, steps, warmup, label):
         for _ in range(warmup):
-            step(*fns)
+            step(fns)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record()
         for _ in range(steps):
-            step(*fns)
+            step(fns)
         e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -273,7 +276,8 @@ def main():
             "workload": wl_name,
             "instances": len(plans),
             "gps_per_step": total_gps,
-            "executor": f"batched, graph chunk {args.chunk}",
+            "executor": f"batched, graph chunk {args.chunk}; least squares through torch.autograd "
+                        "(backward = batched adjoint)",
             "col_tiles": {f"{e['n'][0]}x{e['n'][1]}x{e['n'][2]}:{e['dir']}:{e['pass']}": e["tile"] for e in tiles},
             "plain_ms_per_step": plain_ms,
             "batched_over_plain": (plain_ms / ms) if plain_ms else None,

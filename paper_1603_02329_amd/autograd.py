@@ -23,7 +23,7 @@ import torch
 
 from . import Plan, residual_f64
 
-__all__ = ["PatOperator", "PatLeastSquares", "forward_checkpointed", "replay_segment"]
+__all__ = ["PatOperator", "PatLeastSquares", "PatBatchLeastSquares", "forward_checkpointed", "replay_segment"]
 
 
 def forward_checkpointed(plan: Plan, p0: torch.Tensor, every: int,
@@ -104,3 +104,32 @@ class PatLeastSquares(torch.autograd.Function):
         if float(grad_f) != 1.0:
             g = g * grad_f.to(torch.float32)
         return g, None, None, None
+
+
+class PatBatchLeastSquares(torch.autograd.Function):
+    """Batched f = sum_i 1/2 ||H_i p0_i - target_i||^2 (float64 scalar) over
+    the instances of a ``Batch``; the backward is the batched adjoint of the
+    residuals: grad p0_i = H_i^T (H_i p0_i - target_i) times the incoming
+    gradient.
+
+    ``PatBatchLeastSquares.apply(batch, targets, *p0s)``; targets is a list of
+    (nt_i, ns_i) float32 device tensors in the batch's plan order."""
+
+    @staticmethod
+    def forward(ctx, batch, targets, *p0s):
+        datas = batch.forward([p.detach().contiguous() for p in p0s])
+        res, total = [], 0.0
+        for d, t in zip(datas, targets):
+            r, half = residual_f64(d, t.detach().contiguous())
+            res.append(r)
+            total += half
+        ctx.batch = batch
+        ctx.save_for_backward(*res)
+        return torch.tensor(total, dtype=torch.float64, device=p0s[0].device)
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        grads = ctx.batch.adjoint(list(ctx.saved_tensors))
+        if float(grad_f) != 1.0:
+            grads = [g * grad_f.to(torch.float32) for g in grads]
+        return (None, None, *grads)
