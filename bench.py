@@ -279,6 +279,8 @@ def main():
             "executor": f"batched, graph chunk {args.chunk}; least squares through torch.autograd "
                         "(backward = batched adjoint)",
             "col_tiles": {f"{e['n'][0]}x{e['n'][1]}x{e['n'][2]}:{e['dir']}:{e['pass']}": e["tile"] for e in tiles},
+            "col_tile_policy": (tiles[0].get("policy") if tiles else None),
+            "col_tile_policy_us": (tiles[0].get("policy_us") if tiles else None),
             "plain_ms_per_step": plain_ms,
             "batched_over_plain": (plain_ms / ms) if plain_ms else None,
         },

@@ -183,8 +183,10 @@ int pat_batch_create(pat_batch** out, pat_plan* const* plans, int32_t nb, int32_
  * pat_batch_create_ex  as pat_batch_create, with the grouping explicit: the
  *   instances of one size class (same grid, nt and physics) are split into
  *   `parts` equal groups (0: the default, 2), each launched as its own work
- *   tables, and the groups run on `lanes` streams (0: one per group; group k
- *   on stream k mod lanes).  Groups on different streams overlap on the GPU.
+ *   tables, and the groups run on `lanes` streams (0: one per group; with
+ *   fewer streams than groups, the groups are placed heaviest first, by grid
+ *   points x time steps, on the least-loaded stream).  Groups on different
+ *   streams overlap on the GPU.
  *   pat_batch_create(out, plans, nb, chunk) is pat_batch_create_ex(out,
  *   plans, nb, chunk, 0, 0).  parts = 1, lanes = 1 runs one launch per pass
  *   and size class over all its instances, one launch at a time.
@@ -205,9 +207,16 @@ int pat_batch_adjoint(pat_batch* batch, const float* const* data, float* const* 
  * with columns of 128, 256 or 512 points: 16, 8 or 4 columns per
  * workgroup; 2D passes applying one multiplier per field: one or two fields
  * per workgroup), each variant is launched reps times on the batch's own
- * device buffers and timed with HIP events; the fastest is used from then
- * on.  Results stay bitwise equal to pat_forward / pat_adjoint: a variant
- * only changes how columns and fields are grouped into workgroups.
+ * device buffers and timed with HIP events.  A batch of several groups
+ * then runs its groups at the same time, where a variant that wins alone can
+ * lose (a wide workgroup needs a whole CU's worth of LDS), so a second phase
+ * times width policies in context: each policy (the fastest variant; the
+ * fastest of width <= 8; of width <= 4; of width 8) is applied to every
+ * tuned pass and timed on a short concurrent run of forward steps of all
+ * groups (the longest time axis 4 x chunk steps, the others in proportion);
+ * the fastest policy is used from then on.  Results stay bitwise equal to
+ * pat_forward / pat_adjoint: a variant only changes how columns and fields
+ * are grouped into workgroups.
  *
  *  pat_batch_autotune  reps >= 1 timed launches per candidate.  Waits for the
  *                      batch and `stream` to be idle, runs on `stream`,
@@ -217,8 +226,10 @@ int pat_batch_adjoint(pat_batch* batch, const float* const* data, float* const* 
  *  pat_tuning_report   JSON array, one object per tuned pass: class shape
  *                      n, nt, lossy, instances, direction (0 forward, 1 adjoint), pass
  *                      index, mode, nfield, axis_len, candidates
- *                      [{tile, fpb, us}] (fpb: fields per workgroup) and the
- *                      chosen tile and fpb.  Writes at most cap bytes
+ *                      [{tile, fpb, us}] (fpb: fields per workgroup), the
+ *                      chosen tile and fpb, and for a batch of several groups
+ *                      the chosen width policy and the microseconds of each
+ *                      policy timed ("policy", "policy_us").  Writes at most cap bytes
  *                      including a terminating NUL into buf (buf may be NULL
  *                      when cap is 0) and the full length without the NUL to
  *                      *needed.  Empty array "[]" before any autotune.

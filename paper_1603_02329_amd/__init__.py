@@ -264,7 +264,8 @@ class Batch:
 
     def __init__(self, plans: Sequence[Plan], chunk: int = 0, parts: int = 0, lanes: int = 0):
         """chunk: steps per captured graph (0: 32; 1: eager); parts: groups
-        per size class (0: 2); lanes: streams (0: one per group)."""
+        per size class (0: 2); lanes: streams (0: one per group; fewer:
+        groups placed heaviest first on the least-loaded stream)."""
         self.plans = list(plans)
         arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
         h = ctypes.c_void_p()

@@ -385,9 +385,16 @@ struct BatchClass {
 
 }  // namespace
 
+// Width policies of the autotuner's second phase: how a pass's variant is
+// chosen from its isolated timings.
+enum TunePolicy : int { TP_FASTEST = 0, TP_MAX8, TP_MAX4, TP_EXACT8, TP_COUNT };
+const char* const kPolicyName[TP_COUNT] = {"fastest", "width<=8", "width<=4", "width=8"};
+
 struct pat_batch {
   int chunk = 32;
   std::vector<BatchClass> cls;
+  int policy = -1;                 // width policy chosen in context (-1: none)
+  float policy_us[TP_COUNT] = {};  // its timing of each policy (0: not timed)
   void* arena = nullptr;
   std::vector<hipStream_t> lanes;  // streams the classes run on (a class uses lanes[k % size])
   hipStream_t cap = nullptr;  // capture-only stream
@@ -668,13 +675,33 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
     }
     if (!rc && hipEventCreateWithFlags(&c.done, hipEventDisableTiming) != hipSuccess) rc = PAT_EHIP;
   }
+  // Streams: by default one per group.  With fewer streams than groups, the
+  // groups go heaviest first (grid points x steps) to the least-loaded
+  // stream, so that small classes share streams with each other rather than
+  // queue behind the largest.
   const int nlanes = lanes ? std::min((int)b->cls.size(), (int)lanes) : (int)b->cls.size();
   for (int k = 0; k < nlanes && !rc; ++k) {
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) rc = PAT_EHIP;
     else b->lanes.push_back(s);
   }
-  for (size_t k = 0; k < b->cls.size() && !rc; ++k) b->cls[k].st = b->lanes[k % b->lanes.size()];
+  if (!rc) {
+    std::vector<double> work(b->cls.size());
+    std::vector<int> order(b->cls.size());
+    for (size_t k = 0; k < b->cls.size(); ++k) {
+      double pts = 0;
+      for (auto* p : b->cls[k].plans) pts += (double)p->npoints;
+      work[k] = pts * std::max(1, b->cls[k].nt - 1);
+      order[k] = (int)k;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work[x] > work[y]; });
+    std::vector<double> load(b->lanes.size(), 0.0);
+    for (int k : order) {
+      const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      b->cls[k].st = b->lanes[j];
+      load[j] += work[k];
+    }
+  }
   if (!rc && (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
               hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess))
     rc = PAT_EHIP;
@@ -704,6 +731,62 @@ extern "C" int pat_batch_adjoint(pat_batch* b, const float* const* data, float* 
 // their duration does not depend on the values, and every forward and
 // adjoint run rewrites the state from its input before reading it.  Captured
 // graphs are dropped so that the next run captures the chosen widths.
+namespace {
+
+// the candidate a width policy takes for one tuned pass
+int pick_variant(const BatchClass::Tuned& t, int policy) {
+  int best = -1, fastest = 0;
+  for (int j = 0; j < t.ncand; ++j) {
+    if (t.us[j] < t.us[fastest]) fastest = j;
+    const int w = t.cand[j].tile;
+    const bool ok = policy == TP_FASTEST || (policy == TP_MAX8 && w <= 8) || (policy == TP_MAX4 && w <= 4) ||
+                    (policy == TP_EXACT8 && w == 8);
+    if (ok && (best < 0 || t.us[j] < t.us[best])) best = j;
+  }
+  return best < 0 ? fastest : best;
+}
+
+// set the variants of every tuned pass (in class and record order) and drop
+// the captured graphs
+void apply_choice(pat_batch* b, const std::vector<ColVariant>& v) {
+  size_t k = 0;
+  for (auto& c : b->cls) {
+    for (const auto& t : c.tuned) c.vars[t.dir * kMaxOps + t.idx] = v[k++];
+    for (auto& g : c.graph)
+      if (g) {
+        hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+  }
+}
+
+// Forward steps of every group at once, the longest time axis running
+// `steps` steps and every other group a proportional number, from one fork
+// on `st` to the join of all groups.  The steps only touch plan-owned state
+// (the input and output arrays are read and written outside the steps).
+int time_concurrent(pat_batch* b, int steps, hipStream_t st, hipEvent_t e0, hipEvent_t e1, float* ms) {
+  long ntmax = 1;
+  for (const auto& c : b->cls) ntmax = std::max(ntmax, (long)c.nt - 1);
+  if (hipEventRecord(e0, st) != hipSuccess) return PAT_EHIP;
+  for (auto& c : b->cls) {
+    if (hipStreamWaitEvent(c.st, e0, 0) != hipSuccess) return PAT_EHIP;
+    const long n = std::min<long>(c.nt - 1, ((long)steps * (c.nt - 1) + ntmax - 1) / ntmax);
+    if (n > 0) {
+      const int rc = run_steps(b, c, 0, (int)n);
+      if (rc) return rc;
+    }
+    if (hipEventRecord(c.done, c.st) != hipSuccess) return PAT_EHIP;
+  }
+  for (auto& c : b->cls)
+    if (hipStreamWaitEvent(st, c.done, 0) != hipSuccess) return PAT_EHIP;
+  if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+      hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+    return PAT_EHIP;
+  return PAT_OK;
+}
+
+}  // namespace
+
 extern "C" int pat_batch_autotune(pat_batch* b, int32_t reps, void* stream) {
   if (!b || reps < 1) return PAT_EINVAL;
   hipStream_t st = (hipStream_t)stream;
@@ -753,6 +836,41 @@ extern "C" int pat_batch_autotune(pat_batch* b, int32_t reps, void* stream) {
       }
     if (rc) break;
   }
+  // Second phase, for batches of several groups: the groups run at the same
+  // time, and a wide tile that wins alone (one 1024-thread block per CU with
+  // most of its LDS) can lose when other groups' blocks hold part of a CU.
+  // Each width policy is applied to every tuned pass and timed on a short
+  // concurrent run of forward steps of every group; the fastest is kept.
+  b->policy = -1;
+  for (auto& u : b->policy_us) u = 0.f;
+  if (!rc && b->cls.size() > 1) {
+    std::vector<std::vector<ColVariant>> choice(TP_COUNT);
+    int best = -1;
+    for (int pol = 0; pol < TP_COUNT && !rc; ++pol) {
+      for (auto& c : b->cls)
+        for (const auto& t : c.tuned) choice[pol].push_back(t.cand[pick_variant(t, pol)]);
+      bool same = false;
+      for (int q = 0; q < pol && !same; ++q)
+        same = b->policy_us[q] > 0.f && std::equal(choice[q].begin(), choice[q].end(), choice[pol].begin(),
+                                                   [](const ColVariant& x, const ColVariant& y) {
+                                                     return x.tile == y.tile && x.fpb == y.fpb;
+                                                   });
+      if (same) continue;
+      apply_choice(b, choice[pol]);
+      float ms = 0.f, best_ms = 0.f;
+      for (int r = 0; r < 3 && !rc; ++r) {  // the first run captures the graphs
+        rc = time_concurrent(b, 4 * b->chunk, st, e0, e1, &ms);
+        if (r == 1 || (r > 1 && ms < best_ms)) best_ms = ms;
+      }
+      if (rc) break;
+      b->policy_us[pol] = 1e3f * best_ms;
+      if (best < 0 || b->policy_us[pol] < b->policy_us[best]) best = pol;
+    }
+    if (!rc && best >= 0) {
+      apply_choice(b, choice[best]);
+      b->policy = best;
+    }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   return rc;
@@ -785,8 +903,21 @@ extern "C" int pat_tuning_report(const pat_batch* b, char* buf, size_t cap, size
         s += tmp;
       }
       const ColVariant& ch = c.vars[t.dir * kMaxOps + t.idx];
-      std::snprintf(tmp, sizeof tmp, "],\"tile\":%d,\"fpb\":%d}", ch.tile, ch.fpb);
+      std::snprintf(tmp, sizeof tmp, "],\"tile\":%d,\"fpb\":%d", ch.tile, ch.fpb);
       s += tmp;
+      if (b->policy >= 0) {
+        std::snprintf(tmp, sizeof tmp, ",\"policy\":\"%s\",\"policy_us\":{", kPolicyName[b->policy]);
+        s += tmp;
+        bool firstp = true;
+        for (int q = 0; q < TP_COUNT; ++q) {
+          if (b->policy_us[q] <= 0.f) continue;
+          std::snprintf(tmp, sizeof tmp, "%s\"%s\":%.1f", firstp ? "" : ",", kPolicyName[q], (double)b->policy_us[q]);
+          s += tmp;
+          firstp = false;
+        }
+        s += "}";
+      }
+      s += "}";
     }
   }
   s += "]";

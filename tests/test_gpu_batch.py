@@ -127,6 +127,17 @@ def test_autotune_keeps_results_bitwise(ndim):
         assert e["axis_len"] in (128, 256, 512)
     if ndim == 3:
         assert all(e["n"] == [32, 32, 128] and e["mode"] <= 2 for e in rep)
+    # several groups: one width policy, timed in context, the fastest kept,
+    # and every pass's variant the best of its isolated timings under it
+    assert len({e["policy"] for e in rep}) == 1
+    us = rep[0]["policy_us"]
+    assert us[rep[0]["policy"]] <= min(us.values()) + 0.1
+    rule = {"fastest": lambda w: True, "width<=8": lambda w: w <= 8, "width<=4": lambda w: w <= 4,
+            "width=8": lambda w: w == 8}[rep[0]["policy"]]
+    for e in rep:
+        allowed = [v for v in e["candidates"] if rule(v["tile"])] or e["candidates"]
+        chosen = [v for v in allowed if (v["tile"], v["fpb"]) == (e["tile"], e["fpb"])]
+        assert chosen and chosen[0]["us"] <= min(v["us"] for v in allowed) + 1e-3
     b.close()
 
 
