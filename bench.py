@@ -45,7 +45,8 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-KERNEL_SOURCES = ("paper_1603_02329_amd/csrc/passes_row.hip", "paper_1603_02329_amd/csrc/passes_common.h",
+KERNEL_SOURCES = ("paper_1603_02329_amd/csrc/passes_fused.hip", "paper_1603_02329_amd/csrc/passes_row.h",
+                  "paper_1603_02329_amd/csrc/passes_col.h", "paper_1603_02329_amd/csrc/passes_common.h",
                   "paper_1603_02329_amd/csrc/fft.h", "paper_1603_02329_amd/csrc/pat_internal.h")
 
 
@@ -56,6 +57,28 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def fused_batch(plans) -> bool:
+    """Whether the library's batch of these plans fuses its size classes
+    into shared launches (2D, both axes 128/256/512, nt >= 2, more than one
+    size class of the same physics)."""
+    classes = {}
+    for p in plans:
+        n = p.desc.n
+        if len(n) != 2 or any(v not in (128, 256, 512) for v in n) or p.desc.nt < 2:
+            continue
+        classes.setdefault(p.lossy, set()).add((tuple(n), p.desc.nt))
+    return any(len(v) > 1 for v in classes.values())
+
+
+def row_kernel_name(plans, kind: int) -> str:
+    """Kernel symbol (as rocprofv3 prints it) of row-pass kind `kind` over
+    the one-stream batch of these plans."""
+    if fused_batch(plans):
+        return f"k_rowf<2, {kind}>"
+    nx = max(p.desc.n[0] for p in plans)
+    return f"k_row<{nx}, {len(plans[0].desc.n)}, {kind}>"
 
 
 def counter_traffic(kernel: str):
@@ -174,10 +197,10 @@ def main():
 
     def isolated_kernel(reps=200):
         """The selected pass on its own: `reps` back-to-back launches over a
-        one-stream batch with one group per size class (each launch covers
-        every instance of the largest size and has the GPU to itself), timed
-        with HIP events around the burst.  Returns (ms total, launches,
-        algorithmic bytes total)."""
+        one-stream batch with one group (size classes fused into one launch
+        where the library fuses them, else the largest size's launch), every
+        launch having the GPU to itself, timed with HIP events around the
+        burst.  Returns (ms total, launches, algorithmic bytes total)."""
         b1 = pat.Batch(plans, chunk=1, parts=1, lanes=1)
         us, by = b1.time_pass(tdir, tidx, nx_dom, reps)
         b1.close()
@@ -291,11 +314,14 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": counter_traffic("k_row<512, 2, 1>") if (tdir, tidx) == (0, 1) else None,
+            "kernel_symbol": row_kernel_name(plans, 1) if (tdir, tidx) == (0, 1) else None,
+            "traffic": counter_traffic(row_kernel_name(plans, 1)) if (tdir, tidx) == (0, 1) else None,
             "launches": k_n,
             "avg_launch_us": (k_ms / k_n * 1e3) if k_n else None,
             "measured_in": "back-to-back launches of the pass over a one-stream batch before the timed "
-                           "region (each launch: every instance of the largest size, GPU to itself)",
+                           "region (each launch: " + ("every instance of the batch, its size classes fused"
+                                                      if fused_batch(plans) else "every instance of the largest "
+                                                      "size") + "; GPU to itself)",
             "in_timed_region": {
                 "launches": s_n,
                 "avg_launch_us": (s_ms / s_n * 1e3) if s_n else None,

@@ -44,6 +44,9 @@ extern "C" {
 #define PAT_NO_PML        0x1u  /* switch the PML off: periodic grid             */
 #define PAT_CHECK_FINITE  0x2u  /* record non-finite pressure; see pat_plan_sync */
 
+/* pat_batch_create_ex flags */
+#define PAT_BATCH_NO_FUSE 0x1u  /* keep every size class in launches of its own */
+
 /*
  * Grid, time axis and physics of one solver instance (one multi-grid level).
  *
@@ -187,12 +190,22 @@ int pat_batch_create(pat_batch** out, pat_plan* const* plans, int32_t nb, int32_
  *   fewer streams than groups, the groups are placed heaviest first, by grid
  *   points x time steps, on the least-loaded stream).  Groups on different
  *   streams overlap on the GPU.
+ *   Fusion (default; flags PAT_BATCH_NO_FUSE turns it off): 2D size classes
+ *   whose axes are 128, 256 or 512 points long, with the same physics and
+ *   nt >= 2, share their launches -- part k of each such class joins fused
+ *   group k, whose every pass is one launch over the tiles of all its
+ *   instances.  The group's time loop has as many steps as its longest
+ *   instance (max nt - 1); an instance with S = nt - 1 steps runs its step
+ *   floor(n S / span) at the loop steps n where that value advances, so
+ *   each of its steps runs once and in order, spread evenly over the loop.
+ *   Short classes then ride in the launches of the long ones instead of
+ *   queueing short launches of their own beside them.
  *   pat_batch_create(out, plans, nb, chunk) is pat_batch_create_ex(out,
- *   plans, nb, chunk, 0, 0).  parts = 1, lanes = 1 runs one launch per pass
- *   and size class over all its instances, one launch at a time.
+ *   plans, nb, chunk, 0, 0, 0).  parts = 1, lanes = 1 runs one launch per
+ *   pass and group, one launch at a time.  PAT_EINVAL for unknown flags.
  */
 int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int32_t nb, int32_t chunk, int32_t parts,
-                        int32_t lanes);
+                        int32_t lanes, uint32_t flags);
 void pat_batch_destroy(pat_batch* batch);
 int pat_batch_forward(pat_batch* batch, const float* const* p0, float* const* data, void* stream);
 int pat_batch_adjoint(pat_batch* batch, const float* const* data, float* const* img, void* stream);

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpat.so")
 PAT_OK, PAT_EINVAL, PAT_EUNSTABLE, PAT_ENOMEM, PAT_EHIP, PAT_ENONFINITE, PAT_ENOSYS = range(7)
 PAT_NO_PML = 0x1
 PAT_CHECK_FINITE = 0x2
+PAT_BATCH_NO_FUSE = 0x1
 
 #: every symbol include/pat.h declares
 EXPORTED = [
@@ -81,7 +82,7 @@ def lib() -> ctypes.CDLL:
         "pat_adjoint": (ctypes.c_int, [vp, vp, vp, vp]),
         "pat_forward_range": (ctypes.c_int, [vp, vp, vp, i32, i32, vp, vp]),
         "pat_batch_create": (ctypes.c_int, [pp, pp, i32, i32]),
-        "pat_batch_create_ex": (ctypes.c_int, [pp, pp, i32, i32, i32, i32]),
+        "pat_batch_create_ex": (ctypes.c_int, [pp, pp, i32, i32, i32, i32, ctypes.c_uint32]),
         "pat_batch_destroy": (None, [vp]),
         "pat_batch_forward": (ctypes.c_int, [vp, pp, pp, vp]),
         "pat_batch_adjoint": (ctypes.c_int, [vp, pp, pp, vp]),
@@ -262,14 +263,18 @@ class Plan:
 class Batch:
     """Many plans run together (one launch per pass over all instances)."""
 
-    def __init__(self, plans: Sequence[Plan], chunk: int = 0, parts: int = 0, lanes: int = 0):
+    def __init__(self, plans: Sequence[Plan], chunk: int = 0, parts: int = 0, lanes: int = 0, fuse: bool = True):
         """chunk: steps per captured graph (0: 32; 1: eager); parts: groups
         per size class (0: 2); lanes: streams (0: one per group; fewer:
-        groups placed heaviest first on the least-loaded stream)."""
+        groups placed heaviest first on the least-loaded stream); fuse: 2D
+        size classes of axes 128/256/512 share their launches (see
+        pat_batch_create_ex)."""
         self.plans = list(plans)
+        self._opts = (int(chunk), int(parts), int(lanes), bool(fuse))
         arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
         h = ctypes.c_void_p()
-        _check(lib().pat_batch_create_ex(ctypes.byref(h), arr, len(self.plans), int(chunk), int(parts), int(lanes)),
+        _check(lib().pat_batch_create_ex(ctypes.byref(h), arr, len(self.plans), int(chunk), int(parts), int(lanes),
+                                         0 if fuse else PAT_BATCH_NO_FUSE),
                "pat_batch_create_ex")
         self._h = h
 
@@ -332,25 +337,20 @@ class Batch:
     def autotune(self, reps: int = 20, cache: Optional[str] = None) -> list:
         """Pick the column tile widths by timing (pat_batch_autotune).
 
-        With ``cache`` (a JSON file), choices stored there for this device
-        architecture and every class of the batch are applied without timing;
-        otherwise the batch is timed and its report merged into the file.
+        With ``cache`` (a JSON file), the choices stored there for this
+        device architecture and this batch composition (size classes with
+        their instance counts, grouping options) are applied without timing;
+        otherwise the batch is timed and its report stored in the file.
         Returns the report entries in force."""
         arch = _arch()
-        entries = None
+        key = self._batch_key()
         if cache and os.path.exists(cache):
             with open(cache) as f:
-                stored = json.load(f).get(arch, {})
-            entries = []
-            for key in self._class_keys():
-                if key not in stored:
-                    entries = None
-                    break
-                entries += stored[key]
-        if entries is not None:
-            for e in entries:
-                self.set_tile(e)
-            return entries
+                entries = json.load(f).get(arch, {}).get(key)
+            if entries is not None:
+                for e in entries:
+                    self.set_tile(e)
+                return entries
         _check(lib().pat_batch_autotune(self._h, int(reps), _stream()), "pat_batch_autotune")
         rep = self.tuning_report()
         if cache:
@@ -358,32 +358,25 @@ class Batch:
             if os.path.exists(cache):
                 with open(cache) as f:
                     data = json.load(f)
-            by = data.setdefault(arch, {})
-            for key in self._class_keys():
-                by[key] = [e for e in rep if self._entry_key(e) == key]
+            data.setdefault(arch, {})[key] = rep
             tmp = cache + ".tmp"
             with open(tmp, "w") as f:
                 json.dump(data, f, indent=1)
             os.replace(tmp, cache)
         return rep
 
-    def _key(self, n, nt, lossy) -> str:
-        """Cache key of one size class: grid, time samples, physics, and how
-        many instances of it the batch holds (the timing depends on it)."""
-        n = [int(v) for v in n]
-        count = sum(1 for p in self.plans if _grid3(p) == n and p.nt == nt and p.lossy == bool(lossy))
-        return f"{n[0]}x{n[1]}x{n[2]}/nt{nt}/{'lossy' if lossy else 'lossless'}/i{count}"
-
-    def _class_keys(self) -> list:
-        keys = []
+    def _batch_key(self) -> str:
+        """Cache key of the batch: every size class (grid, time samples,
+        physics, instance count) and the grouping options -- the timings of
+        one class depend on what runs beside it."""
+        count = {}
         for p in self.plans:
-            k = self._key(_grid3(p), p.nt, p.lossy)
-            if k not in keys:
-                keys.append(k)
-        return keys
-
-    def _entry_key(self, e) -> str:
-        return self._key(e["n"], e["nt"], e["lossy"])
+            n = _grid3(p)
+            k = f"{n[0]}x{n[1]}x{n[2]}/nt{p.nt}/{'lossy' if p.lossy else 'lossless'}"
+            count[k] = count.get(k, 0) + 1
+        chunk, parts, lanes, fuse = self._opts
+        return ";".join(f"{k}/i{v}" for k, v in sorted(count.items())) + \
+            f"|chunk{chunk}/parts{parts}/lanes{lanes}/{'fused' if fuse else 'unfused'}"
 
 
 def _grid3(plan) -> list:

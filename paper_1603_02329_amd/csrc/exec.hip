@@ -157,6 +157,8 @@ constexpr int kColW = 4;  // column tile widths a batch holds work tables for
 
 struct Runner {
   int ndim, nx, ny, nz, nt, lossy;
+  int fused = 0;  // fused launches over instances of several sizes (passes_fused.hip)
+  int span = 0;   // fused: steps of the longest instance
   const DevPlan* recs;
   const int2 *row_tab, *red_tab;
   int row_n, red_n;
@@ -166,15 +168,40 @@ struct Runner {
   int col_ns[kColW], col_ws[kColW], col_bpi[kColW], ncolw;
   const ColVariant* vars;  // chosen variant of pass [dir * kMaxOps + idx] (tile 0: default)
   double points;     // grid points covered by one launch (all instances)
+  // fused: per instance grid points and nt (host arrays of ninst entries)
+  const double* inst_points = nullptr;
+  const int* inst_nt = nullptr;
+  int ninst = 0;
 
+  // grid points of the instances a launch at step `step` runs (a fused
+  // launch inside the time loop skips the instances not due at that step)
+  double points_at(const StepArg& sa) const {
+    if (!fused || sa.span <= 0 || sa.ctr) return points;
+    double p = 0;
+    for (int i = 0; i < ninst; ++i) {
+      const long S = inst_nt[i] - 1;
+      if (((long)sa.k + 1) * S / sa.span > (long)sa.k * S / sa.span) p += inst_points[i];
+    }
+    return p;
+  }
   int op(int dir, int idx, const PassOp& o, StepArg sa, hipStream_t st, bool timed) const {
     if (timed) {
-      const TimeScope ts(dir, idx, nx, pass_bytes_per_point(o, ndim, lossy) * points);
+      const TimeScope ts(dir, idx, nx, pass_bytes_per_point(o, ndim, lossy) * points_at(sa));
       return launch1(dir, idx, o, sa, st, ts.e0, ts.e1);
     }
     return launch1(dir, idx, o, sa, st, nullptr, nullptr);
   }
-  int launch_col_w(ColSpec s, ColVariant v, hipStream_t st, hipEvent_t e0, hipEvent_t e1) const {
+  int launch_col_w(ColSpec s, ColVariant v, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                   StepArg sa = StepArg{nullptr, 0}) const {
+    if (fused) {
+      if (v.tile == 0) v = ColVariant{8, 1};
+      for (int j = 0; j < ncolw; ++j)
+        if (col_ws[j] == v.tile)
+          return launch_col_fused(s, v, Launch{recs, col_tabs[j], col_ns[j], st, e0, e1}, sa) == hipSuccess
+                     ? PAT_OK
+                     : PAT_EHIP;
+      return PAT_EHIP;
+    }
     s.tile = v.tile;
     s.fpb = v.fpb;
     v = col_variant_of(s, ndim, ny, nz);
@@ -189,15 +216,15 @@ struct Runner {
     return launch_col(s, ndim, nx, ny, nz, Launch{recs, tab, n, st, e0, e1}) == hipSuccess ? PAT_OK : PAT_EHIP;
   }
   int launch1(int dir, int idx, const PassOp& o, StepArg sa, hipStream_t st, hipEvent_t e0, hipEvent_t e1) const {
-    if (o.is_col) return launch_col_w(o.col, vars ? vars[dir * kMaxOps + idx] : ColVariant{0, 1}, st, e0, e1);
-    hipError_t e;
-    {
-      e = launch_row(o.row, ndim, nx, Launch{recs, row_tab, row_n, st, e0, e1}, sa);
-    }
+    if (o.is_col) return launch_col_w(o.col, vars ? vars[dir * kMaxOps + idx] : ColVariant{0, 1}, st, e0, e1, sa);
+    const Launch L{recs, row_tab, row_n, st, e0, e1};
+    const hipError_t e = fused ? launch_row_fused(o.row, L, sa) : launch_row(o.row, ndim, nx, L, sa);
     return e == hipSuccess ? PAT_OK : PAT_EHIP;
   }
   int row(RowKind k, StepArg sa, hipStream_t st) const {
-    return launch_row(k, ndim, nx, Launch{recs, row_tab, row_n, st}, sa) == hipSuccess ? PAT_OK : PAT_EHIP;
+    const Launch L{recs, row_tab, row_n, st};
+    const hipError_t e = fused ? launch_row_fused(k, L, sa) : launch_row(k, ndim, nx, L, sa);
+    return e == hipSuccess ? PAT_OK : PAT_EHIP;
   }
   int reduce(int n0, int n1, hipStream_t st, int blocks) const {
     return launch_reduce(Launch{recs, red_tab, blocks, st}, n0, n1) == hipSuccess ? PAT_OK : PAT_EHIP;
@@ -208,7 +235,7 @@ struct Runner {
     const int nops = step_ops(dir, ndim, lossy, ops);
     int rc = PAT_OK;
     for (int s = s0; s < s1 && !rc; ++s)
-      for (int i = 0; i < nops && !rc; ++i) rc = op(dir, i, ops[i], StepArg{nullptr, s}, st, true);
+      for (int i = 0; i < nops && !rc; ++i) rc = op(dir, i, ops[i], StepArg{nullptr, s, span}, st, true);
     return rc;
   }
 };
@@ -332,6 +359,12 @@ namespace {
 
 struct BatchClass {
   int ndim, nx, ny, nz, nt, lossy, ns_max;
+  // fused group: instances of several 2D sizes in every launch (nx, ny the
+  // largest, nt - 1 = span = the most steps of any instance)
+  int fused = 0;
+  std::vector<std::pair<int, int>> shapes;  // fused: the (nx, ny) it holds
+  std::vector<double> inst_points;          // per instance: grid points and nt
+  std::vector<int> inst_nt;
   std::vector<pat_plan*> plans;
   std::vector<int> index;  // position of each plan in the caller's list
   DevPlan* recs = nullptr;
@@ -363,6 +396,11 @@ struct BatchClass {
     r.nz = nz;
     r.nt = nt;
     r.lossy = lossy;
+    r.fused = fused;
+    r.span = fused ? nt - 1 : 0;
+    r.inst_points = inst_points.data();
+    r.inst_nt = inst_nt.data();
+    r.ninst = (int)inst_nt.size();
     r.recs = recs;
     r.row_tab = row_tab;
     r.red_tab = red_tab;
@@ -428,7 +466,7 @@ int capture(pat_batch* b, BatchClass& c, int dir) {
   if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return PAT_EHIP;
   int rc = PAT_OK;
   for (int k = 0; k < b->chunk && !rc; ++k)
-    for (int i = 0; i < nops && !rc; ++i) rc = R.op(dir, i, ops[i], StepArg{c.ctr, k}, b->cap, false);
+    for (int i = 0; i < nops && !rc; ++i) rc = R.op(dir, i, ops[i], StepArg{c.ctr, k, R.span}, b->cap, false);
   if (!rc) {
     hipLaunchKernelGGL(k_add_ctr, dim3(1), dim3(1), 0, b->cap, c.ctr, b->chunk);
     if (hipGetLastError() != hipSuccess) rc = PAT_EHIP;
@@ -514,14 +552,15 @@ int batch_run(pat_batch* b, int dir, const float* const* in, float* const* out, 
 }  // namespace
 
 extern "C" int pat_batch_create(pat_batch** out, pat_plan* const* plans, int32_t nb, int32_t chunk) {
-  return pat_batch_create_ex(out, plans, nb, chunk, 0, 0);
+  return pat_batch_create_ex(out, plans, nb, chunk, 0, 0, 0);
 }
 
 extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int32_t nb, int32_t chunk, int32_t parts,
-                                   int32_t lanes) {
+                                   int32_t lanes, uint32_t flags) {
   if (!out) return PAT_EINVAL;
   *out = nullptr;
-  if (!plans || nb < 1 || chunk < 0 || parts < 0 || lanes < 0) return PAT_EINVAL;
+  if (!plans || nb < 1 || chunk < 0 || parts < 0 || lanes < 0 || (flags & ~(uint32_t)PAT_BATCH_NO_FUSE))
+    return PAT_EINVAL;
   for (int i = 0; i < nb; ++i)
     if (!plans[i] || plans[i]->desc.ndim != plans[0]->desc.ndim) return PAT_EINVAL;
   auto* b = new (std::nothrow) pat_batch();
@@ -536,6 +575,7 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
   // launches no longer fill the GPU).
   const int split = parts ? parts : 2;
   std::vector<std::vector<int>> groups;
+  std::vector<int> group_fused;
   {
     std::map<std::tuple<int, int, int, int, int>, int> key2grp;
     std::vector<std::vector<int>> shape_groups;
@@ -549,13 +589,49 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
       }
       shape_groups[it->second].push_back(i);
     }
+    // Fusion: 2D size classes whose axes are 128, 256 or 512 points (and
+    // the same physics) share their launches.  Part k of every such class
+    // forms fused group k, its instances ordered largest grid first.
+    auto fusable = [&](const std::vector<int>& g) {
+      const pat_plan* p = plans[g[0]];
+      return !(flags & PAT_BATCH_NO_FUSE) && p->desc.ndim == 2 && fused_size(p->hp.n[0]) &&
+             fused_size(p->hp.n[1]) && p->desc.nt >= 2;
+    };
+    auto area = [&](const std::vector<int>& g) { return (long)plans[g[0]]->hp.n[0] * plans[g[0]]->hp.n[1]; };
+    for (int lossy = 0; lossy < 2; ++lossy) {
+      std::vector<int> fs;
+      for (size_t k = 0; k < shape_groups.size(); ++k)
+        if (plans[shape_groups[k][0]]->lossy == lossy && fusable(shape_groups[k])) fs.push_back((int)k);
+      if (fs.size() < 2) continue;
+      std::stable_sort(fs.begin(), fs.end(), [&](int x, int y) {
+        const long ax = area(shape_groups[x]), ay = area(shape_groups[y]);
+        return ax != ay ? ax > ay : plans[shape_groups[x][0]]->hp.n[0] > plans[shape_groups[y][0]]->hp.n[0];
+      });
+      for (int k = 0; k < split; ++k) {
+        std::vector<int> g;
+        for (int s : fs) {
+          const std::vector<int>& sg = shape_groups[s];
+          const size_t np = std::min(sg.size(), (size_t)split);
+          if ((size_t)k < np) g.insert(g.end(), sg.begin() + sg.size() * k / np, sg.begin() + sg.size() * (k + 1) / np);
+        }
+        if (!g.empty()) {
+          groups.push_back(g);
+          group_fused.push_back(1);
+        }
+      }
+      for (int s : fs) shape_groups[s].clear();
+    }
     for (auto& g : shape_groups) {
+      if (g.empty()) continue;
       const size_t parts = std::min(g.size(), (size_t)split);
-      for (size_t k = 0; k < parts; ++k)
+      for (size_t k = 0; k < parts; ++k) {
         groups.emplace_back(g.begin() + g.size() * k / parts, g.begin() + g.size() * (k + 1) / parts);
+        group_fused.push_back(0);
+      }
     }
   }
-  for (const auto& g : groups) {
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const auto& g = groups[gi];
     const pat_plan* p0 = plans[g[0]];
     BatchClass c{};
     c.ndim = p0->desc.ndim;
@@ -564,11 +640,17 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
     c.nz = p0->hp.n[2];
     c.nt = p0->desc.nt;
     c.lossy = p0->lossy;
+    c.fused = group_fused[gi];
     c.ns_max = 0;
     for (int i : g) {
       c.plans.push_back(plans[i]);
       c.index.push_back(i);
       c.ns_max = std::max(c.ns_max, plans[i]->desc.n_sensors);
+      c.nt = std::max(c.nt, plans[i]->desc.nt);
+      c.inst_points.push_back((double)plans[i]->npoints);
+      c.inst_nt.push_back(plans[i]->desc.nt);
+      const std::pair<int, int> sh(plans[i]->hp.n[0], plans[i]->hp.n[1]);
+      if (c.fused && std::find(c.shapes.begin(), c.shapes.end(), sh) == c.shapes.end()) c.shapes.push_back(sh);
     }
     b->cls.push_back(std::move(c));
   }
@@ -594,7 +676,7 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
     // and a z-axis pass of one width tile the same number of columns only
     // when ny == nz, so the table is per (width, axis)
     std::vector<std::pair<int, int>> widths;  // (width, blocks per instance)
-    for (int dir = 0; dir < 2; ++dir) {
+    for (int dir = 0; dir < 2 && !c.fused; ++dir) {
       PassOp ops[kMaxOps];
       const int nops = step_ops(dir, c.ndim, c.lossy, ops);
       for (int i = 0; i < nops; ++i) {
@@ -620,23 +702,49 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
     // an instance runs on the same XCD and re-reads what the previous pass
     // of that instance left in that XCD's L2.
     const int ninst = (int)c.plans.size();
-    auto interleave = [&](std::vector<int2>& tab, int tiles) {
-      for (int g0 = 0; g0 < ninst; g0 += kXcds) {
-        const int gn = std::min(kXcds, ninst - g0);
+    // runs of up to eight instances of one grid shape (a fused group lists
+    // its instances by shape); tiles_of(instance) work items each
+    auto interleave = [&](std::vector<int2>& tab, auto tiles_of) {
+      for (int g0 = 0; g0 < ninst;) {
+        int gn = 1;
+        while (g0 + gn < ninst && gn < kXcds && c.plans[g0 + gn]->hp.n[0] == c.plans[g0]->hp.n[0] &&
+               c.plans[g0 + gn]->hp.n[1] == c.plans[g0]->hp.n[1])
+          ++gn;
+        const int tiles = tiles_of(c.plans[g0]);
         for (int t = 0; t < tiles; ++t)
           for (int l = 0; l < gn; ++l) tab.push_back(make_int2(g0 + l, t));
+        g0 += gn;
       }
     };
-    interleave(rt[k], rows_per);
-    c.ncolw = (int)widths.size();
-    for (int j = 0; j < c.ncolw; ++j) {
-      interleave(ct[k][j], widths[j].second);
-      c.col_ws[j] = widths[j].first;
-      c.col_bpi[j] = widths[j].second;
-      c.col_ns[j] = (int)ct[k][j].size();
+    if (c.fused) {
+      interleave(rt[k], [](const pat_plan* p) {
+        const int R2 = fused_row_rows(p->hp.n[0]);
+        return (p->hp.n[1] + R2 - 1) / R2;
+      });
+      const int fw[2] = {8, 4};
+      c.ncolw = 2;
+      for (int j = 0; j < 2; ++j) {
+        interleave(ct[k][j], [&](const pat_plan* p) {
+          const int w = fused_col_tile(p->hp.n[1], fw[j]);
+          return (p->hp.n[0] / 2 + w - 1) / w;
+        });
+        c.col_ws[j] = fw[j];
+        c.col_bpi[j] = 0;
+        c.col_ns[j] = (int)ct[k][j].size();
+      }
+    } else {
+      interleave(rt[k], [&](const pat_plan*) { return rows_per; });
+      c.ncolw = (int)widths.size();
+      for (int j = 0; j < c.ncolw; ++j) {
+        const int bpi = widths[j].second;
+        interleave(ct[k][j], [&](const pat_plan*) { return bpi; });
+        c.col_ws[j] = widths[j].first;
+        c.col_bpi[j] = widths[j].second;
+        c.col_ns[j] = (int)ct[k][j].size();
+      }
     }
     for (int i = 0; i < ninst; ++i) {
-      const int rb = reduce_blocks(c.nt, c.plans[i]->desc.n_sensors);
+      const int rb = reduce_blocks(c.plans[i]->desc.nt, c.plans[i]->desc.n_sensors);
       for (int t = 0; t < rb; ++t) dt[k].push_back(make_int2(i, t));
     }
     c.row_n = (int)rt[k].size();
@@ -809,7 +917,7 @@ extern "C" int pat_batch_autotune(pat_batch* b, int32_t reps, void* stream) {
         BatchClass::Tuned t{};
         t.dir = dir;
         t.idx = i;
-        t.ncand = col_variants(ops[i].col, c.ndim, c.ny, c.nz, t.cand);
+        t.ncand = c.fused ? col_variants_fused(ops[i].col, t.cand) : col_variants(ops[i].col, c.ndim, c.ny, c.nz, t.cand);
         if (t.ncand < 2) continue;
         const Runner R = c.runner();
         int best = 0;
@@ -892,10 +1000,19 @@ extern "C" int pat_tuning_report(const pat_batch* b, char* buf, size_t cap, size
       const ColSpec& cs = ops[t.idx].col;
       std::snprintf(tmp, sizeof tmp,
                     "%s{\"n\":[%d,%d,%d],\"nt\":%d,\"lossy\":%d,\"instances\":%d,\"dir\":%d,\"pass\":%d,"
-                    "\"mode\":%d,\"nfield\":%d,\"axis_len\":%d,\"candidates\":[",
+                    "\"mode\":%d,\"nfield\":%d,\"axis_len\":%d,",
                     firsto ? "" : ",", c.nx, c.ny, c.nz, c.nt, c.lossy, (int)c.plans.size(), t.dir, t.idx, cs.mode,
                     cs.nfield, col_axis_len(cs, c.ndim, c.ny, c.nz));
       s += tmp;
+      if (c.fused) {
+        s += "\"fused\":[";
+        for (size_t q = 0; q < c.shapes.size(); ++q) {
+          std::snprintf(tmp, sizeof tmp, "%s[%d,%d]", q ? "," : "", c.shapes[q].first, c.shapes[q].second);
+          s += tmp;
+        }
+        s += "],";
+      }
+      s += "\"candidates\":[";
       firsto = false;
       for (int j = 0; j < t.ncand; ++j) {
         std::snprintf(tmp, sizeof tmp, "%s{\"tile\":%d,\"fpb\":%d,\"us\":%.3f}", j ? "," : "", t.cand[j].tile,
@@ -943,7 +1060,7 @@ extern "C" int pat_batch_set_tile(pat_batch* b, const int32_t n[3], int32_t nt, 
     ColVariant v{tile, fields_per_block};
     if (tile) {
       ColVariant cand[kMaxColVar];
-      const int nc = col_variants(ops[pass].col, c.ndim, c.ny, c.nz, cand);
+      const int nc = c.fused ? col_variants_fused(ops[pass].col, cand) : col_variants(ops[pass].col, c.ndim, c.ny, c.nz, cand);
       bool ok = false;
       for (int j = 0; j < nc; ++j) ok |= (cand[j].tile == tile && cand[j].fpb == fields_per_block);
       if (!ok) return PAT_EINVAL;

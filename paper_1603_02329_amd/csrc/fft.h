@@ -158,8 +158,11 @@ __host__ __device__ constexpr int staged_len(int M, int E) { return staged_off(M
 __device__ __forceinline__ constexpr int pad8(int a) { return a + (a >> 3); }
 
 // One Stockham stage of span L (product of the radices already applied).
-// TWS: TwStrided table length TWS * M (1 or 2); PAD: padded exchange layout.
-template <int M, int E, int SIGN, int L, class Sync, int TWS, int LAY = TwStrided, bool PAD = false>
+// TWS: TwStrided table length TWS * M (1 or 2); PAD: padded exchange layout;
+// STOP: the span at which to stop -- the stage that reaches it writes its
+// values to the exchange region and returns before any barrier (M: run to
+// the end, the last stage leaving its values in registers).
+template <int M, int E, int SIGN, int L, class Sync, int TWS, int LAY = TwStrided, bool PAD = false, int STOP = M>
 struct FftStage {
   static constexpr int T = M / E;
   static constexpr int R = fft_radix(M, E, L);
@@ -195,12 +198,12 @@ struct FftStage {
         for (int i = 0; i < R; ++i) lds[at(base + i * L)] = x[i];
       }
     }
-    if constexpr (!LAST) {
+    if constexpr (!LAST && L * R != STOP) {
       Sync::sync();
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = lds[at(t + T * m)];
       Sync::sync();
-      FftStage<M, E, SIGN, L * R, Sync, TWS, LAY, PAD>::run(v, lds, t, tw);
+      FftStage<M, E, SIGN, L * R, Sync, TWS, LAY, PAD, STOP>::run(v, lds, t, tw);
     }
   }
 };
@@ -214,6 +217,40 @@ template <int M, int E, int SIGN, class Sync = BlockSync, int TWS = 1, int LAY =
 __device__ __forceinline__ void fft(float2 (&v)[E], float2* lds, int t, const Tw* tw) {
   static_assert((M & (M - 1)) == 0 && M >= E && M <= TWN, "unsupported FFT length");
   FftStage<M, E, SIGN, 1, Sync, TWS, LAY, PAD>::run(v, lds, t, tw);
+}
+
+// The same transform in pieces, for callers that hold a transform's values
+// in different threads at its two ends (the column passes load and store
+// with the column fastest across lanes, but transform with a column's lanes
+// consecutive): each piece ends with its values written to, or starts with
+// them read from, the exchange region at t + T m, and the caller places the
+// barrier between the two thread mappings.
+__host__ __device__ constexpr int fft_last_span(int M, int E) {
+  int L = 1;
+  while (L * fft_radix(M, E, L) < M) L *= fft_radix(M, E, L);
+  return L;
+}
+// first stage: butterflies of the thread's values, written to the region
+template <int M, int E, int SIGN, int LAY, bool PAD>
+__device__ __forceinline__ void fft_head(float2 (&v)[E], float2* lds, int t) {
+  static_assert(fft_radix(M, E, 1) < M, "the transform has a single stage");
+  FftStage<M, E, SIGN, 1, WaveSync, 1, LAY, PAD, fft_radix(M, E, 1)>::run(v, lds, t, nullptr);
+}
+// the stages after the first, on values read at t + T m of its output
+template <int M, int E, int SIGN, class Sync, int LAY, bool PAD>
+__device__ __forceinline__ void fft_tail(float2 (&v)[E], float2* lds, int t, const Tw* tw) {
+  FftStage<M, E, SIGN, fft_radix(M, E, 1), Sync, 1, LAY, PAD>::run(v, lds, t, tw);
+}
+// every stage but the last: the last exchange's values are left in the region
+template <int M, int E, int SIGN, class Sync, int LAY, bool PAD>
+__device__ __forceinline__ void fft_body(float2 (&v)[E], float2* lds, int t, const Tw* tw) {
+  static_assert(fft_radix(M, E, 1) < M, "the transform has a single stage");
+  FftStage<M, E, SIGN, 1, Sync, 1, LAY, PAD, fft_last_span(M, E)>::run(v, lds, t, tw);
+}
+// the last stage, on values read at t + T m of the region (no LDS access)
+template <int M, int E, int SIGN, int LAY, bool PAD>
+__device__ __forceinline__ void fft_last(float2 (&v)[E], int t, const Tw* tw) {
+  FftStage<M, E, SIGN, fft_last_span(M, E), WaveSync, 1, LAY, PAD>::run(v, nullptr, t, tw);
 }
 
 // Fill a TwStaged table for transforms of length M (E values per thread)

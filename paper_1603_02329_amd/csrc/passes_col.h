@@ -208,28 +208,39 @@ struct SyncOf<true> {
   using type = WaveSync;
 };
 
+// LDS of one column-pass block: the tile's column regions (padded
+// exchange, odd stride), the spectrum of packed column 0 (source of its
+// mirror bins) and the staged twiddles
+template <int NA, int TW>
+struct ColLds {
+  static constexpr int LDT = NA + NA / 8 + 1;
+  static constexpr int TWL = staged_len(NA, ColGeo<NA, TW>::E);
+  float2 lds[ColGeo<NA, TW>::TILE * LDT];
+  float2 lmir[NA];
+  Tw tws[TWL > 0 ? TWL : 1];
+};
+
+// One column pass over tile `tile_index` of instance P (ColGeo<NA, TW>::NTH
+// threads); the field of a per-field pass is blockIdx.y.
 template <int NA, int MODE, int NF, int FAM, int TW, int FPB>
-__global__ void __launch_bounds__((ColGeo<NA, TW>::NTH)) k_colm(const DevPlan* __restrict__ plans,
-                                                               const int2* __restrict__ table, ColSpec spec) {
+__device__ __forceinline__ void colm_pass(const DevPlan& P, int tile_index, const ColSpec& spec,
+                                          ColLds<NA, TW>& sh) {
   using G = ColGeo<NA, TW>;
   constexpr int E = G::E, TC = G::TC, TILE = G::TILE;
-  constexpr int LDT = NA + NA / 8 + 1;      // column region: padded exchange, odd stride
-  constexpr int TWL = staged_len(NA, E);
+  constexpr int LDT = ColLds<NA, TW>::LDT;
   using Sync = typename SyncOf<(TC <= 64)>::type;
   constexpr int NIN = (MODE == 0) ? 1 : (MODE == 1 ? FPB : NF);  // input fields per block
   constexpr bool UPFRONT = NIN <= 2;
-  __shared__ float2 lds[TILE * LDT];
-  __shared__ float2 lmir[NA];  // spectrum of packed column 0 (source of its mirror bins)
-  __shared__ Tw tws[TWL > 0 ? TWL : 1];
+  float2* const lds = sh.lds;
+  float2* const lmir = sh.lmir;
+  Tw* const tws = sh.tws;
   load_staged_twiddles<NA, E, G::NTH>(tws, g_tw);
-  const int2 job = table ? table[blockIdx.x] : make_int2(0, (int)blockIdx.x);
-  const DevPlan& P = plans[job.x];
   // mapping A (memory): column ca, position ta; mapping B (transforms): column cb, lane tb
   const int ca = threadIdx.x % TILE, ta = threadIdx.x / TILE;
   const int cb = threadIdx.x / TC, tb = threadIdx.x % TC;
-  const ColPos qa = col_pos<TILE>(P, job.y, ca, false);
+  const ColPos qa = col_pos<TILE>(P, tile_index, ca, false);
   if (!qa.ok) return;  // block-uniform
-  const ColPos q = col_pos<TILE>(P, job.y, cb, false);
+  const ColPos q = col_pos<TILE>(P, tile_index, cb, false);
   float2* La = lds + ca * LDT;
   float2* Lb = lds + cb * LDT;
   const bool special = q.tile0 && q.selfpair;  // block holds a packed column 0 (block-uniform)
@@ -299,31 +310,19 @@ __global__ void __launch_bounds__((ColGeo<NA, TW>::NTH)) k_colm(const DevPlan* _
       }
     }
   };
-  // memory-mapped values v (mapping A) -> transform-mapped s (mapping B)
-  auto a_to_b = [&](const float2 (&v)[E], float2 (&s)[E]) {
+  // Forward transform of one input (mapping A in, spectrum in mapping B
+  // out): the first stage runs in mapping A, where each thread already holds
+  // the eight values of its butterfly, and its exchange carries the values
+  // over to mapping B; a block holding column 0 keeps that column's spectrum
+  // in LDS for its mirror bins.  v is overwritten.
+  auto forward = [&](float2 (&v)[E], float2 (&s)[E]) {
     __syncthreads();  // earlier readers of the regions are done
-#pragma unroll
-    for (int m = 0; m < E; ++m) La[pad8(ta + TC * m)] = v[m];
+    fft_head<NA, E, -1, TwStaged, true>(v, La, ta);
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < E; ++m) s[m] = Lb[pad8(tb + TC * m)];
     Sync::sync();  // the transform reuses the region
-  };
-  auto b_to_a = [&](const float2 (&s)[E], float2 (&v)[E]) {
-    Sync::sync();  // the transform's last exchange reads are done
-#pragma unroll
-    for (int m = 0; m < E; ++m) Lb[pad8(tb + TC * m)] = s[m];
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = La[pad8(ta + TC * m)];
-    __syncthreads();  // the regions are free for the next transform
-  };
-  // forward transform of one input (mapping A in, spectrum in mapping B out);
-  // a block holding column 0 keeps that column's spectrum in LDS for its
-  // mirror bins
-  auto forward = [&](const float2 (&v)[E], float2 (&s)[E]) {
-    a_to_b(v, s);
-    fft<NA, E, -1, Sync, 1, TwStaged, true>(s, Lb, tb, tws);
+    fft_tail<NA, E, -1, Sync, TwStaged, true>(s, Lb, tb, tws);
     if (special) {
       if (fix) {
 #pragma unroll
@@ -332,10 +331,17 @@ __global__ void __launch_bounds__((ColGeo<NA, TW>::NTH)) k_colm(const DevPlan* _
       Sync::sync();
     }
   };
+  // inverse transform (mapping B in) and store (mapping A): every stage but
+  // the last in mapping B, whose final exchange carries the values over to
+  // mapping A for the last stage
   auto inverse_store = [&](float2 (&acc)[E], float2* __restrict__ dst) {
-    fft<NA, E, +1, Sync, 1, TwStaged, true>(acc, Lb, tb, tws);
+    fft_body<NA, E, +1, Sync, TwStaged, true>(acc, Lb, tb, tws);
+    __syncthreads();
     float2 v[E];
-    b_to_a(acc, v);
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = La[pad8(ta + TC * m)];
+    __syncthreads();  // the regions are free for the next transform
+    fft_last<NA, E, +1, TwStaged, true>(v, ta, tws);
     col_store<NA, TC>(dst, qa, ta, v);
   };
 
@@ -373,6 +379,14 @@ __global__ void __launch_bounds__((ColGeo<NA, TW>::NTH)) k_colm(const DevPlan* _
       }
     }
   }
+}
+
+template <int NA, int MODE, int NF, int FAM, int TW, int FPB>
+__global__ void __launch_bounds__((ColGeo<NA, TW>::NTH)) k_colm(const DevPlan* __restrict__ plans,
+                                                               const int2* __restrict__ table, ColSpec spec) {
+  __shared__ ColLds<NA, TW> sh;
+  const int2 job = table ? table[blockIdx.x] : make_int2(0, (int)blockIdx.x);
+  colm_pass<NA, MODE, NF, FAM, TW, FPB>(plans[job.x], job.y, spec, sh);
 }
 
 // multiplier family from the kinds: derivatives a_j / b_j listed in axis

@@ -1,486 +1,20 @@
-// Time-step passes of the k-space scheme on gfx950.
-//
-// Each spectral operator F^-1[m F f] of the scheme is split into two kinds
-// of passes over HBM:
-//   row pass    : per grid row (x fastest), inverse real FFT along x of the
-//                 incoming packed spectra -> the pointwise part of the step
-//                 (velocity, density, state or their transposes, PML, sensor
-//                 gather/scatter) -> forward real FFT along x of the fields the
-//                 next spectral operator needs;
-//   column pass : per tile of x-frequency columns, FFT along y (and z), the
-//                 k-space multiplier, inverse FFT along y (and z).
-// Between passes only packed x-spectra (4 bytes per grid point and field)
-// and the state fields travel through memory; the pressure itself never
-// does.  The multipliers are formed on the fly from 1-D per-axis tables.
-//
-// The forward step (equations mom, mass, state of section II-A, split per
-// axis for the PML) is
-//   col  : S1,S2 <- a_x, a_y applied to S0 = F_x p             (gradient)
-//   row 1: u_j   <- Qsg_j (Qsg_j u_j - B_j d_j p);  S_j <- F_x u_j
-//   col  : S_j   <- b_j applied to S_j                          (divergence)
-//   row 2: rho_j <- Q_j (Q_j rho_j - dt rho0 g_j);  S1 <- F_x(dt rho0 sum g),
-//                                                   S2 <- F_x(sum rho)
-//   col  : S1 <- |k|^(y-2)/dt S1, S2 <- |k|^(y-1) S2            (absorption)
-//   row 3: p = c0^2 sum rho + c0^2 tau A1 - c0^2 eta A2; gather; S0 <- F_x p
-// and the adjoint runs the transposed passes in reverse order.
+// Time-step passes of the k-space scheme on gfx950: the per-length row pass
+// kernels (bodies in passes_row.h), the sensor-sum reduction and the
+// launchers.
 #include <algorithm>
 
-#include "passes_common.h"
+#include "passes_row.h"
 
 namespace pat {
-
-// ------------------------------------------------------------------ geometry
-template <int N>
-struct RowGeo {
-  static constexpr int M = N / 2;             // packed complex bins per row
-  static constexpr int E = (M < 8) ? M : 8;   // values per thread
-  static constexpr int T = M / E;             // threads per row
-  static constexpr int ROWS = (256 / T) < 16 ? (256 / T) : 16;
-  static constexpr int NTH = ROWS * T;
-  static constexpr int LDR = M + M / 8;       // LDS slots per row (padded FFT exchange)
-  static constexpr int TWS = staged_len(M, E);  // staged FFT twiddles
-};
-
-// LDS twiddles of a row pass: the untangling factors exp(-2 pi i k / N),
-// k < M, then the staged FFT tables
-template <int N>
-struct RowTw {
-  Tw u[N / 2];
-  Tw s[RowGeo<N>::TWS > 0 ? RowGeo<N>::TWS : 1];
-};
-template <int N>
-__device__ __forceinline__ void load_row_twiddles(RowTw<N>& tw, const Tw* __restrict__ g) {
-  using G = RowGeo<N>;
-  for (int q = threadIdx.x; q < G::M; q += G::NTH) tw.u[q] = g[q * (TWN / N)];
-  load_staged_twiddles<G::M, G::E, G::NTH>(tw.s, g);
-}
-
-// Packed half spectrum of one row -> real row, as pairs (x[2n], x[2n+1]) at
-// n = t + T m.  Unnormalised inverse real DFT.
-// r holds the packed bins X[t + T m] on entry (already loaded) and the real
-// pairs on exit.
-template <int N>
-__device__ __forceinline__ void c2r(float2 (&r)[RowGeo<N>::E], float2* L, int t, const RowTw<N>& tw) {
-  using G = RowGeo<N>;
-  constexpr int M = G::M, E = G::E, T = G::T;
-#pragma unroll
-  for (int m = 0; m < E; ++m) L[t + T * m] = r[m];
-  WaveSync::sync();
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int k = t + T * m;
-    const float2 X = L[k];
-    if (k == 0) {
-      r[m] = f2(X.x + X.y, X.x - X.y);
-    } else {
-      const float2 Y = conjf2(L[M - k]);
-      const float2 A = X + Y;
-      const float2 B = twmul<+1>(X - Y, tw.u[k]);
-      r[m] = A + mul_si<+1>(B);
-    }
-  }
-  WaveSync::sync();
-  fft<M, E, +1, WaveSync, 1, TwStaged, true>(r, L, t, tw.s);
-}
-
-// Real row held as pairs (x[2n], x[2n+1]) -> packed half spectrum stored at dst.
-template <int N>
-__device__ __forceinline__ void r2c(float2 (&r)[RowGeo<N>::E], float2* __restrict__ dst, float2* L, int t,
-                                    bool valid, const RowTw<N>& tw) {
-  using G = RowGeo<N>;
-  constexpr int M = G::M, E = G::E, T = G::T;
-  fft<M, E, -1, WaveSync, 1, TwStaged, true>(r, L, t, tw.s);
-#pragma unroll
-  for (int m = 0; m < E; ++m) L[t + T * m] = r[m];
-  WaveSync::sync();
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int k = t + T * m;
-    const float2 Z = L[k];
-    float2 X;
-    if (k == 0) {
-      X = f2(Z.x + Z.y, Z.x - Z.y);
-    } else {
-      const float2 Y = conjf2(L[M - k]);
-      const float2 A = Z + Y;
-      const float2 B = twmul<-1>(Z - Y, tw.u[k]);
-      X = 0.5f * (A + mul_si<-1>(B));
-    }
-    if (valid) gst(dst, k, X);
-  }
-  WaveSync::sync();
-}
-
-// Sensor gather of sample `n` from the real row p held in LDS (as floats).
-template <int N>
-__device__ __forceinline__ void gather_row(const DevPlan& P, int n, const float* Lf, int row, int t, bool valid) {
-  using G = RowGeo<N>;
-  WaveSync::sync();
-  if (valid) {
-    const int e1 = gld(P.g_ptr, row + 1);
-    float* out = P.partial + (long)n * P.nslots;
-    for (int e = gld(P.g_ptr, row) + t; e < e1; e += G::T) {
-      const GTap tap = gld(P.g_tap, e);
-      gst(out, tap.slot, fmaf(tap.w0, Lf[tap.x0], tap.w1 * Lf[tap.x0 + 1]));
-    }
-  }
-  WaveSync::sync();
-}
-
-// Add W^T h[n] for this row to the real row held in LDS (as floats).
-template <int N>
-__device__ __forceinline__ void scatter_row(const DevPlan& P, int n, float* Lf, int row, int t, bool valid) {
-  using G = RowGeo<N>;
-  WaveSync::sync();
-  if (valid) {
-    const int g1 = gld(P.s_ptr, row + 1);
-    const float* h = P.in + (long)n * P.ns;
-    for (int g = gld(P.s_ptr, row) + t; g < g1; g += G::T) {
-      const SGroup grp = gld(P.s_grp, g);
-      float acc = 0.f;
-      for (int e = grp.beg; e < grp.end; ++e) {
-        const STap tp = gld(P.s_tap, e);
-        acc = fmaf(tp.w, gld(h, tp.s), acc);
-      }
-      Lf[grp.x] += acc;
-    }
-  }
-  WaveSync::sync();
-}
-
-// c0^2 tau and c0^2 eta from c0^2 when alpha0 is uniform (equation Twelve:
-// tau = -2 a0 c0^(y-1), eta = 2 a0 c0^y tan(pi y / 2))
-template <int E>
-__device__ __forceinline__ void absorption_coefs(const DevPlan& P, const float2 (&c2)[E], float2 (&ct)[E],
-                                                 float2 (&ce)[E]) {
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const float lx = __builtin_amdgcn_logf(c2[m].x), ly = __builtin_amdgcn_logf(c2[m].y);
-    ct[m] = f2(P.ktau * __builtin_amdgcn_exp2f(P.etau * lx), P.ktau * __builtin_amdgcn_exp2f(P.etau * ly));
-    ce[m] = f2(P.keta * __builtin_amdgcn_exp2f(P.eeta * lx), P.keta * __builtin_amdgcn_exp2f(P.eeta * ly));
-  }
-}
-
-__device__ __forceinline__ void check_finite(const DevPlan& P, float2 v) {
-  if ((P.flags & PAT_CHECK_FINITE) && !(isfinite(v.x) && isfinite(v.y))) atomicOr(P.bad, 1);
-}
-
-// ------------------------------------------------------------------ row passes
-// Each row pass first issues every global load it needs (the packed input
-// spectra and the per-point state and medium values of its rows) so that the
-// memory latency is paid once per block, then runs the transforms from
-// registers.  The velocity passes treat one axis component per block
-// (blockIdx.y): the components are independent, and the split halves the
-// registers a block holds.
-template <int N>
-struct RowIo {
-  static constexpr int E = RowGeo<N>::E, T = RowGeo<N>::T;
-  const long base;
-  const int t;
-  const bool valid;
-  __device__ __forceinline__ void ld(const float* a, float2 (&v)[E]) const {
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = valid ? ld2(a, base + t + T * m) : f2(0.f, 0.f);
-  }
-  __device__ __forceinline__ void ld(const float2* a, float2 (&v)[E]) const {
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = valid ? gld(a, base + t + T * m) : f2(0.f, 0.f);
-  }
-  // 1-D x table (PML factor along x), pairs at n = t + T m
-  __device__ __forceinline__ void ldx(const float* a, float2 (&v)[E]) const {
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = ld2(a, t + T * m);
-  }
-  __device__ __forceinline__ void st(float* a, const float2 (&v)[E]) const {
-    if (!valid) return;
-#pragma unroll
-    for (int m = 0; m < E; ++m) st2(a, base + t + T * m, v[m]);
-  }
-  __device__ __forceinline__ void zero(float2 (&v)[E]) const {
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = f2(0.f, 0.f);
-  }
-};
 
 template <int N, int D, int K>
 __global__ void __launch_bounds__(RowGeo<N>::NTH) k_row(const DevPlan* __restrict__ plans,
                                                         const int2* __restrict__ table, StepArg sa) {
   using G = RowGeo<N>;
-  constexpr int M = G::M, E = G::E, T = G::T;
   __shared__ float2 lds[G::ROWS * G::LDR];
   __shared__ RowTw<N> tws;
-  load_row_twiddles<N>(tws, g_tw);
   const int2 job = table ? table[blockIdx.x] : make_int2(0, (int)blockIdx.x);
-  const DevPlan& P = plans[job.x];
-  const int rl = threadIdx.x / T, t = threadIdx.x % T;
-  const int row = job.y * G::ROWS + rl;
-  const bool valid = row < P.nrows;
-  const int rowc = valid ? row : 0;
-  const int ny = P.n[1];
-  const int yy = rowc % ny, zz = rowc / ny;
-  float2* L = lds + rl * G::LDR;
-  float* Lf = reinterpret_cast<float*>(L);
-  const RowIo<N> io{(long)rowc * M, t, valid};
-  const int it = step_of(sa);  // forward step n / adjoint iteration i
-
-  // per-row PML factors of the y and z axes
-  float qrow[3] = {1.f, gld(P.Q[1], yy), 1.f};
-  float qsrow[3] = {1.f, gld(P.Qsg[1], yy), 1.f};
-  if constexpr (D == 3) {
-    qrow[2] = gld(P.Q[2], zz);
-    qsrow[2] = gld(P.Qsg[2], zz);
-  }
-  auto qpair = [&](int j, const float2& qx) { return j == 0 ? qx : f2(qrow[j], qrow[j]); };
-  auto qspair = [&](int j, const float2& qx) { return j == 0 ? qx : f2(qsrow[j], qsrow[j]); };
-
-  if constexpr (K == R_FWD_INIT) {
-    float2 p[E], ic[E];
-    io.ld(P.in, p);
-    io.ld(P.inv_dc2, ic);
-    __syncthreads();  // twiddles
-    float2 rr[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      rr[m] = mul2(p[m], ic[m]);
-      L[t + T * m] = p[m];
-    }
-#pragma unroll
-    for (int j = 0; j < D; ++j) io.st(P.r[j], rr);
-    gather_row<N>(P, 0, Lf, rowc, t, valid);
-    r2c<N>(p, P.S[0] + io.base, L, t, valid, tws);
-  } else if constexpr (K == R_FWD_1 || K == R_ADJ_1) {
-    // one axis component j per block
-    const int j = (int)blockIdx.y;
-    const bool first = (it == 0);
-    const bool last = (K == R_ADJ_1) && (it == P.nt - 2);
-    float2 d[E], b[E], u[E], qx[E];
-    io.ld(P.S[1 + j], d);
-    io.ld(P.B[j], b);
-    if (first) io.zero(u); else io.ld(P.u[j], u);
-    if (j == 0) io.ldx(P.Qsg[0], qx);
-    __syncthreads();  // twiddles
-    c2r<N>(d, L, t, tws);
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const float2 qs = qspair(j, qx[m]);
-      if constexpr (K == R_FWD_1) {
-        // u <- Qsg (Qsg u - B d p); the first step starts from u = (B/2) d p
-        const float2 db = mul2(b[m], d[m]);
-        const float2 u0 = first ? scl2(0.5f, db) : u[m];
-        u[m] = mul2(qs, mul2(qs, u0) - db);
-        d[m] = u[m];
-      } else {
-        // ubar -= d+ gbar; feed B Qsg ubar (last step: B Qsg ubar (1 - Qsg/2)), ubar <- Qsg^2 ubar
-        const float2 ub = u[m] - d[m];
-        const float2 bq = mul2(b[m], mul2(qs, ub));
-        d[m] = last ? mul2(bq, f2(1.f - 0.5f * qs.x, 1.f - 0.5f * qs.y)) : bq;
-        u[m] = mul2(mul2(qs, qs), ub);
-      }
-    }
-    if (K == R_FWD_1 || !last) io.st(P.u[j], u);
-    r2c<N>(d, P.S[1 + j] + io.base, L, t, valid, tws);
-  } else if constexpr (K == R_FWD_2 || K == R_FWD_2LL) {
-    float2 g[D][E], r[D][E], dr[E], c2[E], qx[E];
-#pragma unroll
-    for (int j = 0; j < D; ++j) io.ld(P.S[1 + j], g[j]);
-#pragma unroll
-    for (int j = 0; j < D; ++j) io.ld(P.r[j], r[j]);
-    io.ld(P.dtr0, dr);
-    if constexpr (K == R_FWD_2LL) io.ld(P.c2, c2);
-    io.ldx(P.Q[0], qx);
-    __syncthreads();  // twiddles
-#pragma unroll
-    for (int j = 0; j < D; ++j) c2r<N>(g[j], L, t, tws);
-    float2 sdiv[E], srho[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      sdiv[m] = f2(0.f, 0.f);
-      srho[m] = f2(0.f, 0.f);
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        const float2 q = qpair(j, qx[m]);
-        const float2 tj = mul2(dr[m], g[j][m]);
-        r[j][m] = mul2(q, mul2(q, r[j][m]) - tj);
-        sdiv[m] = sdiv[m] + tj;
-        srho[m] = srho[m] + r[j][m];
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < D; ++j) io.st(P.r[j], r[j]);
-    if constexpr (K == R_FWD_2) {
-      r2c<N>(sdiv, P.S[1] + io.base, L, t, valid, tws);
-      r2c<N>(srho, P.S[2] + io.base, L, t, valid, tws);
-    } else {
-#pragma unroll
-      for (int m = 0; m < E; ++m) {
-        srho[m] = mul2(c2[m], srho[m]);
-        if (valid) check_finite(P, srho[m]);
-        L[t + T * m] = srho[m];
-      }
-      gather_row<N>(P, it + 1, Lf, rowc, t, valid);
-      r2c<N>(srho, P.S[0] + io.base, L, t, valid, tws);
-    }
-  } else if constexpr (K == R_FWD_3) {
-    // the spectra first; the pointwise operands after the transforms (loading
-    // all of them up front would double the registers held across the FFTs)
-    float2 a1[E], a2[E], rs[E], c2[E];
-    io.ld(P.S[1], a1);
-    io.ld(P.S[2], a2);
-    __syncthreads();  // twiddles
-    c2r<N>(a1, L, t, tws);
-    c2r<N>(a2, L, t, tws);
-    io.ld(P.r[0], rs);
-#pragma unroll
-    for (int j = 1; j < D; ++j) {
-      float2 rj[E];
-      io.ld(P.r[j], rj);
-#pragma unroll
-      for (int m = 0; m < E; ++m) rs[m] = rs[m] + rj[m];
-    }
-    io.ld(P.c2, c2);
-    // p = c0^2 sum rho + c0^2 tau A1 - c0^2 eta A2, term by term so that no
-    // more than one coefficient array is live at a time
-    if (P.alpha_uniform) {
-#pragma unroll
-      for (int m = 0; m < E; ++m) {
-        float2 ct[1], ce[1];
-        const float2 cm[1] = {c2[m]};
-        absorption_coefs<1>(P, cm, ct, ce);
-        a1[m] = mul2(c2[m], rs[m]) + mul2(ct[0], a1[m]) - mul2(ce[0], a2[m]);
-      }
-    } else {
-      float2 cf[E];
-      io.ld(P.c2tau, cf);
-#pragma unroll
-      for (int m = 0; m < E; ++m) a1[m] = mul2(c2[m], rs[m]) + mul2(cf[m], a1[m]);
-      io.ld(P.c2eta, cf);
-#pragma unroll
-      for (int m = 0; m < E; ++m) a1[m] = a1[m] - mul2(cf[m], a2[m]);
-    }
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      if (valid) check_finite(P, a1[m]);
-      L[t + T * m] = a1[m];
-    }
-    gather_row<N>(P, it + 1, Lf, rowc, t, valid);
-    r2c<N>(a1, P.S[0] + io.base, L, t, valid, tws);
-  } else if constexpr (K == R_ADJ_3 || K == R_ADJ_32LL) {
-    const bool first = (it == 0);
-    const int nsamp = P.nt - 1 - it;  // h[n+1] with n = nt-2-it
-    float2 v[E], c2[E], e1[E], e2[E], dr[E], qx[E];
-    if (first) io.zero(v); else io.ld(P.S[0], v);
-    io.ld(P.c2, c2);
-    if constexpr (K == R_ADJ_3) {
-      if (P.alpha_uniform) {
-        absorption_coefs<E>(P, c2, e2, e1);
-      } else {
-        io.ld(P.c2eta, e1);
-        io.ld(P.c2tau, e2);
-      }
-    } else {
-      io.ld(P.dtr0, dr);
-      io.ldx(P.Q[0], qx);
-    }
-    float2 rb[D][E];
-    if constexpr (K == R_ADJ_32LL) {
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        if (first) io.zero(rb[j]); else io.ld(P.r[j], rb[j]);
-      }
-    }
-    __syncthreads();  // twiddles
-    if (!first) c2r<N>(v, L, t, tws);
-#pragma unroll
-    for (int m = 0; m < E; ++m) L[t + T * m] = v[m];
-    scatter_row<N>(P, nsamp, Lf, rowc, t, valid);
-#pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = L[t + T * m];
-    WaveSync::sync();
-    if constexpr (K == R_ADJ_3) {
-      float2 q[E];
-#pragma unroll
-      for (int m = 0; m < E; ++m) {
-        q[m] = mul2(c2[m], v[m]);
-        e1[m] = mul2(e1[m], v[m]);
-        e2[m] = mul2(e2[m], v[m]);
-      }
-      io.st(P.q, q);
-      r2c<N>(e1, P.S[1] + io.base, L, t, valid, tws);
-      r2c<N>(e2, P.S[2] + io.base, L, t, valid, tws);
-    } else {
-      float2 g[D][E];
-#pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const float2 q = mul2(c2[m], v[m]);
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-          const float2 qq = qpair(j, qx[m]);
-          const float2 r1 = rb[j][m] + q;
-          g[j][m] = f2(0.f, 0.f) - mul2(dr[m], mul2(qq, r1));
-          rb[j][m] = mul2(mul2(qq, qq), r1);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < D; ++j) io.st(P.r[j], rb[j]);
-#pragma unroll
-      for (int j = 0; j < D; ++j) r2c<N>(g[j], P.S[1 + j] + io.base, L, t, valid, tws);
-    }
-  } else if constexpr (K == R_ADJ_2) {
-    const bool first = (it == 0);
-    float2 a2[E], a1[E], q[E], dr[E], qx[E];
-    io.ld(P.S[1], a2);
-    io.ld(P.S[2], a1);
-    __syncthreads();  // twiddles
-    c2r<N>(a2, L, t, tws);
-    c2r<N>(a1, L, t, tws);
-    io.ld(P.q, q);
-    io.ld(P.dtr0, dr);
-    io.ldx(P.Q[0], qx);
-#pragma unroll
-    for (int m = 0; m < E; ++m) a2[m] = q[m] - a2[m];  // q - A2, shared by every axis
-    // one axis component at a time: its density, then its transform
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      float2 rb[E], g[E];
-      if (first) io.zero(rb); else io.ld(P.r[j], rb);
-#pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const float2 qq = qpair(j, qx[m]);
-        const float2 r1 = rb[m] + a2[m];
-        g[m] = mul2(dr[m], a1[m] - mul2(qq, r1));
-        rb[m] = mul2(mul2(qq, qq), r1);
-      }
-      io.st(P.r[j], rb);
-      r2c<N>(g, P.S[1 + j] + io.base, L, t, valid, tws);
-    }
-  } else if constexpr (K == R_ADJ_FINAL || K == R_ADJ_SCATTER_ONLY) {
-    float2 v[E], rs[E], ic[E];
-    if constexpr (K == R_ADJ_FINAL) {
-      io.ld(P.S[0], v);
-      io.ld(P.r[0], rs);
-#pragma unroll
-      for (int j = 1; j < D; ++j) {
-        float2 rj[E];
-        io.ld(P.r[j], rj);
-#pragma unroll
-        for (int m = 0; m < E; ++m) rs[m] = rs[m] + rj[m];
-      }
-      io.ld(P.inv_dc2, ic);
-    } else {
-      io.zero(v);
-    }
-    __syncthreads();  // twiddles
-    if constexpr (K == R_ADJ_FINAL) c2r<N>(v, L, t, tws);
-#pragma unroll
-    for (int m = 0; m < E; ++m) L[t + T * m] = v[m];
-    scatter_row<N>(P, 0, Lf, rowc, t, valid);
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      v[m] = L[t + T * m];
-      if constexpr (K == R_ADJ_FINAL) v[m] = v[m] + mul2(rs[m], ic[m]);
-    }
-    io.st(P.out, v);
-  }
+  row_pass<N, D, K, G::ROWS>(plans[job.x], job.y, step_of(sa), lds, tws);
 }
 
 // ------------------------------------------------------------------ gather reduction

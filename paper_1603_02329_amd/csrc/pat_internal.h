@@ -100,12 +100,31 @@ struct DevPlan {
 
 // Step index of a launch: n = (ctr ? *ctr : 0) + k.  Graph-captured chunks
 // pass a device counter advanced once per chunk; eager launches pass k only.
+// span: steps of the longest instance of a fused launch (0: not fused).
 struct StepArg {
   const int32_t* ctr;
   int32_t k;
+  int32_t span = 0;
 };
 
 __device__ __forceinline__ int step_of(const StepArg& s) { return (s.ctr ? *s.ctr : 0) + s.k; }
+
+// Step of one instance inside a fused launch.  The launch's step n (of
+// `span`) runs the instance's step floor(n S / span), S = nt - 1 of the
+// instance, at the n where that value advances: each of the instance's S
+// steps runs exactly once, in order, spread evenly over the span.  With
+// span = 0 every instance runs step n.  Returns whether the instance runs.
+__device__ __forceinline__ bool fused_step(const DevPlan& P, const StepArg& s, int& it) {
+  const int n = step_of(s);
+  if (s.span <= 0) {
+    it = n;
+    return true;
+  }
+  const long S = P.nt - 1;
+  const long a = (long)n * S / s.span, b = ((long)n + 1) * S / s.span;
+  it = (int)a;
+  return b > a;
+}
 
 // multiplier kinds of the column passes
 enum Mult : int32_t {
@@ -176,6 +195,18 @@ ColVariant col_variant_of(const ColSpec& spec, int ndim, int ny, int nz);
 int col_axis_len(const ColSpec& spec, int ndim, int ny, int nz);
 
 hipError_t launch_reduce(const Launch& L, int n0, int n1);
+
+// Fused launches (2D, both axis lengths 128, 256 or 512): one launch covers
+// instances of several sizes, each block running the pass of its own
+// instance's size.  Row passes: 256 threads, 4096 / nx rows per block.
+// Column passes: variant tile t (8 or 4) means NTH = 64 t threads per block,
+// NTH * 8 / ny columns per block for a column of ny points.
+bool fused_size(int n);
+int fused_row_rows(int nx);
+int fused_col_tile(int ny, int tile);
+int col_variants_fused(const ColSpec& spec, ColVariant* out);
+hipError_t launch_row_fused(RowKind kind, const Launch& L, StepArg s);
+hipError_t launch_col_fused(const ColSpec& spec, ColVariant v, const Launch& L, StepArg s);
 
 // Forward / adjoint pass sequences shared by the eager and batched executors.
 // Each entry is one launch: a row pass (kind) or a column pass (spec).

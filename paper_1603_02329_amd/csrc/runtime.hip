@@ -25,6 +25,7 @@
 namespace pat {
 hipError_t upload_twiddles_rows(const Tw* host);
 hipError_t upload_twiddles_cols(const Tw* host);
+hipError_t upload_twiddles_fused(const Tw* host);
 }
 
 using namespace pat;
@@ -56,7 +57,8 @@ int ensure_twiddles() {
     const float ch = (float)c, sh = (float)s;
     tw[q] = Tw{ch, sh, (float)(c - (double)ch), (float)(s - (double)sh)};
   }
-  if (upload_twiddles_rows(tw.data()) != hipSuccess || upload_twiddles_cols(tw.data()) != hipSuccess)
+  if (upload_twiddles_rows(tw.data()) != hipSuccess || upload_twiddles_cols(tw.data()) != hipSuccess ||
+      upload_twiddles_fused(tw.data()) != hipSuccess)
     return PAT_EHIP;
   g_tw_ready[dev] = 1;
   return PAT_OK;

@@ -45,6 +45,58 @@ def test_batch_matches_eager_bitwise(chunk, parts, lanes):
     b.close()
 
 
+def _fused_instances(lossy):
+    """2D size classes with axes of 128, 256 and 512 points (fused into
+    shared launches), different time axes, non-square grids, and a class of
+    one instance (absent from some groups when split in three)."""
+    specs = [
+        dict(n=(128, 128), nt=7, ns=5, pml=6),
+        dict(n=(128, 128), nt=7, ns=4, pml=5),
+        dict(n=(256, 256), nt=13, ns=6, pml=8),
+        dict(n=(256, 128), nt=10, ns=5, pml=6),
+        dict(n=(512, 512), nt=25, ns=7, pml=10),
+        dict(n=(128, 512), nt=4, ns=3, pml=5),
+        dict(n=(512, 512), nt=25, ns=6, pml=10),
+    ]
+    return [synth.small_instance(800 + i, lossy=lossy, **s) for i, s in enumerate(specs)]
+
+
+@pytest.mark.parametrize("lossy,chunk,parts,lanes,tune",
+                         [(True, 1, 0, 0, False), (True, 4, 0, 0, True), (True, 4, 1, 1, False),
+                          (True, 3, 3, 2, False), (False, 4, 0, 0, True)])
+def test_fused_batch_matches_eager_bitwise(lossy, chunk, parts, lanes, tune):
+    """Size classes fused into shared launches, each instance stepping at
+    its own rate through the common loop, equal the eager path bitwise."""
+    insts = _fused_instances(lossy)
+    plans = [pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=DEV) for i in insts]
+    p0 = [torch.from_numpy(i.p0).to(DEV) for i in insts]
+    ref_d = [p.forward(x).clone() for p, x in zip(plans, p0)]
+    rng = np.random.default_rng(8)
+    hs = [torch.from_numpy(rng.standard_normal((i.desc.nt, i.ns)).astype(np.float32)).to(DEV) for i in insts]
+    ref_i = [p.adjoint(h).clone() for p, h in zip(plans, hs)]
+    b = pat.Batch(plans, chunk=chunk, parts=parts, lanes=lanes)
+    if tune:
+        b.forward(p0)  # captures graphs that the tuning must drop
+        rep = b.autotune(reps=2)
+        shapes = {(i.desc.n[0], i.desc.n[1]) for i in insts}
+        assert rep and set().union(*(set(map(tuple, e["fused"])) for e in rep)) == shapes
+        assert all(e["tile"] in (8, 4) for e in rep)
+    for r in range(2):  # graph replays across calls
+        d = b.forward(p0)
+        im = b.adjoint(hs)
+        torch.cuda.synchronize()
+        for k in range(len(insts)):
+            assert torch.equal(d[k], ref_d[k]), (r, k)
+            assert torch.equal(im[k], ref_i[k]), (r, k)
+    b.close()
+    # the same batch unfused
+    b = pat.Batch(plans, chunk=chunk, parts=parts, lanes=lanes, fuse=False)
+    d = b.forward(p0)
+    torch.cuda.synchronize()
+    assert all(torch.equal(d[k], ref_d[k]) for k in range(len(insts)))
+    b.close()
+
+
 def test_forward_range_resume_is_bitwise():
     inst = synth.small_instance(600, (64, 64), nt=37, ns=7, pml=5, lossy=True)
     plan = pat.Plan(inst.desc, inst.c0, inst.rho0, inst.alpha0_db, inst.sensors, device=DEV)
