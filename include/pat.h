@@ -46,6 +46,7 @@ extern "C" {
 
 /* pat_batch_create_ex flags */
 #define PAT_BATCH_NO_FUSE 0x1u  /* keep every size class in launches of its own */
+#define PAT_BATCH_NO_STAGGER 0x2u  /* start every group's time loop at once */
 
 /*
  * Grid, time axis and physics of one solver instance (one multi-grid level).
@@ -200,6 +201,10 @@ int pat_batch_create(pat_batch** out, pat_plan* const* plans, int32_t nb, int32_
  *   each of its steps runs once and in order, spread evenly over the loop.
  *   Short classes then ride in the launches of the long ones instead of
  *   queueing short launches of their own beside them.
+ *   Staggered start (default; PAT_BATCH_NO_STAGGER turns it off): with
+ *   several groups, the groups at odd positions start their time loop once
+ *   the first group has finished one pass, so that concurrent groups tend
+ *   to pair a column pass (arithmetic-bound) with a row pass (memory-bound).
  *   pat_batch_create(out, plans, nb, chunk) is pat_batch_create_ex(out,
  *   plans, nb, chunk, 0, 0, 0).  parts = 1, lanes = 1 runs one launch per
  *   pass and group, one launch at a time.  PAT_EINVAL for unknown flags.

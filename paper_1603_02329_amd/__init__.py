@@ -25,6 +25,7 @@ PAT_OK, PAT_EINVAL, PAT_EUNSTABLE, PAT_ENOMEM, PAT_EHIP, PAT_ENONFINITE, PAT_ENO
 PAT_NO_PML = 0x1
 PAT_CHECK_FINITE = 0x2
 PAT_BATCH_NO_FUSE = 0x1
+PAT_BATCH_NO_STAGGER = 0x2
 
 #: every symbol include/pat.h declares
 EXPORTED = [
@@ -263,18 +264,20 @@ class Plan:
 class Batch:
     """Many plans run together (one launch per pass over all instances)."""
 
-    def __init__(self, plans: Sequence[Plan], chunk: int = 0, parts: int = 0, lanes: int = 0, fuse: bool = True):
+    def __init__(self, plans: Sequence[Plan], chunk: int = 0, parts: int = 0, lanes: int = 0, fuse: bool = True,
+                 stagger: bool = True):
         """chunk: steps per captured graph (0: 32; 1: eager); parts: groups
         per size class (0: 2); lanes: streams (0: one per group; fewer:
         groups placed heaviest first on the least-loaded stream); fuse: 2D
-        size classes of axes 128/256/512 share their launches (see
-        pat_batch_create_ex)."""
+        size classes of axes 128/256/512 share their launches; stagger: odd
+        groups start one pass after the first (see pat_batch_create_ex)."""
         self.plans = list(plans)
-        self._opts = (int(chunk), int(parts), int(lanes), bool(fuse))
+        self._opts = (int(chunk), int(parts), int(lanes), bool(fuse), bool(stagger))
         arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
         h = ctypes.c_void_p()
+        flags = (0 if fuse else PAT_BATCH_NO_FUSE) | (0 if stagger else PAT_BATCH_NO_STAGGER)
         _check(lib().pat_batch_create_ex(ctypes.byref(h), arr, len(self.plans), int(chunk), int(parts), int(lanes),
-                                         0 if fuse else PAT_BATCH_NO_FUSE),
+                                         flags),
                "pat_batch_create_ex")
         self._h = h
 
@@ -374,9 +377,10 @@ class Batch:
             n = _grid3(p)
             k = f"{n[0]}x{n[1]}x{n[2]}/nt{p.nt}/{'lossy' if p.lossy else 'lossless'}"
             count[k] = count.get(k, 0) + 1
-        chunk, parts, lanes, fuse = self._opts
+        chunk, parts, lanes, fuse, stagger = self._opts
         return ";".join(f"{k}/i{v}" for k, v in sorted(count.items())) + \
-            f"|chunk{chunk}/parts{parts}/lanes{lanes}/{'fused' if fuse else 'unfused'}"
+            f"|chunk{chunk}/parts{parts}/lanes{lanes}/{'fused' if fuse else 'unfused'}" + \
+            ("/staggered" if stagger else "")
 
 
 def _grid3(plan) -> list:

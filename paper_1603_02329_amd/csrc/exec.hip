@@ -437,6 +437,8 @@ struct pat_batch {
   std::vector<hipStream_t> lanes;  // streams the classes run on (a class uses lanes[k % size])
   hipStream_t cap = nullptr;  // capture-only stream
   hipEvent_t fork = nullptr;
+  hipEvent_t lead = nullptr;  // the first group's first pass (staggered start)
+  bool stagger = true;
   int nb = 0;
 };
 
@@ -453,6 +455,7 @@ void destroy_batch(pat_batch* b) {
   for (auto s : b->lanes) hipStreamDestroy(s);
   if (b->cap) hipStreamDestroy(b->cap);
   if (b->fork) hipEventDestroy(b->fork);
+  if (b->lead) hipEventDestroy(b->lead);
   if (b->arena) hipFree(b->arena);
   delete b;
 }
@@ -480,17 +483,30 @@ int capture(pat_batch* b, BatchClass& c, int dir) {
 // steps [0, nsteps) of direction dir on the class stream: `full` graph chunks
 // with the nsteps mod chunk remaining steps run eagerly and spread evenly
 // between the chunks (the eager launches are the ones diagnostics can time,
-// so they sample the whole run); the device counter skips the eager steps
-int run_steps(pat_batch* b, BatchClass& c, int dir, int nsteps) {
+// so they sample the whole run); the device counter skips the eager steps.
+// With `lead`, step 0 runs first, eagerly, and `lead` is recorded after its
+// first pass.
+int run_steps(pat_batch* b, BatchClass& c, int dir, int nsteps, hipEvent_t lead = nullptr) {
   const Runner R = c.runner();
-  const int full = b->chunk > 1 ? nsteps / b->chunk : 0;
-  const int rem = nsteps - full * b->chunk;
-  if (full == 0) return R.steps(dir, 0, nsteps, c.st);
   int rc = PAT_OK;
+  int s0 = 0;
+  if (lead && nsteps > 0) {
+    PassOp ops[kMaxOps];
+    const int nops = step_ops(dir, c.ndim, c.lossy, ops);
+    for (int i = 0; i < nops && !rc; ++i) {
+      rc = R.op(dir, i, ops[i], StepArg{nullptr, 0, R.span}, c.st, true);
+      if (!rc && i == 0 && hipEventRecord(lead, c.st) != hipSuccess) rc = PAT_EHIP;
+    }
+    if (rc) return rc;
+    s0 = 1;
+  }
+  const int full = b->chunk > 1 ? (nsteps - s0) / b->chunk : 0;
+  const int rem = nsteps - s0 - full * b->chunk;
+  if (full == 0) return R.steps(dir, s0, nsteps, c.st);
   if (!c.graph[dir] && (rc = capture(b, c, dir))) return rc;
-  hipLaunchKernelGGL(k_set_ctr, dim3(1), dim3(1), 0, c.st, c.ctr, 0);
+  hipLaunchKernelGGL(k_set_ctr, dim3(1), dim3(1), 0, c.st, c.ctr, s0);
   if (hipGetLastError() != hipSuccess) return PAT_EHIP;
-  int n = 0, done_eager = 0;
+  int n = s0, done_eager = 0;
   for (int g = 0; g < full && !rc; ++g) {
     const int want = (int)((long)(g + 1) * rem / full);  // eager steps due by chunk g
     for (; done_eager < want && !rc; ++done_eager, ++n) {
@@ -522,23 +538,33 @@ int set_io_class(BatchClass& c, const float* const* in, float* const* out) {
   return PAT_OK;
 }
 
+// Staggered start: with several groups, the groups at odd positions begin
+// their time loop once the first group has run one pass, so that the
+// streams tend to pair one group's column pass (arithmetic-bound) with
+// another's row pass (memory-bound) rather than two of a kind.
 int batch_run(pat_batch* b, int dir, const float* const* in, float* const* out, hipStream_t st) {
   if (!b || !in || !out) return PAT_EINVAL;
   if (hipEventRecord(b->fork, st) != hipSuccess) return PAT_EHIP;
+  const bool stagger = b->stagger && b->cls.size() > 1;
   int rc = PAT_OK;
-  for (auto& c : b->cls) {
+  for (size_t k = 0; k < b->cls.size(); ++k) {
+    BatchClass& c = b->cls[k];
     if (hipStreamWaitEvent(c.st, b->fork, 0) != hipSuccess) return PAT_EHIP;
     rc = set_io_class(c, in, out);
     if (rc) return rc;
     const Runner R = c.runner();
+    hipEvent_t lead = (stagger && k == 0) ? b->lead : nullptr;
+    const bool follow = stagger && (k & 1);
     if (dir == 0) {
       rc = R.row(R_FWD_INIT, StepArg{nullptr, 0}, c.st);
-      if (!rc) rc = run_steps(b, c, 0, c.nt - 1);
+      if (!rc && follow && hipStreamWaitEvent(c.st, b->lead, 0) != hipSuccess) rc = PAT_EHIP;
+      if (!rc) rc = run_steps(b, c, 0, c.nt - 1, lead);
       if (!rc) rc = R.reduce(0, 0, c.st, c.red_n);
     } else if (c.nt == 1) {
       rc = R.row(R_ADJ_SCATTER_ONLY, StepArg{nullptr, 0}, c.st);
     } else {
-      rc = run_steps(b, c, 1, c.nt - 1);
+      if (follow && hipStreamWaitEvent(c.st, b->lead, 0) != hipSuccess) rc = PAT_EHIP;
+      if (!rc) rc = run_steps(b, c, 1, c.nt - 1, lead);
       if (!rc) rc = R.row(R_ADJ_FINAL, StepArg{nullptr, 0}, c.st);
     }
     if (rc) return rc;
@@ -559,7 +585,8 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
                                    int32_t lanes, uint32_t flags) {
   if (!out) return PAT_EINVAL;
   *out = nullptr;
-  if (!plans || nb < 1 || chunk < 0 || parts < 0 || lanes < 0 || (flags & ~(uint32_t)PAT_BATCH_NO_FUSE))
+  if (!plans || nb < 1 || chunk < 0 || parts < 0 || lanes < 0 ||
+      (flags & ~(uint32_t)(PAT_BATCH_NO_FUSE | PAT_BATCH_NO_STAGGER)))
     return PAT_EINVAL;
   for (int i = 0; i < nb; ++i)
     if (!plans[i] || plans[i]->desc.ndim != plans[0]->desc.ndim) return PAT_EINVAL;
@@ -567,6 +594,7 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
   if (!b) return PAT_ENOMEM;
   b->chunk = chunk == 0 ? 32 : chunk;
   b->nb = nb;
+  b->stagger = !(flags & PAT_BATCH_NO_STAGGER);
   // group by (shape, nt, lossy), then split every group into `parts` equal
   // parts (default 2).  Each part runs on its own stream, so that the passes
   // of different parts -- memory-bound rows of one, arithmetic-bound columns
@@ -811,7 +839,8 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
     }
   }
   if (!rc && (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
-              hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess))
+              hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+              hipEventCreateWithFlags(&b->lead, hipEventDisableTiming) != hipSuccess))
     rc = PAT_EHIP;
   if (rc) {
     destroy_batch(b);

@@ -107,7 +107,7 @@ def test_batch_entry_points_validate_on_host():
     assert L.pat_batch_create(ctypes.byref(h), one, 1, -1) == pat.PAT_EINVAL
     assert L.pat_batch_create_ex(ctypes.byref(h), one, 1, 0, -1, 0, 0) == pat.PAT_EINVAL
     assert L.pat_batch_create_ex(ctypes.byref(h), one, 1, 0, 0, -1, 0) == pat.PAT_EINVAL
-    assert L.pat_batch_create_ex(ctypes.byref(h), one, 1, 0, 0, 0, 0x2) == pat.PAT_EINVAL  # unknown flag
+    assert L.pat_batch_create_ex(ctypes.byref(h), one, 1, 0, 0, 0, 0x4) == pat.PAT_EINVAL  # unknown flag
     assert L.pat_batch_create(ctypes.byref(h), one, 1, 0) == pat.PAT_EINVAL  # null plan pointer
     assert h.value is None
     assert L.pat_batch_autotune(None, 1, None) == pat.PAT_EINVAL
