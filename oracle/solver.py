@@ -14,7 +14,7 @@ g(x) = lam TV(x) + indicator(x >= 0).
   lines of Alg. ISTA; the prox by FGP, ``prox.tv_prox``), then
   t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2, theta_k = (t_k - 1) / t_{k+1},
   y_{k+1} = x_k + theta_k (x_k - x_{k-1}).
-* ``mg_fista`` (Alg. FISTAMG) on two levels: at iteration k > 1 the decision
+* ``mg_fista`` (Alg. FISTAMG) on two or more levels: at iteration k > 1 the decision
   rule (equation conditions) chooses between the direct step P_L(y_k) and a
   recursive step: coarse start x0 = R y_k, coherence term
   v = R grad F_rho,h(y_k) - grad F_rho,h-1(x0) (equation Fourteen; F_rho the
@@ -22,6 +22,12 @@ g(x) = lam TV(x) + indicator(x >= 0).
   Twentyone), restricted bound lower = R y_k - blockmin(y_k) (equation
   constraint), FISTA on phi = F_rho,h-1 + <v, .> with projections onto
   x >= lower, and the correction x_k = y_k + P (x_c - x0).
+* more than two levels (section I: the method extends to more levels):
+  the coarse solve at level i is itself FISTAMG-like -- at each of its
+  iterations after the first the same decision rule, applied to
+  grad phi_i, may replace the projected gradient step by a recursive step
+  to level i + 1 with coherence v_{i+1} = R grad phi_i(y) - grad
+  F_rho,i+1(R y) and bound R y - blockmin(y - lower_i) (``coarse_mg``).
 
 Readings where the paper is silent or garbled:
 * the coarse level has its own plan (grid halved, time step doubled, PML
@@ -33,12 +39,17 @@ Readings where the paper is silent or garbled:
   through <v, x>), or after q_c updates;
 * fine termination (optional): F_{k-1} - F_k < eps_d max(F_{k-1}, F_k);
 * the norms of the decision rule are 2-norms over the grid; R and P are the
-  block average and its piecewise-constant transpose (``transfer``).
+  block average and its piecewise-constant transpose (``transfer``);
+* more than two levels: each coarse level's step size and lambda are the
+  caller's, its data the fine data at every 2^i-th sample; its
+  coarse solve counts updates like the two-level one (q_c, eps_c), its first
+  iteration is a projected gradient step, and its decision rule keeps its
+  own K_d, K_r and last transfer point within one coarse solve.
 """
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 from typing import List, Optional
 
 import numpy as np
@@ -46,7 +57,7 @@ import numpy as np
 from . import kspace, prox, transfer
 
 __all__ = ["Level", "power_iteration", "grad_f", "value_f", "objective", "smoothed", "fista", "coarse_fista",
-           "mg_fista", "MGParams"]
+           "coarse_mg", "mg_fista", "MGParams"]
 
 
 @dataclass
@@ -179,11 +190,73 @@ class MGRecord:
     F: float            # F_h(x_k)
     coarse_updates: int = 0
     grad_ratio: float = 0.0   # ||R grad F_rho(y)|| / ||grad F_rho(y)|| at a decision
-    extra: dict = field(default_factory=dict)
+    depth: int = 0            # deepest level a recursive step reached (0: direct step)
 
 
-def mg_fista(fine: Level, coarse: Level, x0: np.ndarray, n_iter: int, params: MGParams = MGParams()):
-    """Alg. FISTAMG on two levels; returns (x, [MGRecord])."""
+def _decide(p: "MGParams", g: np.ndarray, y: np.ndarray, y_tilde, k_d: int, k_r: int):
+    """The decision rule (equation conditions) at y with gradient g of the
+    level's smoothed objective: (recursive?, ||R g|| / ||g||)."""
+    rg = transfer.restrict(g)
+    ratio = math.sqrt(transfer.norm2(rg)) / max(math.sqrt(transfer.norm2(g)), 1e-300)
+    far = (y_tilde is not None and
+           math.sqrt(transfer.norm2(y - y_tilde)) > p.vartheta * math.sqrt(transfer.norm2(y_tilde)))
+    return (ratio > p.kappa) and (far or k_r == 0 or k_d > p.q_d), ratio, rg
+
+
+def coarse_mg(levels, i: int, x0: np.ndarray, v: np.ndarray, lower: np.ndarray, p: "MGParams"):
+    """The coarse solve at level i of ``levels`` (0 the target level): FISTA
+    on phi_i = F_rho,i + <v, .> over x >= lower, whose iterations after the
+    first may take a recursive step to level i + 1 when there is one (same
+    decision rule, coherence term and restricted bound as at the target
+    level).  With no coarser level it is ``coarse_fista``.  Returns (x,
+    number of updates, deepest level reached)."""
+    lv = levels[i]
+    has_next = i + 1 < len(levels)
+
+    def phi_value(x):
+        return value_f(lv, x) + lv.lam * prox.tv_smooth(x, p.rho)[0] + transfer.dot(v, x)
+
+    x_prev = np.asarray(x0, dtype=np.float64)
+    y = x_prev.copy()
+    t = 1.0
+    phi_prev = phi_value(x_prev)
+    k = k_d = k_r = 0
+    y_tilde = None
+    depth = i
+    while k < p.q_c:
+        _, g = smoothed(lv, y, p.rho)
+        g = g + v
+        recursive = False
+        if has_next and k > 0:
+            recursive, _, rg = _decide(p, g, y, y_tilde, k_d, k_r)
+        if recursive:
+            k_d, k_r = 0, k_r + 1
+            xc0 = transfer.restrict(y)
+            _, gc = smoothed(levels[i + 1], xc0, p.rho)
+            xc, _, d = coarse_mg(levels, i + 1, xc0, rg - gc, transfer.restrict_lower(y, lower), p)
+            depth = max(depth, d)
+            x = y + transfer.prolong(xc - xc0)
+            y_tilde = y.copy()
+        else:
+            k_d += 1
+            x = np.maximum(y - lv.alpha * g, lower)
+        k += 1
+        phi_x = phi_value(x)
+        tn = _t_next(t)
+        theta = (t - 1.0) / tn if p.momentum else 0.0
+        y = x + theta * (x - x_prev)
+        x_prev, t = x, tn
+        if phi_prev - phi_x < p.eps_c * max(abs(phi_prev), abs(phi_x)):
+            break
+        phi_prev = phi_x
+    return x_prev, k, depth
+
+
+def mg_fista(fine: Level, coarse, x0: np.ndarray, n_iter: int, params: MGParams = MGParams()):
+    """Alg. FISTAMG; ``coarse`` is the next coarse level, or a list of
+    levels from the next coarse one down (more than two levels).  Returns
+    (x, [MGRecord])."""
+    levels = [fine] + (list(coarse) if isinstance(coarse, (list, tuple)) else [coarse])
     p = params
     x_prev = np.asarray(x0, dtype=np.float64)
     y = x_prev.copy()
@@ -199,23 +272,17 @@ def mg_fista(fine: Level, coarse: Level, x0: np.ndarray, n_iter: int, params: MG
             # grad f(y) serves the decision (through grad F_rho) and a direct step
             _, gf = grad_f(fine, y)
             gF = gf + fine.lam * prox.tv_smooth(y, p.rho)[1]
-            rg = transfer.restrict(gF)
-            ratio = math.sqrt(transfer.norm2(rg)) / max(math.sqrt(transfer.norm2(gF)), 1e-300)
-            cond1 = ratio > p.kappa
-            far = (y_tilde is not None and
-                   math.sqrt(transfer.norm2(y - y_tilde)) > p.vartheta * math.sqrt(transfer.norm2(y_tilde)))
-            cond2 = far or k_r == 0 or k_d > p.q_d
-            recursive = cond1 and cond2
+            recursive, ratio, rg = _decide(p, gF, y, y_tilde, k_d, k_r)
         if recursive:
             k_d, k_r = 0, k_r + 1
             xc0 = transfer.restrict(y)
-            _, gc = smoothed(coarse, xc0, p.rho)
+            _, gc = smoothed(levels[1], xc0, p.rho)
             v = rg - gc
             lower = transfer.restrict_lower(y)
-            xc, nup = coarse_fista(coarse, xc0, v, lower, p.rho, p.q_c, p.eps_c, p.momentum)
+            xc, nup, depth = coarse_mg(levels, 1, xc0, v, lower, p)
             x = y + transfer.prolong(xc - xc0)
             y_tilde = y.copy()
-            rec = MGRecord("recursive", 0.0, nup, ratio)
+            rec = MGRecord("recursive", 0.0, nup, ratio, depth)
         else:
             k_d += 1
             x = _direct(fine, y, p.prox_iter, gf)

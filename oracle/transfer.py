@@ -37,15 +37,19 @@ def prolong(coarse: np.ndarray) -> np.ndarray:
     return c
 
 
-def restrict_lower(fine: np.ndarray) -> np.ndarray:
+def restrict_lower(fine: np.ndarray, fine_lower=None) -> np.ndarray:
     """The restricted bound of equation constraint (section V-C):
-    lower[I] = (R y)[I] - min_{j in block I} y_j, the index set I_{h,i} of the
-    paper being the 2^d fine points averaged into coarse point i."""
+    lower[I] = (R y)[I] - min_{j in block I} (y_j - l_j), the index set
+    I_{h,i} of the paper being the 2^d fine points averaged into coarse
+    point i.  The paper's fine bound is l = 0 (nonnegativity, the default);
+    a bound l at an intermediate level of more than two levels restricts the
+    same way, so that every coarse x >= lower keeps y + P(x - R y) >= l."""
     f = np.asarray(fine, dtype=np.float64)
+    d = f if fine_lower is None else f - np.asarray(fine_lower, dtype=np.float64)
     nd = f.ndim
     mn = np.full(tuple(s // 2 for s in f.shape), np.inf)
     for corner in np.ndindex(*([2] * nd)):
-        mn = np.minimum(mn, f[tuple(slice(c, None, 2) for c in corner)])
+        mn = np.minimum(mn, d[tuple(slice(c, None, 2) for c in corner)])
     return restrict(f) - mn
 
 

@@ -333,28 +333,101 @@ def config2(instance: int = 0) -> Instance:
     return _hetero2d(2, instance, 256, 1200)
 
 
-def two_level(cfg: int, instance: int, n: int, dx: float, pml: int, nt: int, ns: int) -> Tuple[Instance, Instance]:
-    """Two multi-grid levels of one 2D problem: an n^2 fine level and its
-    (n/2)^2 cell-centred coarse level (dx doubled, PML points halved, N_t
-    halved, dt doubled).  Medium and phantom are continuous functions drawn
-    once and sampled on both grids; the ns sensors (left half-circle of
-    radius n/2 - pml - 8 points) share physical positions.  The fine time
-    step is CFL 0.3 of the fine grid's maximum sound speed."""
+def _level_geometry(count: int):
+    """(scale, offset) of each multi-grid level's indices in fine-grid
+    indices: level l is cell-centred over 2^l blocks of fine points."""
+    return tuple((float(2 ** l), (2 ** l - 1) / 2.0) for l in range(count))
+
+
+def multi_level(cfg: int, instance: int, n: int, dx: float, pml: int, nt: int, ns: int,
+                count: int) -> List[Instance]:
+    """`count` multi-grid levels of one 2D problem: an n^2 fine level and
+    its cell-centred coarse levels (level l: (n/2^l)^2, dx and dt times 2^l,
+    PML points and N_t divided by 2^l).  Medium and phantom are continuous
+    functions drawn once and sampled on every grid; the ns sensors (left
+    half-circle of radius n/2 - pml - 8 points) share physical positions.
+    The fine time step is CFL 0.3 of the fine grid's maximum sound speed."""
     rng = rng_for(cfg, instance)
     shape = (n, n)
-    lv = ((1.0, 0.0), (2.0, 0.5))
-    (c0, rho0, a0), (c0c, rho0c, a0c) = blob_medium(rng, shape, pml, levels=lv)
+    lv = _level_geometry(count)
+    media = blob_medium(rng, shape, pml, levels=lv)
     radius = n / 2 - pml - 8
-    p0, p0c = vessel_phantom(rng, shape, radius, levels=lv)
+    p0s = vessel_phantom(rng, shape, radius, levels=lv)
     sens = half_circle_sensors(n, dx, 0.0, radius, ns)
-    dt_f = 0.3 * dx / float(np.max(c0))
-    fine = Instance(_desc2(n, dx, pml, nt, dt=dt_f), c0, rho0, a0, sens, p0, name=f"cfg{cfg}.fine")
-    nc = n // 2
-    coarse_desc = GridDesc(ndim=2, n=(nc, nc), dx=(2 * dx, 2 * dx), origin=(dx / 2, dx / 2),
-                           nt=nt // 2, dt=2.0 * dt_f, cfl=0.3, pml_size=(pml // 2, pml // 2, 0),
-                           pml_alpha=2.0, alpha_power=1.5, pml=True)
-    coarse = Instance(coarse_desc, c0c, rho0c, a0c, sens.copy(), p0c, name=f"cfg{cfg}.coarse")
-    return fine, coarse
+    dt_f = 0.3 * dx / float(np.max(media[0][0]))
+    out = [Instance(_desc2(n, dx, pml, nt, dt=dt_f), *media[0], sens, p0s[0], name=f"cfg{cfg}.fine")]
+    for l in range(1, count):
+        s, off = lv[l]
+        nl = n >> l
+        desc = GridDesc(ndim=2, n=(nl, nl), dx=(s * dx, s * dx), origin=(off * dx, off * dx),
+                        nt=nt >> l, dt=s * dt_f, cfl=0.3, pml_size=(pml >> l, pml >> l, 0),
+                        pml_alpha=2.0, alpha_power=1.5, pml=True)
+        out.append(Instance(desc, *media[l], sens.copy(), p0s[l], name=f"cfg{cfg}.level{l}"))
+    return out
+
+
+def two_level(cfg: int, instance: int, n: int, dx: float, pml: int, nt: int, ns: int) -> Tuple[Instance, Instance]:
+    """Two multi-grid levels of one 2D problem (``multi_level`` with two
+    levels): an n^2 fine level and its (n/2)^2 cell-centred coarse level."""
+    fine, coarse = multi_level(cfg, instance, n, dx, pml, nt, ns, 2)
+    return fine, Instance(coarse.desc, coarse.c0, coarse.rho0, coarse.alpha0_db, coarse.sensors, coarse.p0,
+                          name=f"cfg{cfg}.coarse")
+
+
+def ellipsoids(rng, shape, pml: int, *, k=6, semi=(3.0, 12.0), amp=(0.5, 1.0), margin=12.0,
+               levels=((1.0, 0.0),)):
+    """The ellipsoid phantom of :func:`ellipsoid_phantom` (centres kept
+    `margin` points clear of the PML) sampled on several levels
+    (``(scale, offset)`` pairs as in :func:`blob_medium`); returns one array
+    per level."""
+    n_phys = list(reversed(shape))
+    params = []
+    for _ in range(k):
+        c = np.array([rng.uniform(pml + margin, n_phys[j] - 1 - pml - margin) for j in range(3)])
+        ax = rng.uniform(*semi, size=3)
+        qm, rm = np.linalg.qr(rng.standard_normal((3, 3)))
+        qm = qm * np.sign(np.diag(rm))
+        params.append((c, ax, qm, rng.uniform(*amp)))
+    outs = []
+    for scale, offset in levels:
+        lshape = tuple(int(round(s / scale)) for s in shape)
+        xs = [x * scale + offset for x in _coords(lshape)]
+        out = np.zeros(lshape)
+        for c, ax, qm, a in params:
+            rel = [xs[j] - c[j] for j in range(3)]
+            acc = np.zeros(lshape)
+            for r in range(3):
+                comp = qm[0, r] * rel[0] + qm[1, r] * rel[1] + qm[2, r] * rel[2]
+                acc += (comp / ax[r]) ** 2
+            out += a * (acc <= 1.0)
+        outs.append(_f32(out))
+    return outs
+
+
+def multi_level_3d(cfg: int, instance: int, n: int, dx: float, pml: int, nt: int, count: int) -> List[Instance]:
+    """`count` multi-grid levels of one 3D problem (n^3 fine, cell-centred
+    coarse levels as in :func:`multi_level`): medium as config 5 (c clipped
+    to [1450, 1600], rho 1000, alpha0 0.75) with blobs of 4-12 points,
+    ellipsoids of semi-axes 2-6 points centred 4 points clear of the PML,
+    sensors on the interior nodes (x, y in [pml, n - 1 - pml]) of the fine
+    plane z = pml at the same physical positions on every level."""
+    rng = rng_for(cfg, instance)
+    shape = (n, n, n)
+    lv = _level_geometry(count)
+    media = blob_medium(rng, shape, pml, c_clip=(1450.0, 1600.0), hetero_rho=False, sig=(4.0, 12.0), levels=lv)
+    p0s = ellipsoids(rng, shape, pml, semi=(2.0, 6.0), margin=4.0, levels=lv)
+    idx = np.arange(pml, n - pml, dtype=np.float64)
+    gx, gy = np.meshgrid(idx, idx, indexing="xy")
+    sens = np.stack([gx.ravel() * dx, gy.ravel() * dx, np.full(gx.size, pml * dx)], axis=1)
+    dt_f = 0.3 * dx / 1600.0
+    out = []
+    for l in range(count):
+        s, off = lv[l]
+        nl = n >> l
+        desc = GridDesc(ndim=3, n=(nl,) * 3, dx=(s * dx,) * 3, origin=(off * dx,) * 3, nt=nt >> l, dt=s * dt_f,
+                        cfl=0.3, pml_size=(pml >> l,) * 3, pml_alpha=2.0, alpha_power=1.5, pml=True)
+        out.append(Instance(desc, *media[l], sens.copy(), p0s[l], name=f"cfg{cfg}.level{l}"))
+    return out
 
 
 def config3(instance: int = 0) -> Tuple[Instance, Instance]:

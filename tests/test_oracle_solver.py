@@ -179,3 +179,82 @@ def test_mg_first_iterations_follow_the_decision_rule():
     assert hist[1].grad_ratio > 0.25 and hist[1].kind == "recursive"
     assert 1 <= hist[1].coarse_updates <= 8
     assert x.min() >= -1e-12 * np.abs(x).max()
+
+
+def test_restrict_lower_with_a_fine_bound():
+    """The bound of an intermediate level: lower[I] = (R y)[I] - min over
+    the block of (y - l), by brute force; every coarse x >= lower keeps the
+    prolonged correction above l, and x = lower touches l in every block."""
+    rng = np.random.default_rng(14)
+    for shape in [(6, 8), (4, 6, 2)]:
+        y = rng.standard_normal(shape)
+        fl = rng.standard_normal(shape)
+        lo = transfer.restrict_lower(y, fl)
+        nd = len(shape)
+        for I in np.ndindex(*lo.shape):
+            pts = [tuple(2 * i + d for i, d in zip(I, delta)) for delta in np.ndindex(*([2] * nd))]
+            expect = sum(y[p] for p in pts) / len(pts) - min(y[p] - fl[p] for p in pts)
+            assert abs(lo[I] - expect) < 1e-14
+        for _ in range(20):
+            xc = lo + np.abs(rng.standard_normal(lo.shape))
+            assert (y + transfer.prolong(xc - transfer.restrict(y)) - fl).min() >= -1e-12
+        gap = y + transfer.prolong(lo - transfer.restrict(y)) - fl
+        assert abs(gap.min()) < 1e-12
+        assert np.allclose(transfer.restrict_lower(y, np.zeros(shape)), transfer.restrict_lower(y), atol=0)
+
+
+def _levels(count, seed=0, n=16, nt=30, ns=12, pml=2, lam=0.0):
+    insts = synth.multi_level(91, seed, n, 1e-4, pml, nt, ns, count)
+    ops = [K.make_plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors) for i in insts]
+    data = K.forward(ops[0], insts[0].p0.astype(np.float64))
+    lv = []
+    for k, op in enumerate(ops):
+        L = solver.power_iteration(op, n_iter=60)
+        lv.append(solver.Level(op, data[::2 ** k][:op.nt], lam=lam, alpha=1.0 / L))
+    return ops, data, lv
+
+
+def test_mg_three_levels_lambda0_reaches_the_nnls_minimum():
+    """Three levels (16^2, 8^2, 4^2): the recursion reaches the coarsest
+    level, every iterate stays feasible, and F converges to the NNLS
+    minimum of the fine problem."""
+    ops, data, lv = _levels(3)
+    H = _dense(ops[0])
+    x_star, res = nnls(H, data.ravel())
+    f_star = 0.5 * res * res
+    # coarse solves stop at a 0.1 % decrease, so that they run long enough
+    # to recurse themselves
+    x, hist = solver.mg_fista(lv[0], lv[1:], np.zeros(ops[0].shape), 300, solver.MGParams(eps_c=1e-3))
+    assert max(r.depth for r in hist) == 2
+    assert x.min() >= -1e-12 * np.abs(x).max()
+    f0 = 0.5 * float(np.sum(data * data))
+    assert hist[-1].F - f_star < 1e-4 * f0
+
+
+def test_mg_two_level_list_equals_two_level_call():
+    """A list of one coarse level runs exactly the two-level algorithm."""
+    ops, data, lv = _levels(2, lam=1e-4)
+    x1, h1 = solver.mg_fista(lv[0], lv[1], np.zeros(ops[0].shape), 6)
+    x2, h2 = solver.mg_fista(lv[0], [lv[1]], np.zeros(ops[0].shape), 6)
+    assert np.array_equal(x1, x2) and [r.F for r in h1] == [r.F for r in h2]
+    assert all(r.depth in (0, 1) for r in h1)
+
+
+def test_mg_recursive_step_in_3d():
+    """3D (16^3 -> 8^3), one coarse update, no momentum: the recursive step
+    is y + P(max(R y - alpha_c R grad F_rho,h(y), lower) - R y), as in 2D."""
+    f, c = synth.multi_level_3d(92, 0, 16, 2e-4, 2, 12, 2)
+    opf = K.make_plan(f.desc, f.c0, f.rho0, f.alpha0_db, f.sensors)
+    opc = K.make_plan(c.desc, c.c0, c.rho0, c.alpha0_db, c.sensors)
+    data = K.forward(opf, f.p0.astype(np.float64))
+    fine = solver.Level(opf, data, lam=1e-4, alpha=1.0 / solver.power_iteration(opf, n_iter=20))
+    coarse = solver.Level(opc, data[::2], lam=1e-4, alpha=1.0 / solver.power_iteration(opc, n_iter=20))
+    prm = solver.MGParams(q_c=1, momentum=False, kappa=0.125, rho=3e-2)
+    x, hist = solver.mg_fista(fine, coarse, np.zeros(opf.shape), 2, prm)
+    assert [r.kind for r in hist] == ["direct", "recursive"]
+    y, _ = solver.fista(fine, np.zeros(opf.shape), 1, momentum=False)
+    _, gf = solver.smoothed(fine, y, prm.rho)
+    ry = transfer.restrict(y)
+    xc = np.maximum(ry - coarse.alpha * transfer.restrict(gf), transfer.restrict_lower(y))
+    expect = y + transfer.prolong(xc - ry)
+    assert np.max(np.abs(x - expect)) <= 1e-12 * np.max(np.abs(expect))
