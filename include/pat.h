@@ -347,9 +347,12 @@ int pat_residual_f64(const float* a, const float* b, float* r, int64_t n, double
  *              `stream`.  At least one of grad, value_host.
  *
  * pat_restrict_lower -- the restricted bound constraint of equation
- *   constraint: lower[I] = (R y)[I] - min over the 2^d block of I of y, so
- *   that y + P(x_c - R y) >= 0 for every coarse x_c >= lower (R, P as in
- *   pat_restrict / pat_prolong).  n_fine as in pat_restrict.
+ *   constraint: lower[I] = (R y)[I] - min over the 2^d block of I of
+ *   (y - l), so that y + P(x_c - R y) >= l for every coarse x_c >= lower
+ *   (R, P as in pat_restrict / pat_prolong).  fine_lower: the fine level's
+ *   bound l (N_fine floats, device), or NULL for l = 0 (the target level's
+ *   nonnegativity); a bound at an intermediate level arises with more than
+ *   two levels.  n_fine as in pat_restrict.
  *
  * pat_axpby -- out = a x + b y over n floats (device; out may alias x or y):
  *   the extrapolation and correction steps of Alg. FISTA / FISTAMG.
@@ -358,7 +361,8 @@ int pat_residual_f64(const float* a, const float* b, float* r, int64_t n, double
  */
 int pat_tv_smooth(int32_t ndim, const int32_t n[3], const float* x, double rho, double scale, float* grad,
                   double* value_host, void* stream);
-int pat_restrict_lower(int32_t ndim, const int32_t n_fine[3], const float* fine, float* lower, void* stream);
+int pat_restrict_lower(int32_t ndim, const int32_t n_fine[3], const float* fine, const float* fine_lower,
+                       float* lower, void* stream);
 int pat_axpby(int64_t n, double a, const float* x, double b, const float* y, float* out, void* stream);
 int pat_project(int64_t n, const float* x, const float* lower, float* out, void* stream);
 

@@ -99,7 +99,7 @@ def lib() -> ctypes.CDLL:
         "pat_timing_end": (ctypes.c_int, [ctypes.POINTER(f64), ctypes.POINTER(i64), ctypes.POINTER(f64)]),
         "pat_batch_autotune": (ctypes.c_int, [vp, i32, vp]),
         "pat_tv_smooth": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, f64, f64, vp, ctypes.POINTER(f64), vp]),
-        "pat_restrict_lower": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, vp]),
+        "pat_restrict_lower": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, vp, vp]),
         "pat_axpby": (ctypes.c_int, [i64, f64, vp, f64, vp, vp, vp]),
         "pat_project": (ctypes.c_int, [i64, vp, vp, vp, vp]),
         "pat_batch_time_pass": (ctypes.c_int, [vp, i32, i32, i32, i32, vp, ctypes.POINTER(f64), ctypes.POINTER(f64)]),
@@ -473,14 +473,15 @@ def tv_smooth(x, rho: float, grad=None, scale: float = 1.0, value: bool = True):
     return out.value if value else None
 
 
-def restrict_lower(fine, out=None):
-    """R(y) - blockmin(y): the coarse bound that keeps a prolonged correction
-    of y feasible."""
+def restrict_lower(fine, fine_lower=None, out=None):
+    """R(y) - blockmin(y - l): the coarse bound that keeps a prolonged
+    correction of y above the fine bound l (None: 0)."""
     torch = _torch()
     nd = fine.dim()
     if out is None:
         out = torch.empty(tuple(s // 2 for s in fine.shape), device=fine.device, dtype=torch.float32)
-    _check(lib().pat_restrict_lower(nd, _i32x3(list(reversed(fine.shape))), _dev_f32(fine, "fine"),
+    fl = None if fine_lower is None else _dev_f32(fine_lower, "fine_lower", fine.numel())
+    _check(lib().pat_restrict_lower(nd, _i32x3(list(reversed(fine.shape))), _dev_f32(fine, "fine"), fl,
                                     _dev_f32(out, "lower", fine.numel() >> nd), _stream()), "pat_restrict_lower")
     return out
 

@@ -179,9 +179,11 @@ __global__ void k_tv_grad(Grid3 g, int ndim, const float* __restrict__ x, float 
 }
 
 // ------------------------------------------------------------------ bound restriction
-// lower_c[I] = (R y)[I] - min over the block {2I + delta} of y: for every
-// coarse x_c >= lower_c, y + P(x_c - R y) >= 0 on the block.
-__global__ void k_restrict_lower(Grid3 c, int ndim, const float* __restrict__ fine, float* __restrict__ lower) {
+// lower_c[I] = (R y)[I] - min over the block {2I + delta} of (y - l): for
+// every coarse x_c >= lower_c, y + P(x_c - R y) >= l on the block (l = 0
+// when fl is null).
+__global__ void k_restrict_lower(Grid3 c, int ndim, const float* __restrict__ fine, const float* __restrict__ fl,
+                                 float* __restrict__ lower) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= c.N) return;
   const int cx = (int)(i % c.n[0]);
@@ -195,7 +197,7 @@ __global__ void k_restrict_lower(Grid3 c, int ndim, const float* __restrict__ fi
       for (int dx = 0; dx < 2; ++dx) {
         const long f = (2L * cx + dx) + fx * ((2L * cy + dy) + fy * (ndim == 3 ? (2L * cz + dz) : 0));
         acc += fine[f];
-        mn = fminf(mn, fine[f]);
+        mn = fminf(mn, fl ? fine[f] - fl[f] : fine[f]);
       }
   lower[i] = acc * (ndim == 3 ? 0.125f : 0.25f) - mn;
 }
@@ -419,8 +421,8 @@ extern "C" int pat_tv_smooth(int32_t ndim, const int32_t n[3], const float* x, d
   return PAT_OK;
 }
 
-extern "C" int pat_restrict_lower(int32_t ndim, const int32_t n_fine[3], const float* fine, float* lower,
-                                  void* stream) {
+extern "C" int pat_restrict_lower(int32_t ndim, const int32_t n_fine[3], const float* fine,
+                                  const float* fine_lower, float* lower, void* stream) {
   Grid3 f;
   if (make_grid(ndim, n_fine, f) || !fine || !lower) return PAT_EINVAL;
   int32_t nc[3];
@@ -431,7 +433,7 @@ extern "C" int pat_restrict_lower(int32_t ndim, const int32_t n_fine[3], const f
   Grid3 c;
   make_grid(ndim, nc, c);
   hipLaunchKernelGGL(k_restrict_lower, dim3(blocks_for(c.N)), dim3(256), 0, (hipStream_t)stream, c, ndim, fine,
-                     lower);
+                     fine_lower, lower);
   return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
 }
 

@@ -1,16 +1,18 @@
-"""Reconstruction of a synthetic two-level 2D problem on the GPU: ISTA,
-FISTA and their two-level variants (Alg. ISTA, Alg. FISTA, Alg. FISTAMG),
+"""Reconstruction of a synthetic multi-level 2D problem on the GPU: ISTA,
+FISTA and their multi-grid variants (Alg. ISTA, Alg. FISTA, Alg. FISTAMG),
 with the objective F, the relative error RE (section VI) and the elapsed
 time after every iteration.
 
     python -m paper_1603_02329_amd.reconstruct [--n 512] [--iters 20]
-        [--methods ista,mg-ista,fista,mg-fista] [--lam 1e-2] [--json out.json]
+        [--methods ista,mg-ista,fista,mg-fista] [--lam 1e-2] [--levels 2]
+        [--eps-c 1e-2] [--json out.json]
 
 The problem: the seeded two-level medium and vessel phantom of the
 synthetic workloads (512^2 / 256^2 by default, N_t 2400 / 1200), data = the
 GPU forward of the phantom plus white Gaussian noise at 40 dB SNR (the
-noise standard deviation is the data's rms times 10^(-40/20)); the coarse
-data are the fine data at even sample indices.  Step sizes from the power
+noise standard deviation is the data's rms times 10^(-40/20)); the data of
+coarse level l (grid n/2^l, N_t / 2^l) are the fine data at every 2^l-th
+sample.  Step sizes from the power
 method on each level: 2/L_f for ISTA (as in section VI-A), 1/L_f for FISTA;
 the two-level parameters are the paper's 2D values (kappa 1/4, vartheta
 0.1, q_d 3, q_c 8, eps_c 1e-2, rho 1e-2).  The data are generated on the
@@ -34,6 +36,8 @@ def main(argv=None):
     ap.add_argument("--methods", default="ista,mg-ista,fista,mg-fista")
     ap.add_argument("--lam", type=float, default=1e-2)
     ap.add_argument("--power-iters", type=int, default=20)
+    ap.add_argument("--levels", type=int, default=2, help="grid levels of the MG variants (2: the paper's)")
+    ap.add_argument("--eps-c", type=float, default=1e-2, help="coarse-solve termination (relative decrease)")
     ap.add_argument("--json", default=None)
     args = ap.parse_args(argv)
 
@@ -47,22 +51,27 @@ def main(argv=None):
     n = args.n
     pml = max(4, 20 * n // 512)
     nt = max(64, 2400 * n // 512)
-    fine_i, coarse_i = synth.two_level(3, 0, n, 1e-4, pml, nt, 256) if n != 512 else synth.config3()
-    pf = Plan(fine_i.desc, fine_i.c0, fine_i.rho0, fine_i.alpha0_db, fine_i.sensors, device=dev)
-    pc = Plan(coarse_i.desc, coarse_i.c0, coarse_i.rho0, coarse_i.alpha0_db, coarse_i.sensors, device=dev)
+    # the first two levels are those of the two-level workload (same draws)
+    insts = synth.multi_level(3, 0, n, 1e-4, pml, nt, 256, max(2, args.levels))
+    plans = [Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=dev) for i in insts]
+    pf = plans[0]
+    fine_i = insts[0]
     p_exact = torch.from_numpy(fine_i.p0).to(dev)
     clean = pf.forward(p_exact)
     rms = math.sqrt(float((clean.double() ** 2).mean()))
     noise = np.random.default_rng(4242).standard_normal(tuple(clean.shape)) * rms * 10.0 ** (-40.0 / 20.0)
     data = (clean + torch.from_numpy(noise.astype(np.float32)).to(dev)).contiguous()
-    data_c = data[::2].contiguous()
-    v0 = torch.from_numpy(np.random.default_rng(7).standard_normal(fine_i.p0.shape).astype(np.float32)).to(dev)
+    datas = [data] + [data[::2 ** l][:insts[l].desc.nt].contiguous() for l in range(1, len(insts))]
+    v = torch.from_numpy(np.random.default_rng(7).standard_normal(fine_i.p0.shape).astype(np.float32)).to(dev)
     t0 = time.perf_counter()
-    Lf = S.power_iteration(pf, v0, args.power_iters)
     from . import restrict
-    Lc = S.power_iteration(pc, restrict(v0), args.power_iters)
-    print(f"grid {n}^2 / {n // 2}^2, N_t {nt} / {nt // 2}; L_f fine {Lf:.4e}, coarse {Lc:.4e} "
-          f"({time.perf_counter() - t0:.1f} s)", flush=True)
+    Ls = []
+    for l, p in enumerate(plans):
+        Ls.append(S.power_iteration(p, v, args.power_iters))
+        v = restrict(v)
+    print("grids " + " / ".join(f"{i.desc.n[0]}^2" for i in insts) + ", N_t " +
+          " / ".join(str(i.desc.nt) for i in insts) + "; L_f " + ", ".join(f"{x:.4e}" for x in Ls) +
+          f" ({time.perf_counter() - t0:.1f} s)", flush=True)
     norm_exact = math.sqrt(float((p_exact.double() ** 2).sum()))
 
     def re(x):
@@ -72,8 +81,8 @@ def main(argv=None):
     for method in [m.strip() for m in args.methods.split(",") if m.strip()]:
         momentum = "fista" in method
         scale = 1.0 if momentum else 2.0
-        fine = S.Level(pf, data, args.lam, scale / Lf)
-        coarse = S.Level(pc, data_c, args.lam, scale / Lc)
+        levels = [S.Level(p, d, args.lam, scale / L) for p, d, L in zip(plans, datas, Ls)]
+        fine = levels[0]
         x0 = torch.zeros_like(p_exact)
         rows = []
         torch.cuda.synchronize()
@@ -84,18 +93,23 @@ def main(argv=None):
             F = rec if isinstance(rec, float) else rec.F
             kind = "direct" if isinstance(rec, float) else rec.kind
             row = {"k": k, "kind": kind, "F": F, "RE": re(x), "seconds": time.perf_counter() - start}
+            if not isinstance(rec, float) and rec.depth > 1:
+                kind = f"{kind}{rec.depth}"
+                row["depth"] = rec.depth
             rows.append(row)
             print(f"{method:9s} k={k:3d} {kind:9s} F={F:.6e} RE={row['RE']:7.3f}% t={row['seconds']:7.2f}s",
                   flush=True)
 
         if method.startswith("mg-"):
-            S.mg_fista(fine, coarse, x0, args.iters, S.MGParams(momentum=momentum), callback=log)
+            S.mg_fista(fine, levels[1:args.levels], x0, args.iters,
+                       S.MGParams(momentum=momentum, eps_c=args.eps_c), callback=log)
         else:
             S.fista(fine, x0, args.iters, momentum=momentum, callback=log)
         results[method] = rows
     if args.json:
         with open(args.json, "w") as f:
-            json.dump({"n": n, "nt": nt, "lam": args.lam, "L_f": [Lf, Lc], "results": results}, f, indent=1)
+            json.dump({"n": n, "nt": nt, "lam": args.lam, "levels": args.levels, "L_f": Ls, "results": results}, f,
+                      indent=1)
 
 
 if __name__ == "__main__":

@@ -1,7 +1,7 @@
 """Reconstruction iterations of sections IV and V on libpat.
 
-ISTA / FISTA (Alg. ISTA, Alg. FISTA) and the two-level MG-FISTA
-(Alg. FISTAMG) for
+ISTA / FISTA (Alg. ISTA, Alg. FISTA) and MG-FISTA (Alg. FISTAMG) on two
+or more levels for
 
     min_x  F(x) = 1/2 ||H x - p_hat||^2 + lam TV(x)   subject to x >= 0
 
@@ -19,6 +19,11 @@ at even sample indices, the coarse step size and lambda are the caller's,
 the coarse loop stops after the update with
 phi_k - phi_{k+1} < eps_c max(|phi_k|, |phi_{k+1}|) or after q_c updates,
 and the fine loop (optionally) when F_{k-1} - F_k < eps_d max(F_{k-1}, F_k).
+With more than two levels (the extension section I allows), the coarse
+solve at level i takes, at its iterations after the first, the recursive
+step to level i + 1 when the same decision rule applied to grad phi_i says
+so: coherence v_{i+1} = R grad phi_i(y) - grad F_rho,i+1(R y) and bound
+R y - blockmin(y - lower_i).
 """
 from __future__ import annotations
 
@@ -28,7 +33,7 @@ from typing import List, Optional
 
 from . import Batch, Plan, axpby, dot_f64, project, prolong, residual_f64, restrict, restrict_lower, tv_prox, tv_smooth
 
-__all__ = ["Level", "MGParams", "MGRecord", "power_iteration", "fista", "coarse_fista", "mg_fista"]
+__all__ = ["Level", "MGParams", "MGRecord", "power_iteration", "fista", "coarse_fista", "coarse_mg", "mg_fista"]
 
 
 class Level:
@@ -161,11 +166,75 @@ class MGRecord:
     F: float                  # F_h(x_k)
     coarse_updates: int = 0
     grad_ratio: float = 0.0   # ||R grad F_rho(y)|| / ||grad F_rho(y)|| at the decision
+    depth: int = 0            # deepest level a recursive step reached (0: direct step)
 
 
-def mg_fista(fine: Level, coarse: Level, x0, n_iter: int, params: MGParams = MGParams(), callback=None):
-    """Alg. FISTAMG on two levels; returns (x, [MGRecord]).
-    ``callback(k, x_k, record)`` runs after every iteration."""
+def _decide(p: MGParams, g, y, y_tilde, k_d: int, k_r: int):
+    """The decision rule at y with gradient g of the level's smoothed
+    objective: (recursive?, ||R g|| / ||g||, R g)."""
+    rg = restrict(g)
+    ratio = math.sqrt(dot_f64(rg)) / max(math.sqrt(dot_f64(g)), 1e-300)
+    far = False
+    if y_tilde is not None:
+        d = axpby(1.0, y, -1.0, y_tilde)
+        far = math.sqrt(dot_f64(d)) > p.vartheta * math.sqrt(dot_f64(y_tilde))
+    return (ratio > p.kappa) and (far or k_r == 0 or k_d > p.q_d), ratio, rg
+
+
+def coarse_mg(levels, i: int, x0, v, lower, p: MGParams):
+    """The coarse solve at level i of ``levels`` (0 the target level): FISTA
+    on phi_i = F_rho,i + <v, .> over x >= lower, whose iterations after the
+    first may take a recursive step to level i + 1 when there is one (same
+    decision rule, coherence term and restricted bound as at the target
+    level); with no coarser level it is ``coarse_fista``.  Returns (x,
+    number of updates, deepest level reached)."""
+    lv = levels[i]
+    has_next = i + 1 < len(levels)
+
+    def phi_value(x):
+        return lv.value_f(x) + lv.lam * tv_smooth(x, p.rho) + dot_f64(v, x)
+
+    x_prev = x0.clone()
+    y = x0.clone()
+    t = 1.0
+    phi_prev = phi_value(x_prev)
+    k = k_d = k_r = 0
+    y_tilde = None
+    depth = i
+    while k < p.q_c:
+        _, g = lv.smoothed(y, p.rho)
+        g = axpby(1.0, g, 1.0, v, out=g)
+        recursive = False
+        if has_next and k > 0:
+            recursive, _, rg = _decide(p, g, y, y_tilde, k_d, k_r)
+        if recursive:
+            k_d, k_r = 0, k_r + 1
+            xc0 = restrict(y)
+            _, gc = levels[i + 1].smoothed(xc0, p.rho)
+            xc, _, d = coarse_mg(levels, i + 1, xc0, axpby(1.0, rg, -1.0, gc), restrict_lower(y, lower), p)
+            depth = max(depth, d)
+            x = axpby(1.0, y, 1.0, prolong(axpby(1.0, xc, -1.0, xc0)))
+            y_tilde = y.clone()
+        else:
+            k_d += 1
+            x = project(axpby(1.0, y, -lv.alpha, g), lower)
+        k += 1
+        phi_x = phi_value(x)
+        tn = _t_next(t)
+        theta = (t - 1.0) / tn if p.momentum else 0.0
+        y = axpby(1.0 + theta, x, -theta, x_prev)
+        x_prev, t = x, tn
+        if phi_prev - phi_x < p.eps_c * max(abs(phi_prev), abs(phi_x)):
+            break
+        phi_prev = phi_x
+    return x_prev, k, depth
+
+
+def mg_fista(fine: Level, coarse, x0, n_iter: int, params: MGParams = MGParams(), callback=None):
+    """Alg. FISTAMG; ``coarse`` is the next coarse level, or a list of levels
+    from the next coarse one down (more than two levels).  Returns (x,
+    [MGRecord]); ``callback(k, x_k, record)`` runs after every iteration."""
+    levels = [fine] + (list(coarse) if isinstance(coarse, (list, tuple)) else [coarse])
     p = params
     x_prev = x0.clone()
     y = x0.clone()
@@ -182,24 +251,17 @@ def mg_fista(fine: Level, coarse: Level, x0, n_iter: int, params: MGParams = MGP
             _, gf = fine.grad_f(y)
             gF = gf.clone()
             tv_smooth(y, p.rho, grad=gF, scale=fine.lam, value=False)
-            rg = restrict(gF)
-            ratio = math.sqrt(dot_f64(rg)) / max(math.sqrt(dot_f64(gF)), 1e-300)
-            cond1 = ratio > p.kappa
-            far = False
-            if y_tilde is not None:
-                d = axpby(1.0, y, -1.0, y_tilde)
-                far = math.sqrt(dot_f64(d)) > p.vartheta * math.sqrt(dot_f64(y_tilde))
-            recursive = cond1 and (far or k_r == 0 or k_d > p.q_d)
+            recursive, ratio, rg = _decide(p, gF, y, y_tilde, k_d, k_r)
         if recursive:
             k_d, k_r = 0, k_r + 1
             xc0 = restrict(y)
-            _, gc = coarse.smoothed(xc0, p.rho)
+            _, gc = levels[1].smoothed(xc0, p.rho)
             v = axpby(1.0, rg, -1.0, gc)
             lower = restrict_lower(y)
-            xc, nup = coarse_fista(coarse, xc0, v, lower, p.rho, p.q_c, p.eps_c, p.momentum)
+            xc, nup, depth = coarse_mg(levels, 1, xc0, v, lower, p)
             x = axpby(1.0, y, 1.0, prolong(axpby(1.0, xc, -1.0, xc0)))
             y_tilde = y.clone()
-            rec = MGRecord("recursive", 0.0, nup, ratio)
+            rec = MGRecord("recursive", 0.0, nup, ratio, depth)
         else:
             k_d += 1
             x = _direct(fine, y, p.prox_iter, gf)

@@ -47,6 +47,9 @@ def test_restrict_lower_axpby_project_match_oracle(shape):
     y = rng.standard_normal(shape).astype(np.float32)
     lo = pat.restrict_lower(_t(y)).cpu().numpy()
     assert np.max(np.abs(lo - transfer.restrict_lower(y))) <= 1e-6
+    fl = rng.standard_normal(shape).astype(np.float32)
+    lo = pat.restrict_lower(_t(y), _t(fl)).cpu().numpy()
+    assert np.max(np.abs(lo - transfer.restrict_lower(y, fl))) <= 1e-6
     a, b = rng.standard_normal(shape).astype(np.float32), rng.standard_normal(shape).astype(np.float32)
     out = pat.axpby(1.5, _t(a), -0.25, _t(b)).cpu().numpy()
     assert np.max(np.abs(out - (np.float32(1.5) * a - np.float32(0.25) * b))) <= 1e-6
@@ -104,3 +107,49 @@ def test_mg_fista_matches_oracle():
     assert _rel(xg.cpu().numpy(), xo) <= 1e-4
     # feasible up to the float32 rounding of y + P(x_c - R y) on the bound
     assert xg.min().item() >= -1e-6 * xg.abs().max().item()
+
+
+def _chain(insts, lam, n_power=30):
+    """Oracle and GPU levels of a multi-level problem: FP32 data of the
+    fine level, every 2^l-th sample at level l, step sizes from the
+    oracle's power iteration."""
+    ops = [K.make_plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors) for i in insts]
+    data = K.forward(ops[0], insts[0].p0.astype(np.float64)).astype(np.float32)
+    olv, glv = [], []
+    for l, (i, op) in enumerate(zip(insts, ops)):
+        d = np.ascontiguousarray(data[::2 ** l][:i.desc.nt])
+        L = solver.power_iteration(op, n_iter=n_power, seed=l)
+        olv.append(solver.Level(op, d.astype(np.float64), lam, 1.0 / L))
+        plan = pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=DEV)
+        glv.append(gsolver.Level(plan, _t(d), lam, 1.0 / L))
+    return olv, glv
+
+
+def _compare_mg(olv, glv, n_iter, prm):
+    x0 = np.zeros(olv[0].shape)
+    xo, ho = solver.mg_fista(olv[0], olv[1:], x0, n_iter, prm)
+    xg, hg = gsolver.mg_fista(glv[0], glv[1:], _t(x0), n_iter, prm)
+    torch.cuda.synchronize()
+    print("oracle:", [(r.kind, r.coarse_updates, r.depth) for r in ho], flush=True)
+    print("gpu:   ", [(r.kind, r.coarse_updates, r.depth) for r in hg], flush=True)
+    assert [(r.kind, r.coarse_updates, r.depth) for r in hg] == [(r.kind, r.coarse_updates, r.depth) for r in ho]
+    assert np.allclose([r.F for r in hg], [r.F for r in ho], rtol=1e-5, atol=0)
+    assert _rel(xg.cpu().numpy(), xo) <= 1e-4
+    assert xg.min().item() >= -1e-6 * xg.abs().max().item()
+    return ho
+
+
+def test_mg_fista_three_levels_matches_oracle():
+    """64^2 -> 32^2 -> 16^2: coarse solves that recurse to the coarsest
+    level, on the GPU and in the FP64 oracle, take the same decisions."""
+    olv, glv = _chain(synth.multi_level(90, 1, 64, 1e-4, 6, 60, 16, 3), 2e-3)
+    ho = _compare_mg(olv, glv, 5, solver.MGParams(eps_c=1e-3))
+    assert max(r.depth for r in ho) == 2
+
+
+def test_mg_fista_3d_matches_oracle():
+    """3D two levels (32^3 -> 16^3, plane of sensors), the paper's 3D
+    parameters (kappa = 1/8, rho = 3e-2)."""
+    olv, glv = _chain(synth.multi_level_3d(92, 0, 32, 2e-4, 4, 24, 2), 1e-2, n_power=20)
+    ho = _compare_mg(olv, glv, 4, solver.MGParams(kappa=0.125, rho=3e-2))
+    assert "recursive" in [r.kind for r in ho]
