@@ -336,3 +336,53 @@ def adjoint(plan: OraclePlan, h: np.ndarray, nsteps_done: Optional[Callable] = N
     img = pbar + sum(rbar) / (nd * plan.c0sq)
     img = img - (dt / 2.0) * sum(spectral(plan.b[j], ubar[j] / plan.rho0_sg[j]) for j in range(nd))
     return img
+
+
+# --------------------------------------------------------------------------
+# adjoint-then-discretize (the paper's adjoint system, for comparison)
+# --------------------------------------------------------------------------
+
+def adjoint_atd(plan: OraclePlan, h: np.ndarray) -> np.ndarray:
+    """The adjoint system of section III (eq. moma, massa, statea with eq.
+    initial2, image rho*(T) / rho0 by eq. adjj) discretized with the scheme
+    of ``forward`` -- the paper's "adjoint-then-discretize" operator, not
+    the exact transpose (``adjoint``).  For data vanishing at the first and
+    last samples it equals the transpose in a homogeneous lossless or
+    absorption-only medium without PML and converges to it in dt otherwise
+    (dispersion and data inside the PML aside); the end samples differ.
+
+    Readings (the paper gives the continuous system only):
+    * the fields are scaled by dV/dt so that the data enter without grid
+      factors: over the adjoint step from t_n to t_n+1 (forward times T - t)
+      the density gains rho0 sigma, sigma = (W^T h[N-1-n] + W^T h[N-2-n]) / 2
+      (trapezoid rule on the time-reversed data), split equally over the d
+      axis components and inside the PML factor like the divergence term;
+    * the time derivative in eq. statea is taken through eq. massa:
+      d/dt (c0^2 / rho0 rho*) = c0^2 (sigma / dt - sum_j g_j);
+    * leapfrog as the forward: u* at half steps from p* = 0, u* = 0, rho* = 0;
+    * p* = c0^2 rho* - rho0 L1[tau c0^2 (sigma / dt - div u*)]
+           - rho0 L2[eta c0^2 / rho0 rho*], the operators in statea's order.
+    """
+    nd, dt = plan.ndim, plan.dt
+    h = np.asarray(h, dtype=np.float64)
+    nt = plan.nt
+    u = [np.zeros(plan.shape) for _ in range(nd)]
+    rho = [np.zeros(plan.shape) for _ in range(nd)]
+    p = np.zeros(plan.shape)
+    for n in range(nt - 1):
+        sigma = 0.5 * (scatter(plan, h[nt - 1 - n]) + scatter(plan, h[nt - 2 - n]))
+        P = _fft(p)
+        for j in range(nd):
+            dp = _ifft(plan.a[j] * P).real
+            u[j] = plan.Qsg[j] * (plan.Qsg[j] * u[j] - dt / plan.rho0_sg[j] * dp)        # eq. moma
+        g = [spectral(plan.b[j], u[j]) for j in range(nd)]
+        for j in range(nd):
+            rho[j] = plan.Q[j] * (plan.Q[j] * rho[j] + plan.rho0 * (sigma / nd - dt * g[j]))  # eq. massa
+        rs = sum(rho)
+        if plan.lossy:
+            A1 = spectral(plan.L1, plan.tau * plan.c0sq * (sigma / dt - sum(g)))
+            A2 = spectral(plan.L2, plan.eta * plan.c0sq / plan.rho0 * rs)
+            p = plan.c0sq * rs - plan.rho0 * (A1 + A2)                                      # eq. statea
+        else:
+            p = plan.c0sq * rs
+    return sum(rho) / plan.rho0                                                             # eq. adjj
