@@ -168,6 +168,27 @@ int pat_forward_range(pat_plan* plan, const float* p0, float* data, int32_t n_be
                       void* state_io, void* stream);
 
 /*
+ * pat_adjoint_atd -- the paper's "adjoint-then-discretize" operator, for
+ * comparison with the exact transpose pat_adjoint (which is what gradients
+ * need).  The adjoint system of section III (eq. moma, massa, statea, with
+ * eq. initial2 and the image rho*(T) / rho0 of eq. adjj) is discretized with
+ * the forward's scheme and PML: leapfrog from p* = u* = rho* = 0, the
+ * time-reversed data entering eq. massa as a mass source -- over step n the
+ * density gains rho0 (W^T h[nt-1-n] + W^T h[nt-2-n]) / 2, split equally over
+ * the axis components -- and p* = c0^2 rho* - rho0 L1[c0^2 tau (sigma / dt -
+ * div u*)] - rho0 L2[c0^2 eta / rho0 rho*] (statea's order).  data: nt x ns
+ * (device), img: N floats (device, overwritten).  For data that vanish at
+ * the first and the last sample it agrees with pat_adjoint to rounding in a
+ * homogeneous lossless or absorption-only medium without PML, and converges
+ * to it at first order in dt in a heterogeneous one; the end samples enter
+ * differently (the t = 0 sample with the trapezoid's half weight), and the
+ * dispersion term and data taken inside the PML give differences that do
+ * not vanish with dt.  nt = 1 gives a zero image.
+ * The plan's state is clobbered as by pat_forward.
+ */
+int pat_adjoint_atd(pat_plan* plan, const float* data, float* img, void* stream);
+
+/*
  * Batched execution of many plans (uneven sizes and nt allowed: instances
  * retire when their own time axis ends).  Each pass of the scheme runs as one
  * launch over a work table that holds the tiles of every active instance; the

@@ -29,7 +29,7 @@ PAT_BATCH_NO_STAGGER = 0x2
 
 #: every symbol include/pat.h declares
 EXPORTED = [
-    "pat_plan_create", "pat_plan_destroy", "pat_plan_info", "pat_forward", "pat_adjoint",
+    "pat_plan_create", "pat_plan_destroy", "pat_plan_info", "pat_forward", "pat_adjoint", "pat_adjoint_atd",
     "pat_forward_range", "pat_batch_create", "pat_batch_create_ex", "pat_batch_destroy", "pat_batch_forward",
     "pat_batch_adjoint", "pat_tv_prox_work_bytes", "pat_tv_prox", "pat_restrict", "pat_prolong",
     "pat_dot_f64", "pat_residual_f64", "pat_plan_sync", "pat_strerror", "pat_timing_begin",
@@ -81,6 +81,7 @@ def lib() -> ctypes.CDLL:
         "pat_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(CInfo)]),
         "pat_forward": (ctypes.c_int, [vp, vp, vp, vp]),
         "pat_adjoint": (ctypes.c_int, [vp, vp, vp, vp]),
+        "pat_adjoint_atd": (ctypes.c_int, [vp, vp, vp, vp]),
         "pat_forward_range": (ctypes.c_int, [vp, vp, vp, i32, i32, vp, vp]),
         "pat_batch_create": (ctypes.c_int, [pp, pp, i32, i32]),
         "pat_batch_create_ex": (ctypes.c_int, [pp, pp, i32, i32, i32, i32, ctypes.c_uint32]),
@@ -243,6 +244,16 @@ class Plan:
             img = torch.empty(self.shape, device=data.device, dtype=torch.float32)
         _check(lib().pat_adjoint(self._h, _dev_f32(data, "data", self.nt * self.ns),
                                  _dev_f32(img, "img", self.npoints), _stream()), "pat_adjoint")
+        return img
+
+    def adjoint_atd(self, data, img=None):
+        """The paper's adjoint-then-discretize operator applied to data
+        (pat_adjoint_atd); for comparison with the exact transpose."""
+        torch = _torch()
+        if img is None:
+            img = torch.empty(self.shape, device=data.device, dtype=torch.float32)
+        _check(lib().pat_adjoint_atd(self._h, _dev_f32(data, "data", self.nt * self.ns),
+                                     _dev_f32(img, "img", self.npoints), _stream()), "pat_adjoint_atd")
         return img
 
     def forward_range(self, p0, data, n_begin: int, n_end: int, state):

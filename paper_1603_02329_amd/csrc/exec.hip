@@ -52,6 +52,19 @@ int step_ops(int dir, int ndim, int lossy, PassOp* ops) {
     } else {
       row(R_FWD_2LL);                    // density update + equation of state + sensors
     }
+  } else if (dir == 2) {
+    // adjoint-then-discretize: the forward's passes, density and state in
+    // the adjoint system's form
+    spec(0, d, 1, M_AX, M_AY, M_AZ);
+    row(R_FWD_1);
+    spec(1, d, 1, M_BX, M_BY, M_BZ);
+    if (lossy) {
+      row(R_ATD_2);
+      spec(1, 2, 1, M_L1DT, M_L2, 0);
+      row(R_ATD_3);
+    } else {
+      row(R_ATD_2LL);
+    }
   } else {
     if (lossy) {
       row(R_ADJ_3);
@@ -89,6 +102,10 @@ double pass_bytes_per_point(const PassOp& op, int ndim, int lossy) {
     case R_ADJ_1: return 20.0 * d;               // S_j, u_j, B_j -> u_j, S_j
     case R_ADJ_FINAL: return 4.0 * (d + 3);      // S0, rho_j, 1/(d c0^2) -> image
     case R_ADJ_SCATTER_ONLY: return 4.0;
+    case R_ATD_2: return 4.0 * (3 * d + 4);      // S_j, rho_j, dt rho0, c0^2 -> rho_j, S1, S2
+    case R_ATD_2LL: return 4.0 * (3 * d + 3);    // S_j, rho_j, dt rho0, c0^2 -> rho_j, S0
+    case R_ATD_3: return 4.0 * (d + 5);          // S1, S2, rho_j, c0^2, dt rho0 -> S0
+    case R_ATD_FINAL: return 4.0 * (d + 2);      // rho_j, dt rho0 -> image
     default: return 0.0;
   }
 }
@@ -292,6 +309,21 @@ extern "C" int pat_adjoint(pat_plan* p, const float* data, float* img, void* str
   if (p->desc.nt == 1) return R.row(R_ADJ_SCATTER_ONLY, StepArg{nullptr, 0}, st);
   rc = R.steps(1, 0, p->desc.nt - 1, st);
   if (!rc) rc = R.row(R_ADJ_FINAL, StepArg{nullptr, 0}, st);
+  return rc;
+}
+
+extern "C" int pat_adjoint_atd(pat_plan* p, const float* data, float* img, void* stream) {
+  if (!p || !data || !img) return PAT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (p->desc.nt == 1)  // no time step: the trapezoid over an empty interval
+    return hipMemsetAsync(img, 0, sizeof(float) * p->npoints, st) == hipSuccess ? PAT_OK : PAT_EHIP;
+  const Runner R = eager_runner(p);
+  int rc = set_io(p, data, img, st);
+  if (rc) return rc;
+  // p* = 0 at the start: its x-spectrum, read by the first gradient pass
+  if (hipMemsetAsync(p->hp.S[0], 0, sizeof(float) * p->npoints, st) != hipSuccess) return PAT_EHIP;
+  rc = R.steps(2, 0, p->desc.nt - 1, st);
+  if (!rc) rc = R.row(R_ATD_FINAL, StepArg{nullptr, 0}, st);
   return rc;
 }
 

@@ -450,6 +450,108 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
       io.st(P.r[j], rb);
       r2c<N>(g, P.S[1 + j] + io.base, L, t, valid, tws);
     }
+  } else if constexpr (K == R_ATD_2 || K == R_ATD_2LL) {
+    // adjoint-then-discretize step `it` (adjoint time it dt, forward time
+    // T - it dt): rho*_j <- Q_j (Q_j rho*_j + rho0 (sigma / d - dt g_j)) with
+    // sigma = (W^T h[nt-1-it] + W^T h[nt-2-it]) / 2; lossy: S1 <- F_x(c0^2 tau
+    // (sigma - dt sum g)) and S2 <- F_x(c0^2 eta / rho0 sum rho*) for the
+    // absorption pass; lossless: S0 <- F_x(c0^2 sum rho*)
+    const bool first = (it == 0);
+    float2 g[D][E], r[D][E], dr[E], c2[E], qx[E];
+#pragma unroll
+    for (int j = 0; j < D; ++j) io.ld(P.S[1 + j], g[j]);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      if (first) io.zero(r[j]); else io.ld(P.r[j], r[j]);
+    }
+    io.ld(P.dtr0, dr);
+    io.ld(P.c2, c2);
+    io.ldx(P.Q[0], qx);
+    __syncthreads();  // twiddles
+#pragma unroll
+    for (int j = 0; j < D; ++j) c2r<N>(g[j], L, t, tws);
+#pragma unroll
+    for (int m = 0; m < E; ++m) L[t + T * m] = f2(0.f, 0.f);
+    scatter_row<N>(P, P.nt - 1 - it, Lf, rowc, t, valid);
+    scatter_row<N>(P, P.nt - 2 - it, Lf, rowc, t, valid);
+    float2 sg[E], sdiv[E], srho[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) sg[m] = 0.5f * L[t + T * m];
+    WaveSync::sync();
+    const float invd = 1.0f / (float)D;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const float2 r0 = P.inv_dt * dr[m];  // rho0
+      const float2 src = mul2(r0, invd * sg[m]);
+      sdiv[m] = f2(0.f, 0.f);
+      srho[m] = f2(0.f, 0.f);
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const float2 q = qpair(j, qx[m]);
+        r[j][m] = mul2(q, mul2(q, r[j][m]) + src - mul2(dr[m], g[j][m]));
+        sdiv[m] = sdiv[m] + g[j][m];
+        srho[m] = srho[m] + r[j][m];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) io.st(P.r[j], r[j]);
+    if constexpr (K == R_ATD_2) {
+      float2 ct[E], ce[E];
+      if (P.alpha_uniform) {
+        absorption_coefs<E>(P, c2, ct, ce);
+      } else {
+        io.ld(P.c2tau, ct);
+        io.ld(P.c2eta, ce);
+      }
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        sdiv[m] = mul2(ct[m], sg[m] - P.dt * sdiv[m]);
+        srho[m] = mul2(ce[m], f2(P.dt * srho[m].x / dr[m].x, P.dt * srho[m].y / dr[m].y));
+      }
+      r2c<N>(sdiv, P.S[1] + io.base, L, t, valid, tws);
+      r2c<N>(srho, P.S[2] + io.base, L, t, valid, tws);
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) srho[m] = mul2(c2[m], srho[m]);
+      r2c<N>(srho, P.S[0] + io.base, L, t, valid, tws);
+    }
+  } else if constexpr (K == R_ATD_3) {
+    // p* = c0^2 sum rho* - rho0 (A1 + A2), the fractional Laplacians already
+    // applied to c0^2 tau (...) and c0^2 eta / rho0 (...) (statea); S0 <- F_x p*
+    float2 a1[E], a2[E], rs[E], c2[E], dr[E];
+    io.ld(P.S[1], a1);
+    io.ld(P.S[2], a2);
+    __syncthreads();  // twiddles
+    c2r<N>(a1, L, t, tws);
+    c2r<N>(a2, L, t, tws);
+    io.ld(P.r[0], rs);
+#pragma unroll
+    for (int j = 1; j < D; ++j) {
+      float2 rj[E];
+      io.ld(P.r[j], rj);
+#pragma unroll
+      for (int m = 0; m < E; ++m) rs[m] = rs[m] + rj[m];
+    }
+    io.ld(P.c2, c2);
+    io.ld(P.dtr0, dr);
+#pragma unroll
+    for (int m = 0; m < E; ++m) a1[m] = mul2(c2[m], rs[m]) - mul2(P.inv_dt * dr[m], a1[m] + a2[m]);
+    r2c<N>(a1, P.S[0] + io.base, L, t, valid, tws);
+  } else if constexpr (K == R_ATD_FINAL) {
+    // image = sum_j rho*_j / rho0 (eq. adjj), rho0 = (dt rho0) / dt
+    float2 rs[E], dr[E];
+    io.ld(P.r[0], rs);
+#pragma unroll
+    for (int j = 1; j < D; ++j) {
+      float2 rj[E];
+      io.ld(P.r[j], rj);
+#pragma unroll
+      for (int m = 0; m < E; ++m) rs[m] = rs[m] + rj[m];
+    }
+    io.ld(P.dtr0, dr);
+#pragma unroll
+    for (int m = 0; m < E; ++m) rs[m] = f2(P.dt * rs[m].x / dr[m].x, P.dt * rs[m].y / dr[m].y);
+    io.st(P.out, rs);
   } else if constexpr (K == R_ADJ_FINAL || K == R_ADJ_SCATTER_ONLY) {
     float2 v[E], rs[E], ic[E];
     if constexpr (K == R_ADJ_FINAL) {

@@ -72,6 +72,10 @@ static hipError_t launch_row_nd(RowKind kind, const Launch& L, StepArg s) {
     PAT_ROW_CASE(R_ADJ_1)
     PAT_ROW_CASE(R_ADJ_FINAL)
     PAT_ROW_CASE(R_ADJ_SCATTER_ONLY)
+    PAT_ROW_CASE(R_ATD_2)
+    PAT_ROW_CASE(R_ATD_2LL)
+    PAT_ROW_CASE(R_ATD_3)
+    PAT_ROW_CASE(R_ATD_FINAL)
     default: return hipErrorInvalidValue;
   }
 #undef PAT_ROW_CASE

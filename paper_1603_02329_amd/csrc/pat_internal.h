@@ -157,7 +157,14 @@ enum RowKind : int32_t {
   R_ADJ_1 = 8,       // transposed velocity update
   R_ADJ_FINAL = 9,   // transposed initial condition -> image
   R_ADJ_SCATTER_ONLY = 10,  // nt == 1: image = W^T h[0]
-  R_COUNT = 11
+  // adjoint-then-discretize (the paper's adjoint system, eq. moma, massa,
+  // statea): the forward's passes with the time-reversed data as a mass
+  // source and the state equation in statea's order
+  R_ATD_2 = 11,      // lossy: density + data source, feeds the absorption pass
+  R_ATD_2LL = 12,    // lossless: density + data source + equation of state
+  R_ATD_3 = 13,      // lossy equation of state (statea)
+  R_ATD_FINAL = 14,  // image = sum_j rho*_j / rho0 (eq. adjj)
+  R_COUNT = 15
 };
 
 hipError_t launch_row(RowKind kind, int ndim, int nx, const Launch& L, StepArg s);
