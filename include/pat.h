@@ -43,6 +43,11 @@ extern "C" {
 /* ------------------------------------------------------------------ flags */
 #define PAT_NO_PML        0x1u  /* switch the PML off: periodic grid             */
 #define PAT_CHECK_FINITE  0x2u  /* record non-finite pressure; see pat_plan_sync */
+#define PAT_SMOOTH_MEDIUM 0x4u  /* smooth c0 and rho0 spectrally before use (section VI-A:
+                                   the paper's models ran on smoothed maps): each axis'
+                                   spectrum times the Blackman window centred on k = 0,
+                                   0.42 + 0.5 cos(2 pi m/n) + 0.08 cos(4 pi m/n); float64,
+                                   on the host, at plan creation */
 
 /* pat_batch_create_ex flags */
 #define PAT_BATCH_NO_FUSE 0x1u  /* keep every size class in launches of its own */

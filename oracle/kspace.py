@@ -155,11 +155,37 @@ def _bcast(v: np.ndarray, ndim: int, j: int) -> np.ndarray:
     return v.reshape(sh)
 
 
+def blackman_k(n: int) -> np.ndarray:
+    """The Blackman window over the n wavenumber bins of one axis, centred
+    on the zero wavenumber: 0.42 + 0.5 cos(2 pi m / n) + 0.08 cos(4 pi m / n)
+    (1 at m = 0, 0 at the Nyquist bin m = n / 2)."""
+    m = np.arange(n)
+    return 0.42 + 0.5 * np.cos(2.0 * math.pi * m / n) + 0.08 * np.cos(4.0 * math.pi * m / n)
+
+
+def smooth_medium(f: np.ndarray) -> np.ndarray:
+    """Spectral smoothing of a medium map (section VI-A: the paper's models
+    ran on maps smoothed against aliasing; the window is this build's
+    reading): the spectrum times the product over the axes of
+    ``blackman_k``, back-transformed (real part)."""
+    f = np.asarray(f, dtype=np.float64)
+    W = np.ones(f.shape)
+    for ax, n in enumerate(f.shape):
+        sh = [1] * f.ndim
+        sh[ax] = n
+        W = W * blackman_k(n).reshape(sh)
+    return np.fft.ifftn(W * np.fft.fftn(f)).real
+
+
 def make_plan(desc, c0, rho0, alpha0_db, sensors) -> OraclePlan:
-    """Derive every coefficient of the scheme in FP64 from the float32 inputs."""
+    """Derive every coefficient of the scheme in FP64 from the float32 inputs
+    (with ``desc.smooth``, from the smoothed sound speed and density)."""
     nd = desc.ndim
     c0 = np.asarray(c0, dtype=np.float64)
     rho0 = np.asarray(rho0, dtype=np.float64)
+    if getattr(desc, "smooth", False):
+        c0 = smooth_medium(c0)
+        rho0 = smooth_medium(rho0)
     shape = c0.shape
     assert shape == tuple(reversed(desc.n[:nd]))
     c_ref = float(c0.max())

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpat.so")
 PAT_OK, PAT_EINVAL, PAT_EUNSTABLE, PAT_ENOMEM, PAT_EHIP, PAT_ENONFINITE, PAT_ENOSYS = range(7)
 PAT_NO_PML = 0x1
 PAT_CHECK_FINITE = 0x2
+PAT_SMOOTH_MEDIUM = 0x4
 PAT_BATCH_NO_FUSE = 0x1
 PAT_BATCH_NO_STAGGER = 0x2
 
@@ -167,7 +168,8 @@ def make_desc(desc, n_sensors: int, check_finite: bool = False) -> CDesc:
     c.pml_alpha = float(desc.pml_alpha)
     c.alpha_power = float(desc.alpha_power)
     c.n_sensors = int(n_sensors)
-    c.flags = (0 if getattr(desc, "pml", True) else PAT_NO_PML) | (PAT_CHECK_FINITE if check_finite else 0)
+    c.flags = ((0 if getattr(desc, "pml", True) else PAT_NO_PML) | (PAT_CHECK_FINITE if check_finite else 0) |
+               (PAT_SMOOTH_MEDIUM if getattr(desc, "smooth", False) else 0))
     return c
 
 

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -40,6 +41,52 @@ namespace {
   } while (0)
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// In-place iterative radix-2 FFT of length n (a power of two), float64;
+// sign -1 forward, +1 inverse (unnormalised).
+void fft_pow2(std::complex<double>* a, int n, int sign) {
+  for (int i = 1, j = 0; i < n; ++i) {
+    int bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (int len = 2; len <= n; len <<= 1) {
+    const double ang = sign * 2.0 * M_PI / len;
+    for (int i = 0; i < n; i += len)
+      for (int k = 0; k < len / 2; ++k) {
+        const std::complex<double> w = std::polar(1.0, ang * k);
+        const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * w;
+        a[i + k] = u + v;
+        a[i + k + len / 2] = u - v;
+      }
+  }
+}
+
+// Spectral smoothing of a medium map (PAT_SMOOTH_MEDIUM): every axis'
+// spectrum multiplied by the Blackman window centred on the zero
+// wavenumber, w(m) = 0.42 + 0.5 cos(2 pi m / n) + 0.08 cos(4 pi m / n),
+// which is 1 at m = 0 and 0 at the Nyquist bin.  The window is a product
+// over the axes, so the filter runs as 1-D passes along each axis.
+void smooth_field(std::vector<double>& f, int nd, const int32_t n[3]) {
+  const int64_t stride[3] = {1, n[0], (int64_t)n[0] * (nd > 1 ? n[1] : 1)};
+  const int64_t N = (int64_t)f.size();
+  for (int j = 0; j < nd; ++j) {
+    const int len = n[j];
+    std::vector<double> w(len);
+    for (int m = 0; m < len; ++m)
+      w[m] = 0.42 + 0.5 * std::cos(2.0 * M_PI * m / len) + 0.08 * std::cos(4.0 * M_PI * m / len);
+    std::vector<std::complex<double>> line(len);
+    for (int64_t base = 0; base < N; ++base) {
+      if ((base / stride[j]) % len != 0) continue;  // one start per line along axis j
+      for (int m = 0; m < len; ++m) line[m] = f[base + m * stride[j]];
+      fft_pow2(line.data(), len, -1);
+      for (int m = 0; m < len; ++m) line[m] *= w[m];
+      fft_pow2(line.data(), len, +1);
+      for (int m = 0; m < len; ++m) f[base + m * stride[j]] = line[m].real() / len;
+    }
+  }
+}
 
 std::mutex g_tw_mu;
 std::vector<int> g_tw_ready;  // per device
@@ -101,7 +148,7 @@ int validate_desc(const pat_desc* d, bool lossy) {
   if (!(d->pml_alpha >= 0) || !std::isfinite(d->pml_alpha)) return PAT_EINVAL;
   if (lossy && !(d->alpha_power > 0 && d->alpha_power < 3 && d->alpha_power != 1.0)) return PAT_EINVAL;
   if (d->n_sensors < 1) return PAT_EINVAL;
-  if (d->flags & ~(PAT_NO_PML | PAT_CHECK_FINITE)) return PAT_EINVAL;
+  if (d->flags & ~(PAT_NO_PML | PAT_CHECK_FINITE | PAT_SMOOTH_MEDIUM)) return PAT_EINVAL;
   return PAT_OK;
 }
 
@@ -220,11 +267,21 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
   PAT_TRY_HIP(hipMemcpyAsync(rho0.data(), rho0_d, N * 4, hipMemcpyDeviceToHost, st));
   if (lossy) PAT_TRY_HIP(hipMemcpyAsync(a0db.data(), alpha0_d, N * 4, hipMemcpyDeviceToHost, st));
   PAT_TRY_HIP(hipStreamSynchronize(st));
-  double cmax = 0;
   for (int64_t i = 0; i < N; ++i) {
     if (!(c0[i] > 0) || !std::isfinite(c0[i]) || !(rho0[i] > 0) || !std::isfinite(rho0[i])) return PAT_EINVAL;
     if (lossy && (!(a0db[i] >= 0) || !std::isfinite(a0db[i]))) return PAT_EINVAL;
-    cmax = std::max(cmax, (double)c0[i]);
+  }
+  // the medium in float64, spectrally smoothed on request (the sound speed
+  // and density maps, as the paper's models were run on smoothed maps)
+  std::vector<double> cd(c0.begin(), c0.end()), rd(rho0.begin(), rho0.end());
+  if (d.flags & PAT_SMOOTH_MEDIUM) {
+    smooth_field(cd, nd, d.n);
+    smooth_field(rd, nd, d.n);
+  }
+  double cmax = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    if (!(cd[i] > 0) || !(rd[i] > 0)) return PAT_EINVAL;
+    cmax = std::max(cmax, cd[i]);
   }
   double dxmin = d.dx[0];
   for (int j = 1; j < nd; ++j) dxmin = std::min(dxmin, d.dx[j]);
@@ -294,10 +351,10 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
   const double a_conv = 100.0 * std::pow(1e-6 / (2.0 * M_PI), y) / (20.0 * std::log10(std::exp(1.0)));
   const double tan_y = std::tan(M_PI * y / 2.0);
   for (int64_t i = 0; i < N; ++i) {
-    const double c = c0[i], r = rho0[i];
+    const double c = cd[i], r = rd[i];
     for (int j = 0; j < nd; ++j) {
       const int64_t ij = (i / strides[j]) % d.n[j];
-      const double rn = (ij + 1 < d.n[j]) ? (double)rho0[i + strides[j]] : r;
+      const double rn = (ij + 1 < d.n[j]) ? rd[i + strides[j]] : r;
       hf(oB[j])[i] = (float)(dt / (0.5 * (r + rn)));
     }
     hf(o_dtr0)[i] = (float)(dt * r);

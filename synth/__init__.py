@@ -66,6 +66,7 @@ class GridDesc:
     pml_alpha: float = 2.0
     alpha_power: float = 1.5
     pml: bool = True
+    smooth: bool = False  # smooth c0 and rho0 spectrally before use
 
     @property
     def shape(self) -> Tuple[int, ...]:
