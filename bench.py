@@ -145,7 +145,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg4")
-    ap.add_argument("--chunk", type=int, default=32, help="graph chunk (steps per captured graph; 1 = eager)")
+    ap.add_argument("--chunk", type=int, default=64, help="graph chunk (steps per captured graph; 1 = eager)")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default column tile widths")

@@ -201,7 +201,7 @@ int pat_adjoint_atd(pat_plan* plan, const float* data, float* img, void* stream)
  * The plans must outlive the batch; a batch is used by one stream at a time.
  *
  *  pat_batch_create   plans: host array of nb plan pointers; chunk >= 1
- *                     (0 selects the default, 32).  All plans must have the
+ *                     (0 selects the default, 64).  All plans must have the
  *                     same ndim.
  *  pat_batch_forward  p0[i], data[i]: host arrays of nb device pointers.
  *  pat_batch_adjoint  data[i], img[i]: host arrays of nb device pointers.

@@ -279,7 +279,7 @@ class Batch:
 
     def __init__(self, plans: Sequence[Plan], chunk: int = 0, parts: int = 0, lanes: int = 0, fuse: bool = True,
                  stagger: bool = True):
-        """chunk: steps per captured graph (0: 32; 1: eager); parts: groups
+        """chunk: steps per captured graph (0: 64; 1: eager); parts: groups
         per size class (0: 2); lanes: streams (0: one per group; fewer:
         groups placed heaviest first on the least-loaded stream); fuse: 2D
         size classes of axes 128/256/512 share their launches; stagger: odd

@@ -461,7 +461,7 @@ enum TunePolicy : int { TP_FASTEST = 0, TP_MAX8, TP_MAX4, TP_EXACT8, TP_COUNT };
 const char* const kPolicyName[TP_COUNT] = {"fastest", "width<=8", "width<=4", "width=8"};
 
 struct pat_batch {
-  int chunk = 32;
+  int chunk = 64;
   std::vector<BatchClass> cls;
   int policy = -1;                 // width policy chosen in context (-1: none)
   float policy_us[TP_COUNT] = {};  // its timing of each policy (0: not timed)
@@ -624,7 +624,7 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
     if (!plans[i] || plans[i]->desc.ndim != plans[0]->desc.ndim) return PAT_EINVAL;
   auto* b = new (std::nothrow) pat_batch();
   if (!b) return PAT_ENOMEM;
-  b->chunk = chunk == 0 ? 32 : chunk;
+  b->chunk = chunk == 0 ? 64 : chunk;
   b->nb = nb;
   b->stagger = !(flags & PAT_BATCH_NO_STAGGER);
   // group by (shape, nt, lossy), then split every group into `parts` equal
