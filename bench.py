@@ -42,6 +42,8 @@ def workload(name: str):
     if name == "cfg3":
         f, c = synth.config3()
         return [f, c], "2D two-level: 512^2/Nt2400 + 256^2/Nt1200 lossy heterogeneous"
+    if name == "cfg5":
+        return [synth.config5()], "3D 128^3 lossy heterogeneous, Nt 800, 128x128 plane of sensors"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -153,7 +155,9 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="streams for the groups (0: one per group)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="run only the isolated kernel-timing phase (for profiling it); no JSON line")
-    ap.add_argument("--time-pass", default="0:1", help="direction:pass_index timed with HIP events")
+    ap.add_argument("--time-pass", default=None,
+                    help="direction:pass_index timed with HIP events (default: the forward velocity row pass, "
+                         "0:1 in 2D, 0:3 in 3D)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="counter probe: a 1 GiB device copy (calibration) and a burst of the roofline "
                          "phase's launches; run under rocprofv3 --pmc")
@@ -176,6 +180,12 @@ def main():
         insts = [synth.Instance(replace(i.desc, nt=min(i.desc.nt, 9)), i.c0, i.rho0, i.alpha0_db, i.sensors,
                                 i.p0, i.name) for i in insts]
     log(f"workload: {wl_name} ({len(insts)} instances)")
+    ndim = insts[0].desc.ndim
+    if args.time_pass is None:
+        args.time_pass = "0:1" if ndim == 2 else "0:3"
+    # algorithmic bytes per grid-point-step (float32): 2D lossy 152; 3D lossy
+    # with homogeneous rho0 184 (the y-z spectral operators as two plane passes)
+    b_alg = 152.0 if ndim == 2 else 184.0
     plans = [pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=dev) for i in insts]
     x_true = [torch.from_numpy(i.p0).to(dev) for i in insts]
     if args.pmc_probe:
@@ -282,6 +292,8 @@ def main():
              (0, 4): "col absorption", (0, 5): "row state+gather", (1, 0): "row adj-state+scatter",
              (1, 1): "col adj-absorption", (1, 2): "row adj-density", (1, 3): "col adj-gradient",
              (1, 4): "row adj-velocity", (1, 5): "col adj-divergence"}
+    if ndim == 3:
+        names = {(0, 3): "row velocity", (0, 7): "row density", (0, 11): "row state+gather"}
     out = {
         "metric": METRIC,
         "value": value,
@@ -314,8 +326,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "kernel_symbol": row_kernel_name(plans, 1) if (tdir, tidx) == (0, 1) else None,
-            "traffic": counter_traffic(row_kernel_name(plans, 1)) if (tdir, tidx) == (0, 1) else None,
+            "kernel_symbol": row_kernel_name(plans, 1) if names.get((tdir, tidx)) == "row velocity" else None,
+            "traffic": (counter_traffic(row_kernel_name(plans, 1)) if names.get((tdir, tidx)) == "row velocity"
+                        else None),
             "launches": k_n,
             "avg_launch_us": (k_ms / k_n * 1e3) if k_n else None,
             "measured_in": "back-to-back launches of the pass over a one-stream batch before the timed "
@@ -328,7 +341,8 @@ def main():
                 "achieved": (s_bytes / (s_ms / 1e3) / 1e9) if s_ms > 0 else None,
                 "note": "eager steps between graph chunks, concurrent with the other streams' passes",
             },
-            "step_frac": value * 152.0 / (HBM_PEAK_GBS * 1e9),
+            "step_frac": value * b_alg / (HBM_PEAK_GBS * 1e9),
+            "bytes_per_gps": b_alg,
         },
     }
     if not args.no_cpu:
