@@ -235,7 +235,7 @@ def main():
             ", ".join(f"{e['n'][0]}:{e['dir']}:{e['pass']}->{e['tile']}" for e in tiles))
     xs = [0.5 * x for x in x_true]
     total_gps = sum(2.0 * p.npoints * p.nt for p in plans)
-    tvw = [torch.empty(max(1, pat.lib().pat_tv_prox_work_bytes(2, pat._i32x3(list(reversed(x.shape))))),
+    tvw = [torch.empty(max(1, pat.lib().pat_tv_prox_work_bytes(x.dim(), pat._i32x3(list(reversed(x.shape))))),
                        dtype=torch.uint8, device=dev) for x in xs]
     alpha = 1e-3
     lam = 1e-3
