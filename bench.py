@@ -245,12 +245,13 @@ def main():
     def step(loss_fn):
         """One gradient-and-prox iteration: the least-squares loss through
         torch.autograd (forward in the Function, the adjoint as its
-        backward), then x <- prox(x - alpha grad)."""
+        backward), then x <- prox(x - alpha grad), the proxes of all
+        instances in one batched call."""
         leaves = [x.detach().requires_grad_(True) for x in xs]
         loss = loss_fn(leaves)
         loss.backward()
-        for k, x in enumerate(leaves):
-            xs[k] = pat.tv_prox(x.detach() - alpha * x.grad, alpha * lam, 20, work=tvw[k])
+        zs = [x.detach() - alpha * x.grad for x in leaves]
+        xs[:] = pat.tv_prox_batched(zs, [alpha * lam] * len(zs), 20, works=tvw)
         return loss
 
     def batched(leaves):

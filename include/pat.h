@@ -326,6 +326,19 @@ int pat_batch_set_tile(pat_batch* batch, const int32_t n[3], int32_t nt, int32_t
 size_t pat_tv_prox_work_bytes(int32_t ndim, const int32_t n[3]);
 int pat_tv_prox(int32_t ndim, const int32_t n[3], const float* z, float* x, double lambda_eff,
                 int32_t n_iter, const float* lower, void* work, size_t work_bytes, void* stream);
+/*
+ * pat_tv_prox_batched -- pat_tv_prox for `count` images of one ndim at once
+ *   (the prox step of many reconstructions in one iteration): every FGP
+ *   iteration is one launch over all the images (24 per launch) instead of
+ *   one per image.  n: host array count x 3; z, x, work: host arrays of
+ *   count device pointers; lambda_eff, work_bytes: host arrays of count;
+ *   lower: NULL or a host array of count device pointers (each may be NULL);
+ *   n_iter common.  Each image's result equals pat_tv_prox's bitwise.
+ *   Everything is validated before anything is enqueued.
+ */
+int pat_tv_prox_batched(int32_t count, int32_t ndim, const int32_t* n, const float* const* z, float* const* x,
+                        const double* lambda_eff, int32_t n_iter, const float* const* lower, void* const* work,
+                        const size_t* work_bytes, void* stream);
 
 /*
  * pat_restrict / pat_prolong -- the transfer operators I_h^{h-1} and

@@ -16,7 +16,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 __all__ = ["lib", "PatError", "Plan", "Batch", "tv_prox", "restrict", "prolong", "dot_f64", "residual_f64",
-           "tv_smooth", "restrict_lower", "axpby", "project",
+           "tv_smooth", "restrict_lower", "axpby", "project", "tv_prox_batched",
            "LIB_PATH", "EXPORTED"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpat.so")
@@ -32,7 +32,8 @@ PAT_BATCH_NO_STAGGER = 0x2
 EXPORTED = [
     "pat_plan_create", "pat_plan_destroy", "pat_plan_info", "pat_forward", "pat_adjoint", "pat_adjoint_atd",
     "pat_forward_range", "pat_batch_create", "pat_batch_create_ex", "pat_batch_destroy", "pat_batch_forward",
-    "pat_batch_adjoint", "pat_tv_prox_work_bytes", "pat_tv_prox", "pat_restrict", "pat_prolong",
+    "pat_batch_adjoint", "pat_tv_prox_work_bytes", "pat_tv_prox", "pat_tv_prox_batched", "pat_restrict",
+    "pat_prolong",
     "pat_dot_f64", "pat_residual_f64", "pat_plan_sync", "pat_strerror", "pat_timing_begin",
     "pat_timing_end", "pat_batch_autotune", "pat_tuning_report", "pat_batch_set_tile", "pat_batch_time_pass",
     "pat_tv_smooth", "pat_restrict_lower", "pat_axpby", "pat_project",
@@ -91,6 +92,8 @@ def lib() -> ctypes.CDLL:
         "pat_batch_adjoint": (ctypes.c_int, [vp, pp, pp, vp]),
         "pat_tv_prox_work_bytes": (sz, [i32, ctypes.POINTER(i32)]),
         "pat_tv_prox": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, f64, i32, vp, vp, sz, vp]),
+        "pat_tv_prox_batched": (ctypes.c_int, [i32, i32, ctypes.POINTER(i32), pp, pp, ctypes.POINTER(f64), i32, pp,
+                                               pp, ctypes.POINTER(sz), vp]),
         "pat_restrict": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, vp]),
         "pat_prolong": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, vp]),
         "pat_dot_f64": (ctypes.c_int, [vp, vp, i64, ctypes.POINTER(f64), vp]),
@@ -434,6 +437,31 @@ def tv_prox(z, lam: float, n_iter: int = 20, lower=None, out=None, work=None):
                              ctypes.c_void_p(work.data_ptr()), ctypes.c_size_t(work.numel()), _stream()),
            "pat_tv_prox")
     return out
+
+
+def tv_prox_batched(zs, lams, n_iter: int = 20, lowers=None, outs=None, works=None):
+    """``tv_prox`` of several images of one dimensionality in one set of
+    launches (pat_tv_prox_batched); returns the list of outputs."""
+    torch = _torch()
+    k = len(zs)
+    nd = zs[0].dim()
+    dims = (ctypes.c_int32 * (3 * k))(*[v for z in zs for v in list(_i32x3(list(reversed(z.shape))))])
+    if outs is None:
+        outs = [torch.empty_like(z) for z in zs]
+    if works is None:
+        works = [torch.empty(max(1, lib().pat_tv_prox_work_bytes(nd, _i32x3(list(reversed(z.shape))))),
+                             dtype=torch.uint8, device=z.device) for z in zs]
+    ptr = lambda xs: (ctypes.c_void_p * k)(*xs)  # noqa: E731
+    zp = ptr([_dev_f32(z, "z").value for z in zs])
+    xp = ptr([_dev_f32(o, "x", z.numel()).value for o, z in zip(outs, zs)])
+    lp = None if lowers is None else ptr([None if lo is None else _dev_f32(lo, "lower", z.numel()).value
+                                          for lo, z in zip(lowers, zs)])
+    wp = ptr([w.data_ptr() for w in works])
+    wb = (ctypes.c_size_t * k)(*[w.numel() for w in works])
+    lam = (ctypes.c_double * k)(*[float(v) for v in lams])
+    _check(lib().pat_tv_prox_batched(k, nd, dims, zp, xp, lam, int(n_iter), lp, wp, wb, _stream()),
+           "pat_tv_prox_batched")
+    return outs
 
 
 def restrict(fine, out=None):

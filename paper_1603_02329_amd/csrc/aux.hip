@@ -3,6 +3,7 @@
 // float64 reductions.  All are O(N) per call (the prox: O(N) per iteration).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <vector>
@@ -42,10 +43,9 @@ inline int blocks_for(long n, int per = 256) { return (int)((n + per - 1) / per)
 // ------------------------------------------------------------------ FGP prox
 // x = max(z - lam * L r, lower), with (L r)_i = sum_a r_a[i] - r_a[i - e_a]
 // (r_a is zero on axis a's last index and outside the grid).
-__global__ void k_prox_primal(Grid3 g, int ndim, const float* __restrict__ z, const float* __restrict__ lower,
-                              const float* __restrict__ r, float lam, float* __restrict__ x) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.N) return;
+__device__ __forceinline__ void prox_primal_at(const Grid3& g, int ndim, long i, const float* __restrict__ z,
+                                               const float* __restrict__ lower, const float* __restrict__ r,
+                                               float lam, float* __restrict__ x) {
   long rem = i;
   int idx[3];
   for (int j = 0; j < 3; ++j) {
@@ -61,13 +61,17 @@ __global__ void k_prox_primal(Grid3 g, int ndim, const float* __restrict__ z, co
   const float lo = lower ? lower[i] : 0.f;
   x[i] = fmaxf(z[i] - lam * div, lo);
 }
+__global__ void k_prox_primal(Grid3 g, int ndim, const float* __restrict__ z, const float* __restrict__ lower,
+                              const float* __restrict__ r, float lam, float* __restrict__ x) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < g.N) prox_primal_at(g, ndim, i, z, lower, r, lam, x);
+}
 
 // p = P_P(r + step * Lt x) with Lt x = x[i] - x[i + e_a] (0 on the last index);
 // r <- p + theta (p - p_prev); p_prev <- p.
-__global__ void k_prox_dual(Grid3 g, int ndim, const float* __restrict__ x, float step, float theta,
-                            float* __restrict__ r, float* __restrict__ pprev) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.N) return;
+__device__ __forceinline__ void prox_dual_at(const Grid3& g, int ndim, long i, const float* __restrict__ x,
+                                             float step, float theta, float* __restrict__ r,
+                                             float* __restrict__ pprev) {
   long rem = i;
   int idx[3];
   for (int j = 0; j < 3; ++j) {
@@ -89,6 +93,55 @@ __global__ void k_prox_dual(Grid3 g, int ndim, const float* __restrict__ x, floa
     r[k] = pa + theta * (pa - pp);
     pprev[k] = pa;
   }
+}
+__global__ void k_prox_dual(Grid3 g, int ndim, const float* __restrict__ x, float step, float theta,
+                            float* __restrict__ r, float* __restrict__ pprev) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < g.N) prox_dual_at(g, ndim, i, x, step, theta, r, pprev);
+}
+
+// Several images in one launch: image k owns blocks [begin[k], begin[k+1]).
+// The argument block stays under the 4 KB of kernel arguments.
+constexpr int kProxBatch = 24;
+struct ProxBatch {
+  int count, ndim;
+  int begin[kProxBatch + 1];
+  Grid3 g[kProxBatch];
+  const float* z[kProxBatch];
+  const float* lower[kProxBatch];
+  float* x[kProxBatch];
+  float* r[kProxBatch];      // dual iterate (ndim * N), then p_prev (ndim * N), then x_t (N)
+  float lam[kProxBatch], step[kProxBatch];
+};
+__device__ __forceinline__ int prox_image(const ProxBatch& b) {
+  int k = 0;
+  while (k + 1 < b.count && (int)blockIdx.x >= b.begin[k + 1]) ++k;
+  return k;
+}
+// final = 0: x_t <- P_C(z - lam L r); final = 1: x <- P_C(z - lam L p_prev)
+__global__ void k_prox_primal_b(ProxBatch b, int final) {
+  const int k = prox_image(b);
+  const long i = (long)(blockIdx.x - b.begin[k]) * blockDim.x + threadIdx.x;
+  const Grid3& g = b.g[k];
+  if (i >= g.N) return;
+  const float* r = b.r[k] + (final ? (long)b.ndim * g.N : 0);
+  float* out = final ? b.x[k] : b.r[k] + 2L * b.ndim * g.N;
+  prox_primal_at(g, b.ndim, i, b.z[k], b.lower[k], r, b.lam[k], out);
+}
+__global__ void k_prox_dual_b(ProxBatch b, float theta) {
+  const int k = prox_image(b);
+  const long i = (long)(blockIdx.x - b.begin[k]) * blockDim.x + threadIdx.x;
+  const Grid3& g = b.g[k];
+  if (i >= g.N) return;
+  float* r = b.r[k];
+  prox_dual_at(g, b.ndim, i, r + 2L * b.ndim * g.N, b.step[k], theta, r, r + (long)b.ndim * g.N);
+}
+__global__ void k_prox_zero_b(ProxBatch b) {  // r and p_prev of every image
+  const int k = prox_image(b);
+  const long i = (long)(blockIdx.x - b.begin[k]) * blockDim.x + threadIdx.x;
+  const Grid3& g = b.g[k];
+  if (i >= g.N) return;
+  for (int a = 0; a < 2 * b.ndim; ++a) b.r[k][(long)a * g.N + i] = 0.f;
 }
 
 __global__ void k_proj(long n, const float* __restrict__ z, const float* __restrict__ lower, float* __restrict__ x) {
@@ -306,6 +359,64 @@ extern "C" size_t pat_tv_prox_work_bytes(int32_t ndim, const int32_t n[3]) {
   Grid3 g;
   if (make_grid(ndim, n, g)) return 0;
   return (size_t)(2 * ndim + 1) * (size_t)g.N * sizeof(float);
+}
+
+extern "C" int pat_tv_prox_batched(int32_t count, int32_t ndim, const int32_t* n, const float* const* z,
+                                   float* const* x, const double* lambda_eff, int32_t n_iter,
+                                   const float* const* lower, void* const* work, const size_t* work_bytes,
+                                   void* stream) {
+  if (count < 0 || (count > 0 && (!n || !z || !x || !lambda_eff || !work || !work_bytes)) || n_iter < 0)
+    return PAT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  // validate everything before launching anything
+  for (int k = 0; k < count; ++k) {
+    Grid3 g;
+    if (make_grid(ndim, n + 3 * k, g)) return PAT_EINVAL;
+    if (!z[k] || !x[k] || z[k] == x[k] || !(lambda_eff[k] >= 0) || !std::isfinite(lambda_eff[k])) return PAT_EINVAL;
+    if (lambda_eff[k] > 0 && n_iter > 0 &&
+        (!work[k] || work_bytes[k] < pat_tv_prox_work_bytes(ndim, n + 3 * k)))
+      return PAT_EINVAL;
+  }
+  std::vector<int> iter;  // images that run FGP iterations; the others are projections
+  for (int k = 0; k < count; ++k) {
+    if (lambda_eff[k] > 0 && n_iter > 0) {
+      iter.push_back(k);
+    } else {
+      const int rc = pat_tv_prox(ndim, n + 3 * k, z[k], x[k], lambda_eff[k], n_iter, lower ? lower[k] : nullptr,
+                                 work[k], work_bytes[k], stream);
+      if (rc) return rc;
+    }
+  }
+  for (size_t k0 = 0; k0 < iter.size(); k0 += kProxBatch) {
+    ProxBatch b{};
+    b.count = (int)std::min<size_t>(kProxBatch, iter.size() - k0);
+    b.ndim = ndim;
+    b.begin[0] = 0;
+    for (int j = 0; j < b.count; ++j) {
+      const int k = iter[k0 + j];
+      make_grid(ndim, n + 3 * k, b.g[j]);
+      b.z[j] = z[k];
+      b.lower[j] = lower ? lower[k] : nullptr;
+      b.x[j] = x[k];
+      b.r[j] = (float*)work[k];
+      b.lam[j] = (float)lambda_eff[k];
+      b.step[j] = (float)(1.0 / (4.0 * ndim * lambda_eff[k]));
+      b.begin[j + 1] = b.begin[j] + blocks_for(b.g[j].N);
+    }
+    const int nb = b.begin[b.count];
+    hipLaunchKernelGGL(k_prox_zero_b, dim3(nb), dim3(256), 0, st, b);
+    double t = 1.0;
+    for (int it = 0; it < n_iter; ++it) {
+      const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+      const float theta = (float)((t - 1.0) / tn);
+      hipLaunchKernelGGL(k_prox_primal_b, dim3(nb), dim3(256), 0, st, b, 0);
+      hipLaunchKernelGGL(k_prox_dual_b, dim3(nb), dim3(256), 0, st, b, theta);
+      t = tn;
+    }
+    hipLaunchKernelGGL(k_prox_primal_b, dim3(nb), dim3(256), 0, st, b, 1);
+    if (hipGetLastError() != hipSuccess) return PAT_EHIP;
+  }
+  return PAT_OK;
 }
 
 extern "C" int pat_tv_prox(int32_t ndim, const int32_t n[3], const float* z, float* x, double lambda_eff,

@@ -62,3 +62,24 @@ def test_dot_f64(n):
     r, half = pat.residual_f64(ta, tb)
     assert np.array_equal(r.cpu().numpy(), a - b)
     assert abs(half - 0.5 * OT.norm2(a - b)) <= 1e-13 * half
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_tv_prox_batched_equals_single(ndim):
+    """The batched prox (more images than one launch takes, mixed sizes,
+    some with a lower bound, one with lambda = 0) equals per-image calls
+    bitwise."""
+    rng = np.random.default_rng(40 + ndim)
+    shapes = [(16, 16), (32, 16), (8, 24), (64, 32)] if ndim == 2 else [(4, 8, 8), (8, 8, 16), (6, 4, 10)]
+    count = 27 if ndim == 2 else 5
+    zs, lams, lowers = [], [], []
+    for k in range(count):
+        sh = shapes[k % len(shapes)]
+        zs.append(torch.from_numpy(rng.standard_normal(sh).astype(np.float32)).to(DEV))
+        lams.append(0.0 if k == 3 else float(rng.uniform(0.05, 0.5)))
+        lowers.append(torch.from_numpy((0.3 * rng.standard_normal(sh)).astype(np.float32)).to(DEV)
+                      if k % 3 == 0 else None)
+    outs = pat.tv_prox_batched(zs, lams, 20, lowers=lowers)
+    for k in range(count):
+        ref = pat.tv_prox(zs[k], lams[k], 20, lower=lowers[k])
+        assert torch.equal(outs[k], ref), k
