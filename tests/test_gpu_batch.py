@@ -97,6 +97,34 @@ def test_fused_batch_matches_eager_bitwise(lossy, chunk, parts, lanes, tune):
     b.close()
 
 
+def test_fused_mixed_physics_bitwise():
+    """Lossy and lossless classes in one batch: each physics fuses its own
+    size classes (the pass sequences differ), a class of another size range
+    (64^2) stays unfused beside them; all equal the eager path bitwise."""
+    specs = [dict(n=(128, 128), nt=7, ns=5, pml=6, lossy=True), dict(n=(256, 256), nt=11, ns=6, pml=8, lossy=True),
+             dict(n=(128, 128), nt=9, ns=4, pml=6, lossy=False), dict(n=(256, 128), nt=5, ns=5, pml=6, lossy=False),
+             dict(n=(64, 64), nt=8, ns=4, pml=4, lossy=True)]
+    insts = [synth.small_instance(880 + i, **s) for i, s in enumerate(specs)]
+    plans = [pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=DEV) for i in insts]
+    p0 = [torch.from_numpy(i.p0).to(DEV) for i in insts]
+    ref_d = [p.forward(x).clone() for p, x in zip(plans, p0)]
+    rng = np.random.default_rng(9)
+    hs = [torch.from_numpy(rng.standard_normal((i.desc.nt, i.ns)).astype(np.float32)).to(DEV) for i in insts]
+    ref_i = [p.adjoint(h).clone() for p, h in zip(plans, hs)]
+    b = pat.Batch(plans, chunk=4)
+    rep = b.autotune(reps=2)
+    fused = [tuple(map(tuple, e["fused"])) for e in rep if "fused" in e]
+    assert {(128, 128), (256, 256)} <= set(s for f in fused for s in f)
+    for r in range(2):
+        d = b.forward(p0)
+        im = b.adjoint(hs)
+        torch.cuda.synchronize()
+        for k in range(len(insts)):
+            assert torch.equal(d[k], ref_d[k]), (r, k)
+            assert torch.equal(im[k], ref_i[k]), (r, k)
+    b.close()
+
+
 def test_forward_range_resume_is_bitwise():
     inst = synth.small_instance(600, (64, 64), nt=37, ns=7, pml=5, lossy=True)
     plan = pat.Plan(inst.desc, inst.c0, inst.rho0, inst.alpha0_db, inst.sensors, device=DEV)
