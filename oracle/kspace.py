@@ -147,6 +147,7 @@ class OraclePlan:
     idx: np.ndarray
     w: np.ndarray
     nt: int
+    smooth_p0: bool = False      # S in H = H0 S and H^T = S H0^T (``smooth_initial``)
 
 
 def _bcast(v: np.ndarray, ndim: int, j: int) -> np.ndarray:
@@ -175,6 +176,16 @@ def smooth_medium(f: np.ndarray) -> np.ndarray:
         sh[ax] = n
         W = W * blackman_k(n).reshape(sh)
     return np.fft.ifftn(W * np.fft.fftn(f)).real
+
+
+def smooth_initial(f: np.ndarray) -> np.ndarray:
+    """The smoothing S of the initial pressure (section VI-A: the forward
+    model filters the high frequencies of p0 with a self-adjoint operator,
+    which the adjoint then includes).  Reading: the spectral window of
+    ``smooth_medium`` -- real and even in k, so that S is a real symmetric
+    matrix and the operator pair stays exactly transposed:
+    H = H0 S, H^T = S H0^T."""
+    return smooth_medium(f)
 
 
 def make_plan(desc, c0, rho0, alpha0_db, sensors) -> OraclePlan:
@@ -234,7 +245,8 @@ def make_plan(desc, c0, rho0, alpha0_db, sensors) -> OraclePlan:
     idx, w = sensor_weights(desc, sensors)
     return OraclePlan(desc=desc, ndim=nd, shape=shape, dt=dt, c_ref=c_ref, lossy=lossy, c0=c0,
                       rho0=rho0, c0sq=c0 ** 2, tau=tau, eta=eta, rho0_sg=rho0_sg, a=a, b=b, L1=L1,
-                      L2=L2, Q=Q, Qsg=Qsg, idx=idx, w=w, nt=int(desc.nt))
+                      L2=L2, Q=Q, Qsg=Qsg, idx=idx, w=w, nt=int(desc.nt),
+                      smooth_p0=bool(getattr(desc, "smooth_p0", False)))
 
 
 # --------------------------------------------------------------------------
@@ -271,6 +283,8 @@ class ForwardState:
     def __init__(self, plan: OraclePlan, p0: np.ndarray):
         nd = plan.ndim
         p0 = np.asarray(p0, dtype=np.float64)
+        if plan.smooth_p0:
+            p0 = smooth_initial(p0)                 # the model's initial pressure is S p0
         P = _fft(p0)
         self.n = 0
         self.p = p0.copy()
@@ -361,7 +375,7 @@ def adjoint(plan: OraclePlan, h: np.ndarray, nsteps_done: Optional[Callable] = N
             nsteps_done(n)
     img = pbar + sum(rbar) / (nd * plan.c0sq)
     img = img - (dt / 2.0) * sum(spectral(plan.b[j], ubar[j] / plan.rho0_sg[j]) for j in range(nd))
-    return img
+    return smooth_initial(img) if plan.smooth_p0 else img     # S^T = S
 
 
 # --------------------------------------------------------------------------
@@ -411,4 +425,5 @@ def adjoint_atd(plan: OraclePlan, h: np.ndarray) -> np.ndarray:
             p = plan.c0sq * rs - plan.rho0 * (A1 + A2)                                      # eq. statea
         else:
             p = plan.c0sq * rs
-    return sum(rho) / plan.rho0                                                             # eq. adjj
+    img = sum(rho) / plan.rho0                                                              # eq. adjj
+    return smooth_initial(img) if plan.smooth_p0 else img

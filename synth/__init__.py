@@ -67,6 +67,7 @@ class GridDesc:
     alpha_power: float = 1.5
     pml: bool = True
     smooth: bool = False  # smooth c0 and rho0 spectrally before use
+    smooth_p0: bool = False  # smooth the initial pressure inside H (and H^T)
 
     @property
     def shape(self) -> Tuple[int, ...]:

@@ -398,3 +398,69 @@ def test_smoothed_plan_uses_the_smoothed_medium():
     cs = K.smooth_medium(inst.c0)
     assert np.max(np.abs(op.c0 - cs)) == 0.0 and op.c_ref == cs.max()
     assert np.max(np.abs(op.rho0 - K.smooth_medium(inst.rho0))) == 0.0
+
+
+# ---------------------------------------------------------------------------
+# smoothing of the initial pressure inside H and H^T (plan option)
+# ---------------------------------------------------------------------------
+
+def _conv_window(f):
+    """Explicit circular convolution, axis by axis, with the inverse DFT of
+    the window (a real, even kernel): O(n^2) per line, no FFT."""
+    out = np.asarray(f, dtype=np.float64).copy()
+    for ax, n in enumerate(out.shape):
+        w = K.blackman_k(n)
+        m = np.arange(n)
+        kern = np.array([np.sum(w * np.cos(2 * np.pi * m * x / n)) / n for x in range(n)])
+        mat = np.array([[kern[(x - s) % n] for s in range(n)] for x in range(n)])
+        out = np.moveaxis(np.tensordot(mat, np.moveaxis(out, ax, 0), axes=(1, 0)), 0, ax)
+    return out
+
+
+@pytest.mark.parametrize("n,lossy", [((16, 12), True), ((16, 16), False), ((8, 8, 8), True)])
+def test_smoothed_p0_forward_and_adjoint_by_convolution(n, lossy):
+    """With the option, H p0 is the plain H applied to the explicitly
+    convolved p0, and H^T h the convolved plain H^T h (also for the
+    adjoint-then-discretize operator): the filter acts on the initial
+    pressure alone, before every use of it (density, velocity start,
+    sample 0), and the adjoint applies it last."""
+    inst = synth.small_instance(23, n, nt=7, ns=5, pml=2, lossy=lossy, hetero=True)
+    plain = _plan(inst)
+    sm = _plan(inst, smooth_p0=True)
+    assert sm.smooth_p0 and not plain.smooth_p0
+    d_s = K.forward(sm, inst.p0)
+    d_ref = K.forward(plain, _conv_window(inst.p0))
+    assert np.max(np.abs(d_s - d_ref)) <= 1e-12 * np.max(np.abs(d_ref))
+    assert np.max(np.abs(d_s - K.forward(plain, inst.p0))) > 1e-3 * np.max(np.abs(d_ref))  # not a no-op
+    h = np.random.default_rng(5).standard_normal(d_s.shape)
+    for op in (K.adjoint, K.adjoint_atd):
+        a_s = op(sm, h)
+        a_ref = _conv_window(op(plain, h))
+        assert np.max(np.abs(a_s - a_ref)) <= 1e-12 * np.max(np.abs(a_ref))
+
+
+@pytest.mark.parametrize("n,nt,ns", [((8, 8), 9, 4), ((4, 4, 4), 5, 3)])
+def test_smoothed_p0_dense_transpose(n, nt, ns):
+    """The filtered pair stays exactly transposed (S is symmetric): dense H
+    and H^T built column by column agree entrywise."""
+    inst = synth.small_instance(29, n, nt=nt, ns=ns, pml=1 if len(n) == 3 else 2, lossy=True, hetero=True)
+    plan = _plan(inst, smooth_p0=True)
+    A, AT = _dense(plan, plan.shape, nt, ns)
+    assert np.abs(A.T - AT).max() <= 1e-13 * np.abs(A).max()
+
+
+def test_smoothed_p0_single_mode_and_constant():
+    """Periodic homogeneous grid: a single Fourier mode of p0 reaches the
+    sensors scaled by the window's value at its bins; a constant p0 is left
+    unchanged (the window is 1 at k = 0); the Nyquist mode is removed."""
+    inst = synth.small_instance(31, (16, 16), nt=6, ns=4, pml=0, lossy=False, hetero=False)
+    plain = _plan(inst, pml=False)
+    sm = _plan(inst, pml=False, smooth_p0=True)
+    x = np.arange(16)
+    for mx, my in ((3, 0), (2, 5), (8, 1)):
+        p0 = np.cos(2 * np.pi * mx * x / 16)[None, :] * np.cos(2 * np.pi * my * x / 16)[:, None]
+        scale = K.blackman_k(16)[mx] * K.blackman_k(16)[my]
+        ref = scale * K.forward(plain, p0)
+        assert np.max(np.abs(K.forward(sm, p0) - ref)) <= 1e-12 * max(1.0, np.max(np.abs(K.forward(plain, p0))))
+    c = np.full((16, 16), 0.7)
+    assert np.max(np.abs(K.forward(sm, c) - K.forward(plain, c))) <= 1e-12
