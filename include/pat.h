@@ -48,6 +48,13 @@ extern "C" {
                                    spectrum times the Blackman window centred on k = 0,
                                    0.42 + 0.5 cos(2 pi m/n) + 0.08 cos(4 pi m/n); float64,
                                    on the host, at plan creation */
+#define PAT_SMOOTH_P0     0x8u  /* filter the initial pressure inside the operators
+                                   (section VI-A: a self-adjoint smoothing of p0 in
+                                   every forward, included in the adjoint):
+                                   H = H0 S, H^T = S H0^T with S = F^-1 w F and w the
+                                   product over the axes of the window above (real and
+                                   even, so S is symmetric); pat_adjoint_atd also ends
+                                   with S */
 
 /* pat_batch_create_ex flags */
 #define PAT_BATCH_NO_FUSE 0x1u  /* keep every size class in launches of its own */
@@ -134,7 +141,8 @@ int pat_plan_info(const pat_plan* plan, pat_info* info);
  *
  * Runs the k-space scheme for nt-1 steps from p(0) = p0, u(0) = 0
  * (equation initial) and samples the pressure at the sensors by linear
- * interpolation at every step, t = 0 included.
+ * interpolation at every step, t = 0 included.  With PAT_SMOOTH_P0 the
+ * scheme starts from S p0 instead (S: the flag's window filter).
  *
  *  p0    device, N floats (initial pressure, the image x).
  *  data  device, nt*n_sensors floats, written as data[n][s].
@@ -147,7 +155,8 @@ int pat_forward(pat_plan* plan, const float* p0, float* data, void* stream);
  *   <pat_forward(p0), h> = <p0, pat_adjoint(h)>   (equation adj2),
  * up to float32 rounding.  It steps the time-reversed system of equations
  * moma/massa/statea with the data injected as a mass source and returns
- * the transposed initial condition (the discrete rho*(T)/rho0 of adjj).
+ * the transposed initial condition (the discrete rho*(T)/rho0 of adjj),
+ * filtered by S when the plan has PAT_SMOOTH_P0.
  *
  *  data  device, nt*n_sensors floats, [n][s].
  *  img   device, N floats, overwritten.

@@ -106,6 +106,10 @@ double pass_bytes_per_point(const PassOp& op, int ndim, int lossy) {
     case R_ATD_2LL: return 4.0 * (3 * d + 3);    // S_j, rho_j, dt rho0, c0^2 -> rho_j, S0
     case R_ATD_3: return 4.0 * (d + 5);          // S1, S2, rho_j, c0^2, dt rho0 -> S0
     case R_ATD_FINAL: return 4.0 * (d + 2);      // rho_j, dt rho0 -> image
+    case R_FILT_IN: return 8.0;                  // field -> S0
+    case R_FWD_INIT_F: return 4.0 * (d + 3);     // S0, 1/(d c0^2) -> rho_j, S0
+    case R_FILT_RE: return 8.0;                  // image -> S0
+    case R_FILT_OUT: return 8.0;                 // S0 -> image
     default: return 0.0;
   }
 }
@@ -243,6 +247,32 @@ struct Runner {
     const hipError_t e = fused ? launch_row_fused(k, L, sa) : launch_row(k, ndim, nx, L, sa);
     return e == hipSuccess ? PAT_OK : PAT_EHIP;
   }
+  // S0 <- w S0: the smoothing window of p0 along y (2D), or along y and z
+  // between the y-transform passes (3D); the x factor rides in the same pass
+  int window(hipStream_t st) const {
+    const ColSpec w{1, 1, {M_WIN, 0, 0}, 0};
+    if (ndim == 2) return launch_col_w(w, ColVariant{0, 1}, st, nullptr, nullptr);
+    int rc = launch_col_w(ColSpec{3, 1, {0, 0, 0}, 0}, ColVariant{0, 1}, st, nullptr, nullptr);
+    if (!rc) rc = launch_col_w(w, ColVariant{0, 1}, st, nullptr, nullptr);
+    if (!rc) rc = launch_col_w(ColSpec{4, 1, {0, 0, 0}, 0}, ColVariant{0, 1}, st, nullptr, nullptr);
+    return rc;
+  }
+  // the forward's initial state, from S p0 when the plans smooth p0
+  int init(bool smooth, hipStream_t st) const {
+    if (!smooth) return row(R_FWD_INIT, StepArg{nullptr, 0}, st);
+    int rc = row(R_FILT_IN, StepArg{nullptr, 0}, st);
+    if (!rc) rc = window(st);
+    if (!rc) rc = row(R_FWD_INIT_F, StepArg{nullptr, 0}, st);
+    return rc;
+  }
+  // image <- S image (the adjoint's last operator when the plans smooth p0)
+  int smooth_out(bool smooth, hipStream_t st) const {
+    if (!smooth) return PAT_OK;
+    int rc = row(R_FILT_RE, StepArg{nullptr, 0}, st);
+    if (!rc) rc = window(st);
+    if (!rc) rc = row(R_FILT_OUT, StepArg{nullptr, 0}, st);
+    return rc;
+  }
   int reduce(int n0, int n1, hipStream_t st, int blocks) const {
     return launch_reduce(Launch{recs, red_tab, blocks, st}, n0, n1) == hipSuccess ? PAT_OK : PAT_EHIP;
   }
@@ -283,6 +313,8 @@ int set_io(const pat_plan* p, const float* in, float* out, hipStream_t st) {
 
 int reduce_blocks(long nsamples, long ns) { return (int)((nsamples * ns + 255) / 256); }
 
+bool smooths_p0(const pat_plan* p) { return (p->desc.flags & PAT_SMOOTH_P0) != 0; }
+
 }  // namespace
 }  // namespace pat
 
@@ -294,7 +326,7 @@ extern "C" int pat_forward(pat_plan* p, const float* p0, float* data, void* stre
   hipStream_t st = (hipStream_t)stream;
   const Runner R = eager_runner(p);
   int rc = set_io(p, p0, data, st);
-  if (!rc) rc = R.row(R_FWD_INIT, StepArg{nullptr, 0}, st);
+  if (!rc) rc = R.init(smooths_p0(p), st);
   if (!rc) rc = R.steps(0, 0, p->desc.nt - 1, st);
   if (!rc) rc = R.reduce(0, 0, st, reduce_blocks(p->desc.nt, p->desc.n_sensors));
   return rc;
@@ -306,9 +338,13 @@ extern "C" int pat_adjoint(pat_plan* p, const float* data, float* img, void* str
   const Runner R = eager_runner(p);
   int rc = set_io(p, data, img, st);
   if (rc) return rc;
-  if (p->desc.nt == 1) return R.row(R_ADJ_SCATTER_ONLY, StepArg{nullptr, 0}, st);
-  rc = R.steps(1, 0, p->desc.nt - 1, st);
-  if (!rc) rc = R.row(R_ADJ_FINAL, StepArg{nullptr, 0}, st);
+  if (p->desc.nt == 1) {
+    rc = R.row(R_ADJ_SCATTER_ONLY, StepArg{nullptr, 0}, st);
+  } else {
+    rc = R.steps(1, 0, p->desc.nt - 1, st);
+    if (!rc) rc = R.row(R_ADJ_FINAL, StepArg{nullptr, 0}, st);
+  }
+  if (!rc) rc = R.smooth_out(smooths_p0(p), st);
   return rc;
 }
 
@@ -324,6 +360,7 @@ extern "C" int pat_adjoint_atd(pat_plan* p, const float* data, float* img, void*
   if (hipMemsetAsync(p->hp.S[0], 0, sizeof(float) * p->npoints, st) != hipSuccess) return PAT_EHIP;
   rc = R.steps(2, 0, p->desc.nt - 1, st);
   if (!rc) rc = R.row(R_ATD_FINAL, StepArg{nullptr, 0}, st);
+  if (!rc) rc = R.smooth_out(smooths_p0(p), st);
   return rc;
 }
 
@@ -340,7 +377,7 @@ extern "C" int pat_forward_range(pat_plan* p, const float* p0, float* data, int3
   if (rc) return rc;
   int s0;
   if (n_begin == 0) {
-    rc = R.row(R_FWD_INIT, StepArg{nullptr, 0}, st);
+    rc = R.init(smooths_p0(p), st);
     s0 = 0;
   } else {
     if (hipMemcpyAsync(state, state_io, p->state_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return PAT_EHIP;
@@ -391,6 +428,7 @@ namespace {
 
 struct BatchClass {
   int ndim, nx, ny, nz, nt, lossy, ns_max;
+  bool smooth_p0 = false;  // the instances smooth p0 (all or none of a class)
   // fused group: instances of several 2D sizes in every launch (nx, ny the
   // largest, nt - 1 = span = the most steps of any instance)
   int fused = 0;
@@ -588,16 +626,18 @@ int batch_run(pat_batch* b, int dir, const float* const* in, float* const* out, 
     hipEvent_t lead = (stagger && k == 0) ? b->lead : nullptr;
     const bool follow = stagger && (k & 1);
     if (dir == 0) {
-      rc = R.row(R_FWD_INIT, StepArg{nullptr, 0}, c.st);
+      rc = R.init(c.smooth_p0, c.st);
       if (!rc && follow && hipStreamWaitEvent(c.st, b->lead, 0) != hipSuccess) rc = PAT_EHIP;
       if (!rc) rc = run_steps(b, c, 0, c.nt - 1, lead);
       if (!rc) rc = R.reduce(0, 0, c.st, c.red_n);
     } else if (c.nt == 1) {
       rc = R.row(R_ADJ_SCATTER_ONLY, StepArg{nullptr, 0}, c.st);
+      if (!rc) rc = R.smooth_out(c.smooth_p0, c.st);
     } else {
       if (follow && hipStreamWaitEvent(c.st, b->lead, 0) != hipSuccess) rc = PAT_EHIP;
       if (!rc) rc = run_steps(b, c, 1, c.nt - 1, lead);
       if (!rc) rc = R.row(R_ADJ_FINAL, StepArg{nullptr, 0}, c.st);
+      if (!rc) rc = R.smooth_out(c.smooth_p0, c.st);
     }
     if (rc) return rc;
     if (hipEventRecord(c.done, c.st) != hipSuccess) return PAT_EHIP;
@@ -637,11 +677,11 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
   std::vector<std::vector<int>> groups;
   std::vector<int> group_fused;
   {
-    std::map<std::tuple<int, int, int, int, int>, int> key2grp;
+    std::map<std::tuple<int, int, int, int, int, int>, int> key2grp;
     std::vector<std::vector<int>> shape_groups;
     for (int i = 0; i < nb; ++i) {
       const pat_plan* p = plans[i];
-      const auto key = std::make_tuple(p->hp.n[0], p->hp.n[1], p->hp.n[2], p->desc.nt, p->lossy);
+      const auto key = std::make_tuple(p->hp.n[0], p->hp.n[1], p->hp.n[2], p->desc.nt, p->lossy, (int)smooths_p0(p));
       auto it = key2grp.find(key);
       if (it == key2grp.end()) {
         it = key2grp.emplace(key, (int)shape_groups.size()).first;
@@ -658,10 +698,16 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
              fused_size(p->hp.n[1]) && p->desc.nt >= 2;
     };
     auto area = [&](const std::vector<int>& g) { return (long)plans[g[0]]->hp.n[0] * plans[g[0]]->hp.n[1]; };
-    for (int lossy = 0; lossy < 2; ++lossy) {
+    // the classes of one fused group share the pass sequence: the same
+    // physics (lossy or not) and the same initial and final passes
+    for (int phys = 0; phys < 4; ++phys) {
+      const int lossy = phys & 1;
+      const bool smooth = phys >> 1;
       std::vector<int> fs;
-      for (size_t k = 0; k < shape_groups.size(); ++k)
-        if (plans[shape_groups[k][0]]->lossy == lossy && fusable(shape_groups[k])) fs.push_back((int)k);
+      for (size_t k = 0; k < shape_groups.size(); ++k) {
+        const pat_plan* p = plans[shape_groups[k][0]];
+        if (p->lossy == lossy && smooths_p0(p) == smooth && fusable(shape_groups[k])) fs.push_back((int)k);
+      }
       if (fs.size() < 2) continue;
       std::stable_sort(fs.begin(), fs.end(), [&](int x, int y) {
         const long ax = area(shape_groups[x]), ay = area(shape_groups[y]);
@@ -700,6 +746,7 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
     c.nz = p0->hp.n[2];
     c.nt = p0->desc.nt;
     c.lossy = p0->lossy;
+    c.smooth_p0 = smooths_p0(p0);
     c.fused = group_fused[gi];
     c.ns_max = 0;
     for (int i : g) {

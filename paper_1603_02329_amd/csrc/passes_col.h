@@ -58,9 +58,10 @@ __device__ __forceinline__ XBin xbin(const DevPlan& P, int kxi) {
 }
 
 // Multiplier families of the column passes (compile-time): staggered
-// derivatives a_j = i k_j kappa e^{+i k_j dx_j/2}, b_j (e^{-...}), or the
-// fractional Laplacians |k|^(y-2)/dt, |k|^(y-1).
-enum ColFam : int { F_A = 0, F_B = 1, F_ABS = 2 };
+// derivatives a_j = i k_j kappa e^{+i k_j dx_j/2}, b_j (e^{-...}), the
+// fractional Laplacians |k|^(y-2)/dt, |k|^(y-1), or the separable smoothing
+// window of the initial pressure, w_x(kx) w_y(ky) [w_z(kz)].
+enum ColFam : int { F_A = 0, F_B = 1, F_ABS = 2, F_WIN = 3 };
 
 // Column pass over a tile of TILE consecutive packed x-bins and all NA points
 // of one axis.
@@ -251,7 +252,7 @@ __device__ __forceinline__ void colm_pass(const DevPlan& P, int tile_index, cons
   auto in_ptr = [&](int k) -> const float2* { return MODE == 0 ? P.S[0] : P.S[fbase + k]; };
   auto out_ptr = [&](int i) -> float2* { return MODE == 0 ? P.S[1 + i] : (MODE == 1 ? P.S[fbase + i] : P.S[0]); };
   // multiplier kind of input / output i: derivative axis (F_A, F_B) or Mult kind
-  auto which_of = [&](int i) { return FAM == F_ABS ? spec.mult[i] : i; };
+  auto which_of = [&](int i) { return (FAM == F_ABS || FAM == F_WIN) ? spec.mult[i] : i; };
 
   float2 vin[UPFRONT ? NIN : 1][E];
   if constexpr (UPFRONT) {
@@ -273,6 +274,16 @@ __device__ __forceinline__ void colm_pass(const DevPlan& P, int tile_index, cons
   float k2v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) k2v[m] = gld(P.ksq[ax_last], tb + TC * m);
+  // window family: the x (and, along z, the y) factor of this column, the
+  // x factor at x-bin nx/2 for the packed column 0, and the along-axis one
+  float wfix = 1.f, wfixN = 1.f, wv[E];
+  if constexpr (FAM == F_WIN) {
+    const float wy = q.along_y ? 1.f : gld(P.win[1], kyf);
+    wfix = gld(P.win[0], unpackedB ? q.M : q.kxi) * wy * P.scale;
+    wfixN = gld(P.win[0], q.M) * wy * P.scale;
+#pragma unroll
+    for (int m = 0; m < E; ++m) wv[m] = gld(P.win[ax_last], tb + TC * m);
+  }
   // factor g of element m (kappa/N, or the Laplacian factor)
   auto factor = [&](float k2, int which) -> float {
     if constexpr (FAM == F_ABS) {
@@ -290,6 +301,7 @@ __device__ __forceinline__ void colm_pass(const DevPlan& P, int tile_index, cons
     return gld(SA ? P.shA[axis] : P.shB[axis], tb + TC * m);
   };
   auto mult = [&](int which, int m, bool nyq) -> float2 {
+    if constexpr (FAM == F_WIN) return f2((nyq ? wfixN : wfix) * wv[m], 0.f);
     const float g = factor((nyq ? k2fixN : k2fix) + k2v[m], which);
     if constexpr (FAM == F_ABS) return f2(g, 0.f);
     else return scl2(g, shift(which, m, nyq));
@@ -392,6 +404,7 @@ __global__ void __launch_bounds__((ColGeo<NA, TW>::NTH)) k_colm(const DevPlan* _
 // multiplier family from the kinds: derivatives a_j / b_j listed in axis
 // order, or the two fractional Laplacians
 inline int col_family(const ColSpec& spec) {
+  if (spec.mult[0] == M_WIN) return F_WIN;
   if (spec.mult[0] == M_L1DT || spec.mult[0] == M_L2) return F_ABS;
   return (spec.mult[0] >= M_BX) ? F_B : F_A;
 }
@@ -409,7 +422,14 @@ hipError_t launch_colm(const ColSpec& spec, const Launch& L) {
     else if (fam == F_B) PAT_COLM(MODE, NF, F_B, GY);   \
     else PAT_COLM(MODE, NF, F_ABS, GY);                 \
   } while (0)
-  if constexpr (FPB != 1) {
+  if (fam == F_WIN) {  // the smoothing window: one field, mode 1
+    if constexpr (FPB == 1) {
+      if (spec.mode != 1 || spec.nfield != 1) return hipErrorInvalidValue;
+      PAT_COLM(1, 1, F_WIN, 1);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  } else if constexpr (FPB != 1) {
     if (spec.mode != 1 || spec.nfield != FPB) return hipErrorInvalidValue;
     PAT_COLM_FAM(1, FPB, 1);
   } else if (spec.mode == 1) {

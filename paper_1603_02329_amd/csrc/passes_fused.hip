@@ -102,6 +102,10 @@ hipError_t launch_row_fused(RowKind kind, const Launch& L, StepArg s) {
     PAT_ROWF_CASE(R_ADJ_1)
     PAT_ROWF_CASE(R_ADJ_FINAL)
     PAT_ROWF_CASE(R_ADJ_SCATTER_ONLY)
+    PAT_ROWF_CASE(R_FILT_IN)
+    PAT_ROWF_CASE(R_FWD_INIT_F)
+    PAT_ROWF_CASE(R_FILT_RE)
+    PAT_ROWF_CASE(R_FILT_OUT)
     default: return hipErrorInvalidValue;
   }
 #undef PAT_ROWF_CASE
@@ -128,6 +132,8 @@ hipError_t launch_colf(const ColSpec& spec, int fpb, const Launch& L, StepArg s)
     else PAT_COLF(1, 2, F_ABS, 2, 1);
   } else if (spec.mode == 2 && spec.nfield == 2 && fam == F_B && fpb == 1) {
     PAT_COLF(2, 2, F_B, 1, 1);
+  } else if (spec.mode == 1 && spec.nfield == 1 && fam == F_WIN && fpb == 1) {
+    PAT_COLF(1, 1, F_WIN, 1, 1);
   } else {
     return hipErrorInvalidValue;
   }

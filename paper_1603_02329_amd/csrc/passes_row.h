@@ -230,11 +230,16 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
   auto qpair = [&](int j, const float2& qx) { return j == 0 ? qx : f2(qrow[j], qrow[j]); };
   auto qspair = [&](int j, const float2& qx) { return j == 0 ? qx : f2(qsrow[j], qsrow[j]); };
 
-  if constexpr (K == R_FWD_INIT) {
+  if constexpr (K == R_FWD_INIT || K == R_FWD_INIT_F) {
     float2 p[E], ic[E];
-    io.ld(P.in, p);
+    if constexpr (K == R_FWD_INIT) io.ld(P.in, p);
+    else io.ld(P.S[0], p);  // the windowed spectrum of p0
     io.ld(P.inv_dc2, ic);
     __syncthreads();  // twiddles
+    if constexpr (K == R_FWD_INIT_F) {
+      c2r<N>(p, L, t, tws);  // the smoothed p0 (the window pass holds the 1/N)
+      WaveSync::sync();
+    }
     float2 rr[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -552,6 +557,18 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
 #pragma unroll
     for (int m = 0; m < E; ++m) rs[m] = f2(P.dt * rs[m].x / dr[m].x, P.dt * rs[m].y / dr[m].y);
     io.st(P.out, rs);
+  } else if constexpr (K == R_FILT_IN || K == R_FILT_RE) {
+    // x-spectrum of a real field: p0 (forward) or the image (adjoint)
+    float2 v[E];
+    io.ld(K == R_FILT_IN ? P.in : P.out, v);
+    __syncthreads();  // twiddles
+    r2c<N>(v, P.S[0] + io.base, L, t, valid, tws);
+  } else if constexpr (K == R_FILT_OUT) {
+    float2 v[E];
+    io.ld(P.S[0], v);
+    __syncthreads();  // twiddles
+    c2r<N>(v, L, t, tws);
+    io.st(P.out, v);
   } else if constexpr (K == R_ADJ_FINAL || K == R_ADJ_SCATTER_ONLY) {
     float2 v[E], rs[E], ic[E];
     if constexpr (K == R_ADJ_FINAL) {

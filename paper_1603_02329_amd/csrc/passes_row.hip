@@ -76,6 +76,10 @@ static hipError_t launch_row_nd(RowKind kind, const Launch& L, StepArg s) {
     PAT_ROW_CASE(R_ATD_2LL)
     PAT_ROW_CASE(R_ATD_3)
     PAT_ROW_CASE(R_ATD_FINAL)
+    PAT_ROW_CASE(R_FILT_IN)
+    PAT_ROW_CASE(R_FWD_INIT_F)
+    PAT_ROW_CASE(R_FILT_RE)
+    PAT_ROW_CASE(R_FILT_OUT)
     default: return hipErrorInvalidValue;
   }
 #undef PAT_ROW_CASE

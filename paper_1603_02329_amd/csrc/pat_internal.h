@@ -76,6 +76,7 @@ struct DevPlan {
   const float* ksq[3];     // k_j^2; x: packed bins 0..nx/2, y/z: 0..n-1
   const float2* shA[3];    // i k_j exp(+i k_j dx_j/2)
   const float2* shB[3];    // i k_j exp(-i k_j dx_j/2)
+  const float* win[3];     // smoothing window of p0 (PAT_SMOOTH_P0), bins as ksq
 
   // state (N floats each) and packed spectra (N/2 complex each)
   float* u[3];
@@ -132,6 +133,7 @@ enum Mult : int32_t {
   M_BX = 3, M_BY = 4, M_BZ = 5,   // b_j = i k_j kappa e^{-i k_j dx_j/2}
   M_L1DT = 6,                      // |k|^(y-2) / dt
   M_L2 = 7,                        // |k|^(y-1)
+  M_WIN = 8,                       // separable smoothing window of p0, real
 };
 
 // ---------------------------------------------------------------- launchers
@@ -164,7 +166,13 @@ enum RowKind : int32_t {
   R_ATD_2LL = 12,    // lossless: density + data source + equation of state
   R_ATD_3 = 13,      // lossy equation of state (statea)
   R_ATD_FINAL = 14,  // image = sum_j rho*_j / rho0 (eq. adjj)
-  R_COUNT = 15
+  // smoothing of the initial pressure (PAT_SMOOTH_P0): S = F^-1 w F, the
+  // window w applied by a column pass (M_WIN) between two row passes
+  R_FILT_IN = 15,    // S0 <- F_x in         (forward: p0)
+  R_FWD_INIT_F = 16, // R_FWD_INIT from the filtered p0 = F_x^-1 S0
+  R_FILT_RE = 17,    // S0 <- F_x out        (adjoint: the image)
+  R_FILT_OUT = 18,   // out <- F_x^-1 S0
+  R_COUNT = 19
 };
 
 hipError_t launch_row(RowKind kind, int ndim, int nx, const Launch& L, StepArg s);

@@ -148,7 +148,7 @@ int validate_desc(const pat_desc* d, bool lossy) {
   if (!(d->pml_alpha >= 0) || !std::isfinite(d->pml_alpha)) return PAT_EINVAL;
   if (lossy && !(d->alpha_power > 0 && d->alpha_power < 3 && d->alpha_power != 1.0)) return PAT_EINVAL;
   if (d->n_sensors < 1) return PAT_EINVAL;
-  if (d->flags & ~(PAT_NO_PML | PAT_CHECK_FINITE | PAT_SMOOTH_MEDIUM)) return PAT_EINVAL;
+  if (d->flags & ~(PAT_NO_PML | PAT_CHECK_FINITE | PAT_SMOOTH_MEDIUM | PAT_SMOOTH_P0)) return PAT_EINVAL;
   return PAT_OK;
 }
 
@@ -304,7 +304,7 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
   // ---- device arena layout
   const int M = nx / 2;
   Carve cv;
-  size_t oB[3] = {0, 0, 0}, oQ[3], oQs[3], oK[3], oA[3], oBb[3], oU[3] = {0, 0, 0}, oR[3] = {0, 0, 0};
+  size_t oB[3] = {0, 0, 0}, oQ[3], oQs[3], oK[3], oA[3], oBb[3], oW[3], oU[3] = {0, 0, 0}, oR[3] = {0, 0, 0};
   for (int j = 0; j < nd; ++j) oB[j] = cv.take<float>(N);
   const size_t o_dtr0 = cv.take<float>(N), o_c2 = cv.take<float>(N), o_inv = cv.take<float>(N);
   const size_t o_c2tau = lossy ? cv.take<float>(N) : 0, o_c2eta = lossy ? cv.take<float>(N) : 0;
@@ -316,6 +316,7 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
     oK[j] = cv.take<float>(tlen[j]);
     oA[j] = cv.take<float2>(tlen[j]);
     oBb[j] = cv.take<float2>(tlen[j]);
+    oW[j] = cv.take<float>(tlen[j]);
   }
   const size_t state_begin = (cv.off + 255) & ~size_t(255);
   // forward state between two steps: u_j, rho_j and the x-spectrum of p (S0),
@@ -381,6 +382,8 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
       const double k = 2.0 * M_PI * mt / (n * d.dx[j]);
       const double h = k * d.dx[j] / 2.0;
       hf(oK[j])[m] = (float)(k * k);
+      // Blackman window centred on k = 0 (1 there, 0 at the Nyquist bin)
+      hf(oW[j])[m] = (float)(0.42 + 0.5 * std::cos(2.0 * M_PI * m / n) + 0.08 * std::cos(4.0 * M_PI * m / n));
       if (2 * m == n) {  // Nyquist: i k e^{+-i pi/2} is exactly real
         hc(oA[j])[m] = make_float2((float)k, 0.f);
         hc(oBb[j])[m] = make_float2((float)(-k), 0.f);
@@ -443,6 +446,7 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
     h.ksq[j] = (const float*)(A + oK[j]);
     h.shA[j] = (const float2*)(A + oA[j]);
     h.shB[j] = (const float2*)(A + oBb[j]);
+    h.win[j] = (const float*)(A + oW[j]);
     h.u[j] = (float*)(A + oU[j]);
     h.r[j] = (float*)(A + oR[j]);
   }

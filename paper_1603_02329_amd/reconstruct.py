@@ -5,7 +5,7 @@ time after every iteration.
 
     python -m paper_1603_02329_amd.reconstruct [--n 512] [--iters 20]
         [--methods ista,mg-ista,fista,mg-fista] [--lam 1e-2] [--levels 2]
-        [--eps-c 1e-2] [--json out.json]
+        [--eps-c 1e-2] [--smooth-p0] [--json out.json]
 
 The problem: the seeded two-level medium and vessel phantom of the
 synthetic workloads (512^2 / 256^2 by default, N_t 2400 / 1200), data = the
@@ -17,7 +17,8 @@ method on each level: 2/L_f for ISTA (as in section VI-A), 1/L_f for FISTA;
 the two-level parameters are the paper's 2D values (kappa 1/4, vartheta
 0.1, q_d 3, q_c 8, eps_c 1e-2, rho 1e-2).  The data are generated on the
 reconstruction grid itself, so this shows convergence against time, not
-the paper's inverse-crime-free errors.
+the paper's inverse-crime-free errors.  With --smooth-p0 every level's
+operators filter the initial pressure (H = H0 S, H^T = S H0^T).
 """
 from __future__ import annotations
 
@@ -38,6 +39,8 @@ def main(argv=None):
     ap.add_argument("--power-iters", type=int, default=20)
     ap.add_argument("--levels", type=int, default=2, help="grid levels of the MG variants (2: the paper's)")
     ap.add_argument("--eps-c", type=float, default=1e-2, help="coarse-solve termination (relative decrease)")
+    ap.add_argument("--smooth-p0", action="store_true",
+                    help="filter the initial pressure inside H and H^T on every level (section VI-A)")
     ap.add_argument("--json", default=None)
     args = ap.parse_args(argv)
 
@@ -53,6 +56,10 @@ def main(argv=None):
     nt = max(64, 2400 * n // 512)
     # the first two levels are those of the two-level workload (same draws)
     insts = synth.multi_level(3, 0, n, 1e-4, pml, nt, 256, max(2, args.levels))
+    if args.smooth_p0:
+        from dataclasses import replace
+        insts = [synth.Instance(replace(i.desc, smooth_p0=True), i.c0, i.rho0, i.alpha0_db, i.sensors, i.p0, i.name)
+                 for i in insts]
     plans = [Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=dev) for i in insts]
     pf = plans[0]
     fine_i = insts[0]

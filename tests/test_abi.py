@@ -72,6 +72,12 @@ def test_plan_create_rejects_bad_descriptors_on_host():
     dummy = ctypes.c_void_p(16)
     assert L.pat_plan_create(ctypes.byref(h), ctypes.byref(cd), dummy, dummy, dummy, (ctypes.c_double * 6)(),
                              None) == pat.PAT_EINVAL
+    # unknown plan flag (0x10 is the lowest undefined bit)
+    cd = pat.make_desc(base, 3)
+    cd.flags = pat.PAT_SMOOTH_P0 << 1
+    assert L.pat_plan_create(ctypes.byref(h), ctypes.byref(cd), dummy, dummy, None, (ctypes.c_double * 6)(),
+                             None) == pat.PAT_EINVAL
+    assert pat.make_desc(replace(base, smooth_p0=True), 3).flags == pat.PAT_SMOOTH_P0
     # NULL arguments
     cd = pat.make_desc(base, 3)
     assert L.pat_plan_create(ctypes.byref(h), ctypes.byref(cd), None, dummy, None, (ctypes.c_double * 6)(),

@@ -101,7 +101,7 @@ def test_batched_autograd_matches_the_oracle():
         g_ref = K.adjoint(op, r)
         g = xs[k].grad.cpu().numpy().astype(np.float64)
         assert np.linalg.norm(g - g_ref) <= 1e-5 * np.linalg.norm(g_ref), k
-    assert abs(float(loss) - ref_loss) <= 1e-6 * ref_loss
+    assert abs(float(loss.detach()) - ref_loss) <= 1e-6 * ref_loss
     datas = batch.forward([x.detach() for x in xs])
     res = [pat.residual_f64(d, t)[0] for d, t in zip(datas, targets)]
     imgs = batch.adjoint(res)

@@ -1,5 +1,7 @@
 """GPU: the batched executor (work tables + graph-captured chunks) and the
 segmented forward reproduce the eager single-instance path bitwise."""
+from dataclasses import replace
+
 import numpy as np
 import pytest
 
@@ -123,6 +125,47 @@ def test_fused_mixed_physics_bitwise():
             assert torch.equal(d[k], ref_d[k]), (r, k)
             assert torch.equal(im[k], ref_i[k]), (r, k)
     b.close()
+
+
+@pytest.mark.parametrize("fuse", [True, False])
+def test_smoothed_p0_batch_bitwise(fuse):
+    """Plans that filter p0 beside plans that do not: the batch groups them
+    apart (their first and last passes differ), fuses the filtered 2D
+    classes among themselves, and equals the eager path bitwise; nt = 1
+    runs the filter after the sensor transpose.  A 3D batch likewise."""
+    specs2 = [dict(n=(128, 128), nt=7, ns=5, pml=6, lossy=True, sm=True),
+              dict(n=(256, 256), nt=11, ns=6, pml=8, lossy=True, sm=True),
+              dict(n=(128, 128), nt=9, ns=4, pml=6, lossy=True, sm=False),
+              dict(n=(256, 128), nt=5, ns=5, pml=6, lossy=False, sm=True),
+              dict(n=(64, 64), nt=8, ns=4, pml=4, lossy=True, sm=True),
+              dict(n=(64, 64), nt=1, ns=4, pml=4, lossy=True, sm=True)]
+    specs3 = [dict(n=(16, 32, 16), nt=6, ns=5, pml=3, lossy=True, sm=True),
+              dict(n=(16, 32, 16), nt=6, ns=4, pml=3, lossy=True, sm=False),
+              dict(n=(32, 16, 16), nt=5, ns=4, pml=2, lossy=False, sm=True)]
+    for specs, seed in ((specs2, 900), (specs3, 920)):
+        insts, plans = [], []
+        for i, sp in enumerate(specs):
+            sp = dict(sp)
+            sm = sp.pop("sm")
+            inst = synth.small_instance(seed + i, **sp)
+            desc = replace(inst.desc, smooth_p0=sm)
+            insts.append(inst)
+            plans.append(pat.Plan(desc, inst.c0, inst.rho0, inst.alpha0_db, inst.sensors, device=DEV))
+        p0 = [torch.from_numpy(i.p0).to(DEV) for i in insts]
+        ref_d = [p.forward(x).clone() for p, x in zip(plans, p0)]
+        rng = np.random.default_rng(seed)
+        hs = [torch.from_numpy(rng.standard_normal((i.desc.nt, i.ns)).astype(np.float32)).to(DEV) for i in insts]
+        ref_i = [p.adjoint(h).clone() for p, h in zip(plans, hs)]
+        b = pat.Batch(plans, chunk=4, fuse=fuse)
+        print("batch", len(specs[0]["n"]), "D fuse", fuse, flush=True)
+        for r in range(2):
+            d = b.forward(p0)
+            im = b.adjoint(hs)
+            torch.cuda.synchronize()
+            for k in range(len(insts)):
+                assert torch.equal(d[k], ref_d[k]), (r, k)
+                assert torch.equal(im[k], ref_i[k]), (r, k)
+        b.close()
 
 
 def test_forward_range_resume_is_bitwise():
