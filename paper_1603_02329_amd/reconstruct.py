@@ -39,6 +39,8 @@ def main(argv=None):
     ap.add_argument("--power-iters", type=int, default=20)
     ap.add_argument("--levels", type=int, default=2, help="grid levels of the MG variants (2: the paper's)")
     ap.add_argument("--eps-c", type=float, default=1e-2, help="coarse-solve termination (relative decrease)")
+    ap.add_argument("--no-batch-levels", action="store_true",
+                    help="run the fine and coarse gradients one after the other instead of in one batch")
     ap.add_argument("--smooth-p0", action="store_true",
                     help="filter the initial pressure inside H and H^T on every level (section VI-A)")
     ap.add_argument("--json", default=None)
@@ -109,7 +111,8 @@ def main(argv=None):
 
         if method.startswith("mg-"):
             S.mg_fista(fine, levels[1:args.levels], x0, args.iters,
-                       S.MGParams(momentum=momentum, eps_c=args.eps_c), callback=log)
+                       S.MGParams(momentum=momentum, eps_c=args.eps_c,
+                                  batch_levels=False if args.no_batch_levels else None), callback=log)
         else:
             S.fista(fine, x0, args.iters, momentum=momentum, callback=log)
         results[method] = rows

@@ -158,6 +158,11 @@ class MGParams:
     eps_d: Optional[float] = None
     momentum: bool = True
     prox_iter: int = 20
+    # gradients of two adjacent levels in one batch at every iteration that
+    # may recurse (the coarse one ahead of the decision); None: where the two
+    # grids fuse into common launches (2D), so that the coarse gradient costs
+    # next to nothing beside the fine one
+    batch_levels: Optional[bool] = None
 
 
 @dataclass
@@ -167,6 +172,43 @@ class MGRecord:
     coarse_updates: int = 0
     grad_ratio: float = 0.0   # ||R grad F_rho(y)|| / ||grad F_rho(y)|| at the decision
     depth: int = 0            # deepest level a recursive step reached (0: direct step)
+
+
+class _LevelPair:
+    """Levels i and i + 1 whose data-term gradients run together: one batch
+    over both plans, so that every pass of the scheme is one launch over both
+    grids (2D grids of 128 to 512 points share the launches, the coarse level
+    stepping at its own rate; otherwise the two run side by side on two
+    streams).  Results equal the levels' own calls bitwise."""
+
+    def __init__(self, fine: Level, coarse: Level):
+        self.fine, self.coarse = fine, coarse
+        self.batch = Batch([fine.plan, coarse.plan])
+
+    def grads(self, y):
+        """(grad f_i(y), R y, grad f_{i+1}(R y))."""
+        yc = restrict(y)
+        d = self.batch.forward([y, yc])
+        rf, _ = residual_f64(d[0], self.fine.data)
+        rc, _ = residual_f64(d[1], self.coarse.data)
+        gf, gc = self.batch.adjoint([rf, rc])
+        return gf, yc, gc
+
+    def close(self):
+        self.batch.close()
+
+
+def _pair(pairs, levels, i: int, p: MGParams):
+    """The batched pair (i, i + 1), made on first use, or None when the
+    levels' gradients run one after the other."""
+    if pairs is None or i + 1 >= len(levels):
+        return None
+    if i not in pairs:
+        use = getattr(p, "batch_levels", None)
+        if use is None:
+            use = levels[i].plan.ndim == 2
+        pairs[i] = _LevelPair(levels[i], levels[i + 1]) if use else None
+    return pairs[i]
 
 
 def _decide(p: MGParams, g, y, y_tilde, k_d: int, k_r: int):
@@ -181,13 +223,14 @@ def _decide(p: MGParams, g, y, y_tilde, k_d: int, k_r: int):
     return (ratio > p.kappa) and (far or k_r == 0 or k_d > p.q_d), ratio, rg
 
 
-def coarse_mg(levels, i: int, x0, v, lower, p: MGParams):
+def coarse_mg(levels, i: int, x0, v, lower, p: MGParams, pairs=None):
     """The coarse solve at level i of ``levels`` (0 the target level): FISTA
     on phi_i = F_rho,i + <v, .> over x >= lower, whose iterations after the
     first may take a recursive step to level i + 1 when there is one (same
     decision rule, coherence term and restricted bound as at the target
     level); with no coarser level it is ``coarse_fista``.  Returns (x,
-    number of updates, deepest level reached)."""
+    number of updates, deepest level reached).  ``pairs``: the batched
+    level pairs of ``mg_fista`` (None: every gradient on its own level)."""
     lv = levels[i]
     has_next = i + 1 < len(levels)
 
@@ -202,16 +245,25 @@ def coarse_mg(levels, i: int, x0, v, lower, p: MGParams):
     y_tilde = None
     depth = i
     while k < p.q_c:
-        _, g = lv.smoothed(y, p.rho)
+        pair = _pair(pairs, levels, i, p) if (has_next and k > 0) else None
+        if pair is not None:
+            g, xc0, gc = pair.grads(y)
+            tv_smooth(y, p.rho, grad=g, scale=lv.lam, value=False)
+        else:
+            _, g = lv.smoothed(y, p.rho)
         g = axpby(1.0, g, 1.0, v, out=g)
         recursive = False
         if has_next and k > 0:
             recursive, _, rg = _decide(p, g, y, y_tilde, k_d, k_r)
         if recursive:
             k_d, k_r = 0, k_r + 1
-            xc0 = restrict(y)
-            _, gc = levels[i + 1].smoothed(xc0, p.rho)
-            xc, _, d = coarse_mg(levels, i + 1, xc0, axpby(1.0, rg, -1.0, gc), restrict_lower(y, lower), p)
+            if pair is not None:
+                tv_smooth(xc0, p.rho, grad=gc, scale=levels[i + 1].lam, value=False)
+            else:
+                xc0 = restrict(y)
+                _, gc = levels[i + 1].smoothed(xc0, p.rho)
+            xc, _, d = coarse_mg(levels, i + 1, xc0, axpby(1.0, rg, -1.0, gc), restrict_lower(y, lower), p,
+                                 pairs)
             depth = max(depth, d)
             x = axpby(1.0, y, 1.0, prolong(axpby(1.0, xc, -1.0, xc0)))
             y_tilde = y.clone()
@@ -236,6 +288,17 @@ def mg_fista(fine: Level, coarse, x0, n_iter: int, params: MGParams = MGParams()
     [MGRecord]); ``callback(k, x_k, record)`` runs after every iteration."""
     levels = [fine] + (list(coarse) if isinstance(coarse, (list, tuple)) else [coarse])
     p = params
+    pairs = {}
+    try:
+        return _mg_fista(levels, x0, n_iter, p, callback, pairs)
+    finally:
+        for pr in pairs.values():
+            if pr is not None:
+                pr.close()
+
+
+def _mg_fista(levels, x0, n_iter: int, p: MGParams, callback, pairs):
+    fine = levels[0]
     x_prev = x0.clone()
     y = x0.clone()
     t = 1.0
@@ -246,19 +309,27 @@ def mg_fista(fine: Level, coarse, x0, n_iter: int, params: MGParams = MGParams()
         recursive = False
         ratio = 0.0
         rg = gf = None
+        pair = _pair(pairs, levels, 0, p) if k > 1 else None
         if k > 1:
-            # grad f(y) serves the decision (through grad F_rho) and a direct step
-            _, gf = fine.grad_f(y)
+            # grad f(y) serves the decision (through grad F_rho) and a direct
+            # step; with a batched pair the coarse gradient at R y comes along
+            if pair is not None:
+                gf, xc0, gc = pair.grads(y)
+            else:
+                _, gf = fine.grad_f(y)
             gF = gf.clone()
             tv_smooth(y, p.rho, grad=gF, scale=fine.lam, value=False)
             recursive, ratio, rg = _decide(p, gF, y, y_tilde, k_d, k_r)
         if recursive:
             k_d, k_r = 0, k_r + 1
-            xc0 = restrict(y)
-            _, gc = levels[1].smoothed(xc0, p.rho)
+            if pair is not None:
+                tv_smooth(xc0, p.rho, grad=gc, scale=levels[1].lam, value=False)
+            else:
+                xc0 = restrict(y)
+                _, gc = levels[1].smoothed(xc0, p.rho)
             v = axpby(1.0, rg, -1.0, gc)
             lower = restrict_lower(y)
-            xc, nup, depth = coarse_mg(levels, 1, xc0, v, lower, p)
+            xc, nup, depth = coarse_mg(levels, 1, xc0, v, lower, p, pairs)
             x = axpby(1.0, y, 1.0, prolong(axpby(1.0, xc, -1.0, xc0)))
             y_tilde = y.clone()
             rec = MGRecord("recursive", 0.0, nup, ratio, depth)

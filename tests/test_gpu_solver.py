@@ -153,3 +153,45 @@ def test_mg_fista_3d_matches_oracle():
     olv, glv = _chain(synth.multi_level_3d(92, 0, 32, 2e-4, 4, 24, 2), 1e-2, n_power=20)
     ho = _compare_mg(olv, glv, 4, solver.MGParams(kappa=0.125, rho=3e-2))
     assert "recursive" in [r.kind for r in ho]
+
+
+def _gpu_chain(insts, lam, n_power=8):
+    """GPU levels of a multi-level problem (data: the GPU forward of the
+    phantom, every 2^l-th sample at level l; steps from the GPU power
+    iteration)."""
+    plans = [pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=DEV) for i in insts]
+    data = plans[0].forward(_t(insts[0].p0))
+    v = torch.ones_like(_t(insts[0].p0))
+    lv = []
+    for l, (i, plan) in enumerate(zip(insts, plans)):
+        L = gsolver.power_iteration(plan, v, n_power)
+        lv.append(gsolver.Level(plan, data[::2 ** l][:i.desc.nt].contiguous(), lam, 1.0 / L))
+        v = pat.restrict(v)
+    return lv
+
+
+@pytest.mark.parametrize("what", ["2d-fused", "2d-three", "3d"])
+def test_mg_level_pairs_bitwise(what):
+    """Adjacent levels' gradients in one batch (the coarse one computed
+    ahead of the decision) give the same iterates bitwise as the levels'
+    own calls one after the other: 256^2 -> 128^2 (the two grids share
+    every launch), 256^2 -> 128^2 -> 64^2, and 3D 32^3 -> 16^3 (two streams)."""
+    if what == "2d-fused":
+        lv, prm, n_it = _gpu_chain(synth.multi_level(93, 0, 256, 1e-4, 10, 240, 32, 2), 1e-3), {"kappa": 0.1}, 6
+    elif what == "2d-three":
+        lv, prm, n_it = _gpu_chain(synth.multi_level(94, 0, 256, 1e-4, 10, 240, 32, 3), 1e-3), \
+            {"kappa": 0.1, "eps_c": 1e-3}, 5
+    else:
+        lv, prm, n_it = _gpu_chain(synth.multi_level_3d(95, 0, 32, 2e-4, 4, 24, 2), 1e-2), \
+            {"kappa": 0.125, "rho": 3e-2}, 4
+    x0 = torch.zeros(lv[0].plan.shape, device=DEV)
+    out = []
+    for batched in (False, True):
+        x, h = gsolver.mg_fista(lv[0], lv[1:], x0, n_it, gsolver.MGParams(batch_levels=batched, **prm))
+        torch.cuda.synchronize()
+        out.append((x, [(r.kind, r.coarse_updates, r.depth, r.F, r.grad_ratio) for r in h]))
+        print(what, "batched" if batched else "sequential",
+              [(r.kind, r.coarse_updates, r.depth, round(r.grad_ratio, 3)) for r in h], flush=True)
+    assert "recursive" in [r[0] for r in out[0][1]]
+    assert out[0][1] == out[1][1]
+    assert torch.equal(out[0][0], out[1][0])
