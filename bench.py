@@ -163,8 +163,9 @@ def main():
                          "phase's launches; run under rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the solver runs each instance on a single device "
-              "(see DESIGN.md for how the path would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the solver runs each instance on a single device, and "
+              "independent instances would be split across GPUs without communication; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

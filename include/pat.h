@@ -38,7 +38,7 @@ extern "C" {
 #define PAT_ENOMEM      3  /* device or host allocation failed                    */
 #define PAT_EHIP        4  /* a HIP runtime call failed                           */
 #define PAT_ENONFINITE  5  /* a non-finite pressure was seen (PAT_CHECK_FINITE)   */
-#define PAT_ENOSYS      6  /* combination not supported by this build             */
+#define PAT_ENOSYS      6  /* combination not supported by this library           */
 
 /* ------------------------------------------------------------------ flags */
 #define PAT_NO_PML        0x1u  /* switch the PML off: periodic grid             */

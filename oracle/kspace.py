@@ -166,8 +166,8 @@ def blackman_k(n: int) -> np.ndarray:
 
 def smooth_medium(f: np.ndarray) -> np.ndarray:
     """Spectral smoothing of a medium map (section VI-A: the paper's models
-    ran on maps smoothed against aliasing; the window is this build's
-    reading): the spectrum times the product over the axes of
+    ran on maps smoothed against aliasing; the paper does not name the
+    window, this one is a chosen reading): the spectrum times the product over the axes of
     ``blackman_k``, back-transformed (real part)."""
     f = np.asarray(f, dtype=np.float64)
     W = np.ones(f.shape)

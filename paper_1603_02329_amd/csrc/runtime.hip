@@ -516,7 +516,7 @@ extern "C" const char* pat_strerror(int code) {
     case PAT_ENOMEM: return "out of memory";
     case PAT_EHIP: return "HIP runtime error";
     case PAT_ENONFINITE: return "non-finite pressure produced";
-    case PAT_ENOSYS: return "not supported by this build";
+    case PAT_ENOSYS: return "not supported by this library";
   }
   return "unknown error";
 }
