@@ -195,3 +195,28 @@ def test_mg_level_pairs_bitwise(what):
     assert "recursive" in [r[0] for r in out[0][1]]
     assert out[0][1] == out[1][1]
     assert torch.equal(out[0][0], out[1][0])
+
+
+@pytest.mark.parametrize("momentum", [True, False])
+def test_fista_batched_equals_per_problem(momentum):
+    """Several reconstructions in lockstep (one batch for H and H^T of all,
+    one batched prox): per problem bitwise the iterates and objectives of
+    the one-problem loop.  Sizes: two 128^2 and one 256^2 problem (their
+    launches fused) and a 64^2 one beside them."""
+    specs = [(128, 60), (256, 90), (128, 70), (64, 40)]
+    levels = []
+    for j, (n, nt) in enumerate(specs):
+        inst = synth.multi_level(96, j, n, 1e-4, max(4, n // 16), nt, 24, 1)[0]
+        plan = pat.Plan(inst.desc, inst.c0, inst.rho0, inst.alpha0_db, inst.sensors, device=DEV)
+        data = plan.forward(_t(inst.p0))
+        L = gsolver.power_iteration(plan, torch.ones_like(_t(inst.p0)), 6)
+        levels.append(gsolver.Level(plan, data, 1e-3, 1.0 / L))
+    x0s = [torch.zeros(lv.plan.shape, device=DEV) for lv in levels]
+    xs, hists = gsolver.fista_batched(levels, x0s, 4, momentum=momentum)
+    torch.cuda.synchronize()
+    for j, lv in enumerate(levels):
+        x1, h1 = gsolver.fista(lv, x0s[j], 4, momentum=momentum)
+        torch.cuda.synchronize()
+        print(j, h1, hists[j], flush=True)
+        assert h1 == hists[j]
+        assert torch.equal(x1, xs[j])
