@@ -213,12 +213,13 @@ def main():
         launch having the GPU to itself, timed with HIP events around the
         burst.  Returns (ms total, launches, algorithmic bytes total)."""
         b1 = pat.Batch(plans, chunk=1, parts=1, lanes=1)
+        b1.time_pass(tdir, tidx, nx_dom, 100)  # untimed warm-up burst: clocks settle
         us, by = b1.time_pass(tdir, tidx, nx_dom, reps)
         b1.close()
         return us * reps / 1e3, reps, by * reps
 
-    # the roofline phase runs first, on the GPU as a fresh process finds it,
-    # so that `--roofline-only` (the profiled command) repeats it exactly
+    # the roofline phase runs first, so that `--roofline-only` (the profiled
+    # command) repeats it exactly
     k_ms, k_n, k_bytes = isolated_kernel()
     log(f"isolated pass {tdir}:{tidx}: {k_n} launches, {k_ms / k_n * 1e3:.2f} us/launch, "
         f"{k_bytes / (k_ms / 1e3) / 1e9:.0f} GB/s")
@@ -334,7 +335,7 @@ def main():
             "launches": k_n,
             "avg_launch_us": (k_ms / k_n * 1e3) if k_n else None,
             "measured_in": "back-to-back launches of the pass over a one-stream batch before the timed "
-                           "region (each launch: " + ("every instance of the batch, its size classes fused"
+                           "region, after an untimed burst of 100 (each launch: " + ("every instance of the batch, its size classes fused"
                                                       if fused_batch(plans) else "every instance of the largest "
                                                       "size") + "; GPU to itself)",
             "in_timed_region": {
