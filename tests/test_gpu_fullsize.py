@@ -69,14 +69,18 @@ def test_fullsize_single(case):
 
 
 def test_fullsize_batch48():
-    """All 48 uneven instances through one batch (graph chunks of 32 steps);
-    the six with stored references are checked."""
+    """All 48 uneven instances through one batch in the benchmark's launch
+    configuration (default grouping and fusion, graph chunks of 64 steps,
+    column variants autotuned on the batch's own buffers); the six with
+    stored references are checked."""
     ids = [0, 1, 16, 17, 32, 33]
     gold = {i: _load(f"cfg4_{i}") for i in ids}
     insts = synth.config4()
     plans = [pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=DEV) for i in insts]
-    batch = pat.Batch(plans, chunk=32)
+    batch = pat.Batch(plans)
     p0 = [torch.from_numpy(i.p0).to(DEV) for i in insts]
+    batch.forward(p0)
+    batch.autotune(reps=3)
     datas = batch.forward(p0)
     hs = []
     for k, inst in enumerate(insts):
@@ -91,7 +95,7 @@ def test_fullsize_batch48():
 
 def test_batch48_short_all_instances():
     """All 48 instances with the time axis cut to a tenth, through the
-    batched executor (default grouping, graph chunks of 32 steps, autotuned
+    batched executor (default grouping, graph chunks of 64 steps, autotuned
     column variants), each checked against the oracle.
 
     With a tenth of the time axis the wave from many phantoms has not yet
