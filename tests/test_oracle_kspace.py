@@ -464,3 +464,54 @@ def test_smoothed_p0_single_mode_and_constant():
         assert np.max(np.abs(K.forward(sm, p0) - ref)) <= 1e-12 * max(1.0, np.max(np.abs(K.forward(plain, p0))))
     c = np.full((16, 16), 0.7)
     assert np.max(np.abs(K.forward(sm, c) - K.forward(plain, c))) <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# PML: reflection and one-way attenuation of a plane pulse (section VI-A)
+# ---------------------------------------------------------------------------
+
+def _pml_pulse_energies(alpha, L=20, nx=256, ny=8, steps=(100, 450, 800)):
+    """Interior sum of p^2 at the given steps for a plane Gaussian pulse
+    (width 4 points, centred) in a homogeneous medium with a PML of L points
+    and alpha nepers per point on the x ends only.  At step 100 the two
+    halves travel in the interior; by 450 they are inside the layers (what
+    the interior holds then is reflection); by 800 each has crossed its
+    layer, wrapped around the periodic grid and crossed the opposite layer,
+    and is back in the interior."""
+    dx = 1e-4
+    x = np.arange(nx)
+    p0 = np.exp(-((x - nx / 2) / 4.0) ** 2)[None, :] * np.ones((ny, 1))
+    desc = synth.GridDesc(ndim=2, n=(nx, ny), dx=(dx, dx), origin=(0.0, 0.0), nt=2, dt=0.0, cfl=0.3,
+                          pml_size=(L, 0, 0), pml_alpha=alpha, alpha_power=1.5, pml=True)
+    c0 = np.full((ny, nx), 1500.0, np.float32)
+    op = K.make_plan(desc, c0, np.full((ny, nx), 1000.0, np.float32), None, np.array([[nx / 2 * dx, 4 * dx]]))
+    out = {}
+    for st in K.forward_states(op, p0, nsteps=max(steps)):
+        if st.n in steps:
+            out[st.n] = float((st.p[:, L:nx - L] ** 2).sum())
+    return out
+
+
+def test_pml_reflection_below_bound():
+    """Normal incidence on 20 points at 2 Np per point: the reflected energy
+    is far below 1 % of the incident one."""
+    e = _pml_pulse_energies(2.0)
+    assert e[450] / e[100] < 1e-6
+
+
+@pytest.mark.parametrize("alpha", [0.05, 0.2])
+def test_pml_one_way_attenuation_brackets_the_profile_integral(alpha):
+    """A plane wave crossing a layer with sigma = alpha (c/dx)(depth/L)^4 loses
+    the amplitude factor exp(-int sigma/c dx) = exp(-alpha L/5) in the
+    continuum; on the grid the integral becomes a sum over the points
+    crossed, which for this increasing profile lies between its midpoint sum
+    (about L/5) and its right-end sum S = sum_{d=1..L} (d/L)^4.  The pulses
+    cross two layers and their energy goes as the amplitude squared, so
+    -ln(E_800 / E_100) / (4 alpha) must lie in [L/5 - 0.1, S + 0.1].  (A
+    square profile gives L/3, a factor Q applied once per step half the
+    rate, sigma per metre instead of per point a value 10^4 off.)"""
+    L = 20
+    e = _pml_pulse_energies(alpha, L=L)
+    s_right = sum((d / L) ** 4 for d in range(1, L + 1))
+    k = -math.log(e[800] / e[100]) / (4.0 * alpha)
+    assert L / 5 - 0.1 <= k <= s_right + 0.1, (k, L / 5, s_right)
