@@ -515,3 +515,36 @@ def test_pml_one_way_attenuation_brackets_the_profile_integral(alpha):
     s_right = sum((d / L) ** 4 for d in range(1, L + 1))
     k = -math.log(e[800] / e[100]) / (4.0 * alpha)
     assert L / 5 - 0.1 <= k <= s_right + 0.1, (k, L / 5, s_right)
+
+
+@pytest.mark.parametrize("m1,m2", [((1500.0, 1000.0), (1800.0, 1200.0)), ((1500.0, 1000.0), (1500.0, 1600.0)),
+                                   ((1600.0, 1100.0), (1450.0, 950.0))])
+def test_interface_reflection_matches_impedance_contrast(m1, m2):
+    """Heterogeneous propagation: a plane pulse meeting, at normal incidence,
+    the step from medium 1 to medium 2 (sound speed and density each change;
+    one case changes the density alone, one lowers both) reflects the
+    pressure amplitude R = (Z2 - Z1) / (Z2 + Z1), Z = rho c, so the reflected
+    pulse carries R^2 of the incident sum of p^2 (both in medium 1).  The
+    pulse's other half has by then left through the PML."""
+    (c1, r1), (c2, r2) = m1, m2
+    nx, ny, L, dx = 512, 8, 20, 1e-4
+    x = np.arange(nx)
+    c = (np.where(x < 300, c1, c2)[None, :] * np.ones((ny, 1))).astype(np.float32)
+    rho = (np.where(x < 300, r1, r2)[None, :] * np.ones((ny, 1))).astype(np.float32)
+    p0 = np.exp(-((x - 200) / 4.0) ** 2)[None, :] * np.ones((ny, 1))
+    desc = synth.GridDesc(ndim=2, n=(nx, ny), dx=(dx, dx), origin=(0.0, 0.0), nt=2, dt=0.0, cfl=0.3,
+                          pml_size=(L, 0, 0), pml_alpha=2.0, alpha_power=1.5, pml=True)
+    op = K.make_plan(desc, c, rho, None, np.array([[200 * dx, 4 * dx]]))
+    v1 = c1 * op.dt / dx                       # grid points per step in medium 1
+    n_inc, n_ref = int(50 / v1), int(200 / v1)  # incident half at 250; reflection back at 200
+    e = {}
+    for st in K.forward_states(op, p0, nsteps=n_ref):
+        if st.n == n_inc:
+            e["inc"] = float((st.p[:, 201:299] ** 2).sum())
+        if st.n == n_ref:
+            e["ref"] = float((st.p[:, 101:299] ** 2).sum())
+            e["left"] = float((st.p[:, L:101] ** 2).sum())
+    z1, z2 = r1 * c1, r2 * c2
+    R = (z2 - z1) / (z2 + z1)
+    assert abs(e["ref"] / e["inc"] / (R * R) - 1.0) < 0.03, (e, R * R)
+    assert e["left"] < 1e-9 * e["inc"]
