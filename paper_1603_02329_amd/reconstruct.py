@@ -112,7 +112,7 @@ def main(argv=None):
         if method.startswith("mg-"):
             S.mg_fista(fine, levels[1:args.levels], x0, args.iters,
                        S.MGParams(momentum=momentum, eps_c=args.eps_c,
-                                  batch_levels=False if args.no_batch_levels else None), callback=log)
+                                  batch_levels=not args.no_batch_levels), callback=log)
         else:
             S.fista(fine, x0, args.iters, momentum=momentum, callback=log)
         results[method] = rows
