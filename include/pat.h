@@ -251,6 +251,23 @@ int pat_batch_forward(pat_batch* batch, const float* const* p0, float* const* da
 int pat_batch_adjoint(pat_batch* batch, const float* const* data, float* const* img, void* stream);
 
 /*
+ * pat_forward_batched / pat_adjoint_batched -- H and H^T (section III) of
+ * many plans in one call: plans, p0 / data and data / img are host arrays of
+ * nb plan and device pointers, as for pat_batch_forward / pat_batch_adjoint.
+ * The first call with a given list of plans (same pointers, same order)
+ * builds a batch with the default settings (pat_batch_create_ex(..., 0, 0,
+ * 0, 0)) and keeps it for later calls with that list; destroying any of its
+ * plans frees it.  Results equal pat_forward / pat_adjoint per instance
+ * bitwise.  A list is used by one stream at a time, and a plan by one list
+ * at a time.  PAT_EINVAL for NULL arrays or entries, nb < 1, or plans of
+ * different ndim.
+ */
+int pat_forward_batched(pat_plan* const* plans, int32_t nb, const float* const* p0, float* const* data,
+                        void* stream);
+int pat_adjoint_batched(pat_plan* const* plans, int32_t nb, const float* const* data, float* const* img,
+                        void* stream);
+
+/*
  * Tile-shape autotuner of the batched executor: how many columns of the
  * column FFTs inside the k-space derivative and fractional-Laplacian
  * operators (section Forward Problem, lossless and lossy media) one

@@ -16,7 +16,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 __all__ = ["lib", "PatError", "Plan", "Batch", "tv_prox", "restrict", "prolong", "dot_f64", "residual_f64",
-           "tv_smooth", "restrict_lower", "axpby", "project", "tv_prox_batched",
+           "tv_smooth", "restrict_lower", "axpby", "project", "tv_prox_batched", "forward_batched",
+           "adjoint_batched",
            "LIB_PATH", "EXPORTED"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpat.so")
@@ -37,7 +38,8 @@ EXPORTED = [
     "pat_prolong",
     "pat_dot_f64", "pat_residual_f64", "pat_plan_sync", "pat_strerror", "pat_timing_begin",
     "pat_timing_end", "pat_batch_autotune", "pat_tuning_report", "pat_batch_set_tile", "pat_batch_time_pass",
-    "pat_tv_smooth", "pat_restrict_lower", "pat_axpby", "pat_project",
+    "pat_tv_smooth", "pat_restrict_lower", "pat_axpby", "pat_project", "pat_forward_batched",
+    "pat_adjoint_batched",
 ]
 
 
@@ -91,6 +93,8 @@ def lib() -> ctypes.CDLL:
         "pat_batch_destroy": (None, [vp]),
         "pat_batch_forward": (ctypes.c_int, [vp, pp, pp, vp]),
         "pat_batch_adjoint": (ctypes.c_int, [vp, pp, pp, vp]),
+        "pat_forward_batched": (ctypes.c_int, [pp, i32, pp, pp, vp]),
+        "pat_adjoint_batched": (ctypes.c_int, [pp, i32, pp, pp, vp]),
         "pat_tv_prox_work_bytes": (sz, [i32, ctypes.POINTER(i32)]),
         "pat_tv_prox": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, f64, i32, vp, vp, sz, vp]),
         "pat_tv_prox_batched": (ctypes.c_int, [i32, i32, ctypes.POINTER(i32), pp, pp, ctypes.POINTER(f64), i32, pp,
@@ -439,6 +443,34 @@ def tv_prox(z, lam: float, n_iter: int = 20, lower=None, out=None, work=None):
                              ctypes.c_void_p(work.data_ptr()), ctypes.c_size_t(work.numel()), _stream()),
            "pat_tv_prox")
     return out
+
+
+def forward_batched(plans, p0s, datas=None):
+    """H of several plans in one call (pat_forward_batched: the library keeps
+    one batch per distinct plan list); returns the list of data tensors."""
+    torch = _torch()
+    if datas is None:
+        datas = [torch.empty((p.nt, p.ns), device=x.device, dtype=torch.float32) for p, x in zip(plans, p0s)]
+    k = len(plans)
+    hs = (ctypes.c_void_p * k)(*[p.handle.value for p in plans])
+    a = (ctypes.c_void_p * k)(*[_dev_f32(x, "p0", p.npoints).value for p, x in zip(plans, p0s)])
+    b = (ctypes.c_void_p * k)(*[_dev_f32(d, "data", p.nt * p.ns).value for p, d in zip(plans, datas)])
+    _check(lib().pat_forward_batched(hs, k, a, b, _stream()), "pat_forward_batched")
+    return datas
+
+
+def adjoint_batched(plans, datas, imgs=None):
+    """H^T of several plans in one call (pat_adjoint_batched); returns the
+    list of images."""
+    torch = _torch()
+    if imgs is None:
+        imgs = [torch.empty(p.shape, device=d.device, dtype=torch.float32) for p, d in zip(plans, datas)]
+    k = len(plans)
+    hs = (ctypes.c_void_p * k)(*[p.handle.value for p in plans])
+    a = (ctypes.c_void_p * k)(*[_dev_f32(d, "data", p.nt * p.ns).value for p, d in zip(plans, datas)])
+    b = (ctypes.c_void_p * k)(*[_dev_f32(x, "img", p.npoints).value for p, x in zip(plans, imgs)])
+    _check(lib().pat_adjoint_batched(hs, k, a, b, _stream()), "pat_adjoint_batched")
+    return imgs
 
 
 def tv_prox_batched(zs, lams, n_iter: int = 20, lowers=None, outs=None, works=None):

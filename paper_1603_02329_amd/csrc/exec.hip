@@ -939,6 +939,68 @@ extern "C" int pat_batch_adjoint(pat_batch* b, const float* const* data, float* 
   return batch_run(b, 1, data, img, (hipStream_t)stream);
 }
 
+// ===================================================================== one-call batched entry points
+// One batch (default settings) per distinct list of plans, made on the first
+// call and kept until one of its plans is destroyed.  The map lives on the
+// heap and is never torn down: at process exit the HIP runtime may already
+// be gone, so nothing is freed from a static destructor.
+namespace {
+std::mutex g_bmu;
+std::map<std::vector<pat_plan*>, pat_batch*>& batch_cache() {
+  static auto* m = new std::map<std::vector<pat_plan*>, pat_batch*>();
+  return *m;
+}
+
+int cached_batch(pat_plan* const* plans, int nb, pat_batch** out) {
+  if (!plans || nb < 1 || !out) return PAT_EINVAL;
+  std::vector<pat_plan*> key(plans, plans + nb);
+  for (pat_plan* p : key)
+    if (!p) return PAT_EINVAL;
+  std::lock_guard<std::mutex> lk(g_bmu);
+  auto& m = batch_cache();
+  auto it = m.find(key);
+  if (it == m.end()) {
+    pat_batch* b = nullptr;
+    const int rc = pat_batch_create_ex(&b, plans, nb, 0, 0, 0, 0);
+    if (rc) return rc;
+    it = m.emplace(std::move(key), b).first;
+  }
+  *out = it->second;
+  return PAT_OK;
+}
+}  // namespace
+
+namespace pat {
+void batch_cache_forget(const pat_plan* p) {
+  std::lock_guard<std::mutex> lk(g_bmu);
+  auto& m = batch_cache();
+  for (auto it = m.begin(); it != m.end();) {
+    if (std::find(it->first.begin(), it->first.end(), p) != it->first.end()) {
+      destroy_batch(it->second);
+      it = m.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+}  // namespace pat
+
+extern "C" int pat_forward_batched(pat_plan* const* plans, int32_t nb, const float* const* p0, float* const* data,
+                                   void* stream) {
+  if (!p0 || !data) return PAT_EINVAL;
+  pat_batch* b = nullptr;
+  const int rc = cached_batch(plans, nb, &b);
+  return rc ? rc : batch_run(b, 0, p0, data, (hipStream_t)stream);
+}
+
+extern "C" int pat_adjoint_batched(pat_plan* const* plans, int32_t nb, const float* const* data, float* const* img,
+                                   void* stream) {
+  if (!data || !img) return PAT_EINVAL;
+  pat_batch* b = nullptr;
+  const int rc = cached_batch(plans, nb, &b);
+  return rc ? rc : batch_run(b, 1, data, img, (hipStream_t)stream);
+}
+
 // ===================================================================== column tile autotuner
 // For every column pass of every class that has more than one instantiated
 // tile width, each candidate is launched `reps` times over the class's own

@@ -238,6 +238,10 @@ int step_ops(int direction /*0 fwd, 1 adj*/, int ndim, int lossy, PassOp* ops);
 // 2D): reads + writes of full-grid arrays the pass must touch
 double pass_bytes_per_point(const PassOp& op, int ndim, int lossy);
 
+// drop the batches pat_forward_batched / pat_adjoint_batched keep for plan
+// lists that hold p (called when p is destroyed)
+void batch_cache_forget(const pat_plan* p);
+
 
 }  // namespace pat
 

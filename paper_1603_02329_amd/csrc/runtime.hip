@@ -480,6 +480,7 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
 extern "C" void pat_plan_destroy(pat_plan* p) {
   if (!p) return;
   hipDeviceSynchronize();
+  batch_cache_forget(p);
   hipFree(p->arena);
   delete p;
 }

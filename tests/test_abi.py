@@ -117,6 +117,12 @@ def test_batch_entry_points_validate_on_host():
     assert L.pat_batch_create(ctypes.byref(h), one, 1, 0) == pat.PAT_EINVAL  # null plan pointer
     assert h.value is None
     assert L.pat_batch_autotune(None, 1, None) == pat.PAT_EINVAL
+    ptrs = (ctypes.c_void_p * 1)(None)
+    for fn in (L.pat_forward_batched, L.pat_adjoint_batched):
+        assert fn(None, 1, ptrs, ptrs, None) == pat.PAT_EINVAL     # no plan array
+        assert fn(one, 0, ptrs, ptrs, None) == pat.PAT_EINVAL      # nb < 1
+        assert fn(one, 1, ptrs, ptrs, None) == pat.PAT_EINVAL      # null plan entry
+        assert fn(one, 1, None, ptrs, None) == pat.PAT_EINVAL      # no input array
     need = ctypes.c_size_t()
     assert L.pat_tuning_report(None, None, 0, ctypes.byref(need)) == pat.PAT_EINVAL
     n = (ctypes.c_int32 * 3)(16, 16, 1)

@@ -168,6 +168,33 @@ def test_smoothed_p0_batch_bitwise(fuse):
         b.close()
 
 
+def test_one_call_batched_entry_points():
+    """pat_forward_batched / pat_adjoint_batched: per instance bitwise the
+    eager results, on the first call (batch built) and the second (kept);
+    after one of its plans is destroyed, a new list with a new plan works."""
+    specs = [dict(n=(128, 128), nt=7, ns=5, pml=6, lossy=True), dict(n=(256, 256), nt=9, ns=4, pml=8, lossy=True),
+             dict(n=(64, 32), nt=6, ns=3, pml=4, lossy=False)]
+    insts = [synth.small_instance(940 + i, **sp) for i, sp in enumerate(specs)]
+    plans = [pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=DEV) for i in insts]
+    p0 = [torch.from_numpy(i.p0).to(DEV) for i in insts]
+    rng = np.random.default_rng(7)
+    hs = [torch.from_numpy(rng.standard_normal((i.desc.nt, i.ns)).astype(np.float32)).to(DEV) for i in insts]
+    ref_d = [p.forward(x).clone() for p, x in zip(plans, p0)]
+    ref_i = [p.adjoint(h).clone() for p, h in zip(plans, hs)]
+    for r in range(2):
+        d = pat.forward_batched(plans, p0)
+        im = pat.adjoint_batched(plans, hs)
+        torch.cuda.synchronize()
+        for k in range(len(plans)):
+            assert torch.equal(d[k], ref_d[k]), (r, k)
+            assert torch.equal(im[k], ref_i[k]), (r, k)
+    plans[2].close()  # frees the kept batch of this list
+    fresh = pat.Plan(insts[2].desc, insts[2].c0, insts[2].rho0, insts[2].alpha0_db, insts[2].sensors, device=DEV)
+    d = pat.forward_batched([plans[0], fresh], [p0[0], p0[2]])
+    torch.cuda.synchronize()
+    assert torch.equal(d[0], ref_d[0]) and torch.equal(d[1], ref_d[2])
+
+
 def test_forward_range_resume_is_bitwise():
     inst = synth.small_instance(600, (64, 64), nt=37, ns=7, pml=5, lossy=True)
     plan = pat.Plan(inst.desc, inst.c0, inst.rho0, inst.alpha0_db, inst.sensors, device=DEV)
