@@ -1,7 +1,7 @@
 """Reconstruction of a synthetic multi-level 2D problem on the GPU: ISTA,
 FISTA and their multi-grid variants (Alg. ISTA, Alg. FISTA, Alg. FISTAMG),
-with the objective F, the relative error RE (section VI) and the elapsed
-time after every iteration.
+with the objective F, the relative error RE and the residual norm RES
+(section VI) and the elapsed time after every iteration.
 
     python -m paper_1603_02329_amd.reconstruct [--n 512] [--iters 20]
         [--methods ista,mg-ista,fista,mg-fista] [--lam 1e-2] [--levels 2]
@@ -101,13 +101,13 @@ def main(argv=None):
             torch.cuda.synchronize()
             F = rec if isinstance(rec, float) else rec.F
             kind = "direct" if isinstance(rec, float) else rec.kind
-            row = {"k": k, "kind": kind, "F": F, "RE": re(x), "seconds": time.perf_counter() - start}
+            row = {"k": k, "kind": kind, "F": F, "RE": re(x), "RES": fine.res, "seconds": time.perf_counter() - start}
             if not isinstance(rec, float) and rec.depth > 1:
                 kind = f"{kind}{rec.depth}"
                 row["depth"] = rec.depth
             rows.append(row)
-            print(f"{method:9s} k={k:3d} {kind:9s} F={F:.6e} RE={row['RE']:7.3f}% t={row['seconds']:7.2f}s",
-                  flush=True)
+            print(f"{method:9s} k={k:3d} {kind:9s} F={F:.6e} RE={row['RE']:7.3f}% RES={row['RES']:.4e} "
+                  f"t={row['seconds']:7.2f}s", flush=True)
 
         if method.startswith("mg-"):
             S.mg_fista(fine, levels[1:args.levels], x0, args.iters,

@@ -46,6 +46,7 @@ class Level:
 
     def __init__(self, plan: Plan, data, lam: float, alpha: float, graphs: bool = False):
         self.plan, self.data, self.lam, self.alpha = plan, data, lam, alpha
+        self.res = float("nan")
         self._batch = Batch([plan]) if graphs else None
 
     def forward(self, x):
@@ -64,8 +65,11 @@ class Level:
         return residual_f64(self.forward(x), self.data)[1]
 
     def objective(self, x) -> float:
-        """F(x) = f(x) + lam TV(x)."""
-        return self.value_f(x) + self.lam * tv_smooth(x, 0.0)
+        """F(x) = f(x) + lam TV(x); keeps the residual norm RES(x) =
+        ||H x - p_hat|| (section VI) in ``self.res``."""
+        half = self.value_f(x)
+        self.res = math.sqrt(2.0 * half)
+        return half + self.lam * tv_smooth(x, 0.0)
 
     def smoothed(self, x, rho: float):
         """(F_rho(x), grad F_rho(x)) = (f + lam J_rho, grad f + lam grad J_rho)."""
@@ -142,7 +146,10 @@ def fista_batched(levels, x0s, n_iter: int, momentum: bool = True, prox_iter: in
             zs = [axpby(1.0, y, -lv.alpha, g) for y, lv, g in zip(ys, levels, gs)]
             xs = tv_prox_batched(zs, [lv.alpha * lv.lam for lv in levels], prox_iter)
             dx = batch.forward(xs)
-            Fs = [residual_f64(di, lv.data)[1] + lv.lam * tv_smooth(x, 0.0) for di, lv, x in zip(dx, levels, xs)]
+            halves = [residual_f64(di, lv.data)[1] for di, lv in zip(dx, levels)]
+            Fs = [h + lv.lam * tv_smooth(x, 0.0) for h, lv, x in zip(halves, levels, xs)]
+            for lv, h in zip(levels, halves):
+                lv.res = math.sqrt(2.0 * h)
             for h, F in zip(hist, Fs):
                 h.append(F)
             if callback is not None:
@@ -210,6 +217,7 @@ class MGRecord:
     coarse_updates: int = 0
     grad_ratio: float = 0.0   # ||R grad F_rho(y)|| / ||grad F_rho(y)|| at the decision
     depth: int = 0            # deepest level a recursive step reached (0: direct step)
+    res: float = 0.0          # RES(x_k) = ||H x_k - p_hat|| at the target level
 
 
 class _LevelPair:
@@ -374,6 +382,7 @@ def _mg_fista(levels, x0, n_iter: int, p: MGParams, callback, pairs):
             x = _direct(fine, y, p.prox_iter, gf)
             rec = MGRecord("direct", 0.0, 0, ratio)
         rec.F = fine.objective(x)
+        rec.res = fine.res
         hist.append(rec)
         if callback is not None:
             callback(k, x, rec)
