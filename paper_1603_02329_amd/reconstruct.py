@@ -1,9 +1,9 @@
-"""Reconstruction of a synthetic multi-level 2D problem on the GPU: ISTA,
+"""Reconstruction of a synthetic multi-level 2D or 3D problem on the GPU: ISTA,
 FISTA and their multi-grid variants (Alg. ISTA, Alg. FISTA, Alg. FISTAMG),
 with the objective F, the relative error RE and the residual norm RES
 (section VI) and the elapsed time after every iteration.
 
-    python -m paper_1603_02329_amd.reconstruct [--n 512] [--iters 20]
+    python -m paper_1603_02329_amd.reconstruct [--dim 2|3] [--n 512] [--iters 20]
         [--methods ista,mg-ista,fista,mg-fista] [--lam 1e-2] [--levels 2]
         [--eps-c 1e-2] [--smooth-p0] [--json out.json]
 
@@ -17,7 +17,10 @@ method on each level: 2/L_f for ISTA (as in section VI-A), 1/L_f for FISTA;
 the two-level parameters are the paper's 2D values (kappa 1/4, vartheta
 0.1, q_d 3, q_c 8, eps_c 1e-2, rho 1e-2).  The data are generated on the
 reconstruction grid itself, so this shows convergence against time, not
-the paper's inverse-crime-free errors.  With --smooth-p0 every level's
+the paper's inverse-crime-free errors.  --dim 3: the 3D workload's medium
+and ellipsoid phantom (128^3 / 64^3 by default, N_t 800 / 400, planar
+sensor at the PML), with the paper's 3D parameters (kappa 1/8, rho 3e-2;
+section VI-B).  With --smooth-p0 every level's
 operators filter the initial pressure (H = H0 S, H^T = S H0^T).
 """
 from __future__ import annotations
@@ -32,10 +35,14 @@ import numpy as np
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("--n", type=int, default=512, help="fine grid size (power of two, >= 64)")
+    ap.add_argument("--dim", type=int, default=2, choices=(2, 3), help="2D (default) or 3D problem")
+    ap.add_argument("--n", type=int, default=0,
+                    help="fine grid size (power of two; default 512 in 2D, 128 in 3D)")
     ap.add_argument("--iters", type=int, default=20)
     ap.add_argument("--methods", default="ista,mg-ista,fista,mg-fista")
     ap.add_argument("--lam", type=float, default=1e-2)
+    ap.add_argument("--kappa", type=float, default=0.0, help="decision threshold (default 1/4 in 2D, 1/8 in 3D)")
+    ap.add_argument("--rho", type=float, default=0.0, help="TV smoothing (default 1e-2 in 2D, 3e-2 in 3D)")
     ap.add_argument("--power-iters", type=int, default=20)
     ap.add_argument("--levels", type=int, default=2, help="grid levels of the MG variants (2: the paper's)")
     ap.add_argument("--eps-c", type=float, default=1e-2, help="coarse-solve termination (relative decrease)")
@@ -53,11 +60,20 @@ def main(argv=None):
     from . import solver as S
 
     dev = torch.device("cuda:0")
-    n = args.n
-    pml = max(4, 20 * n // 512)
-    nt = max(64, 2400 * n // 512)
-    # the first two levels are those of the two-level workload (same draws)
-    insts = synth.multi_level(3, 0, n, 1e-4, pml, nt, 256, max(2, args.levels))
+    nd = args.dim
+    n = args.n or (512 if nd == 2 else 128)
+    kappa = args.kappa or (0.25 if nd == 2 else 0.125)
+    rho = args.rho or (1e-2 if nd == 2 else 3e-2)
+    if nd == 2:
+        pml = max(4, 20 * n // 512)
+        nt = max(64, 2400 * n // 512)
+        # the first two levels are those of the two-level workload (same draws)
+        insts = synth.multi_level(3, 0, n, 1e-4, pml, nt, 256, max(2, args.levels))
+    else:
+        # the 128^3 workload's grid, PML and time axis; planar sensor at the PML
+        pml = max(2, 16 * n // 128)
+        nt = max(32, 800 * n // 128)
+        insts = synth.multi_level_3d(5, 0, n, 2e-4, pml, nt, max(2, args.levels))
     if args.smooth_p0:
         from dataclasses import replace
         insts = [synth.Instance(replace(i.desc, smooth_p0=True), i.c0, i.rho0, i.alpha0_db, i.sensors, i.p0, i.name)
@@ -78,7 +94,7 @@ def main(argv=None):
     for l, p in enumerate(plans):
         Ls.append(S.power_iteration(p, v, args.power_iters))
         v = restrict(v)
-    print("grids " + " / ".join(f"{i.desc.n[0]}^2" for i in insts) + ", N_t " +
+    print("grids " + " / ".join(f"{i.desc.n[0]}^{nd}" for i in insts) + ", N_t " +
           " / ".join(str(i.desc.nt) for i in insts) + "; L_f " + ", ".join(f"{x:.4e}" for x in Ls) +
           f" ({time.perf_counter() - t0:.1f} s)", flush=True)
     norm_exact = math.sqrt(float((p_exact.double() ** 2).sum()))
@@ -111,15 +127,15 @@ def main(argv=None):
 
         if method.startswith("mg-"):
             S.mg_fista(fine, levels[1:args.levels], x0, args.iters,
-                       S.MGParams(momentum=momentum, eps_c=args.eps_c,
+                       S.MGParams(momentum=momentum, eps_c=args.eps_c, kappa=kappa, rho=rho,
                                   batch_levels=not args.no_batch_levels), callback=log)
         else:
             S.fista(fine, x0, args.iters, momentum=momentum, callback=log)
         results[method] = rows
     if args.json:
         with open(args.json, "w") as f:
-            json.dump({"n": n, "nt": nt, "lam": args.lam, "levels": args.levels, "L_f": Ls, "results": results}, f,
-                      indent=1)
+            json.dump({"dim": nd, "n": n, "nt": nt, "lam": args.lam, "kappa": kappa, "rho": rho, "levels": args.levels,
+                       "L_f": Ls, "results": results}, f, indent=1)
 
 
 if __name__ == "__main__":
