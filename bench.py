@@ -83,11 +83,10 @@ def row_kernel_name(plans, kind: int) -> str:
     return f"k_row<{nx}, {len(plans[0].desc.n)}, {kind}>"
 
 
-def counter_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary, or None when that summary was taken on different kernel
-    sources (or is missing)."""
-    path = os.path.join(ROOT, "profiles", "cfg4_counters_fetch_write.md")
+def _summary_fields(name: str):
+    """The `- key: value` lines of a committed rocprofv3 counter summary, or
+    None when it is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     fields = {}
@@ -95,10 +94,23 @@ def counter_traffic(kernel: str):
         if line.startswith("- ") and ": " in line:
             k, v = line[2:].strip().split(": ", 1)
             fields[k] = v.strip("` ")
-    if fields.get("kernel_source_sha256") != kernel_source_hash():
-        return None
+    return fields if fields.get("kernel_source_sha256") == kernel_source_hash() else None
+
+
+def counter_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when that summary was taken on different kernel
+    sources (or is missing)."""
+    fields = _summary_fields("cfg4_counters_fetch_write.md")
     key = f"traffic_bytes_per_launch[{kernel}]"
-    return float(fields[key]) if key in fields else None
+    return float(fields[key]) if fields and key in fields else None
+
+
+def step_traffic():
+    """Measured HBM bytes per grid-point-step of a whole forward + adjoint of
+    the 48-instance workload (committed counter summary), or None."""
+    fields = _summary_fields("cfg4_step_counters_fetch_write.md")
+    return float(fields["traffic_bytes_per_gps"]) if fields and "traffic_bytes_per_gps" in fields else None
 
 
 def cpu_baseline(insts, seconds_target=15.0):
@@ -161,6 +173,10 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="counter probe: a 1 GiB device copy (calibration) and a burst of the roofline "
                          "phase's launches; run under rocprofv3 --pmc")
+    ap.add_argument("--pmc-step", action="store_true",
+                    help="counter probe of a whole step: the calibration copy, then one forward and one "
+                         "adjoint of the workload with the time axes cut to a tenth, every pass launched "
+                         "eagerly; run under rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the solver runs each instance on a single device, and "
@@ -173,6 +189,14 @@ def main():
     import paper_1603_02329_amd as pat
     dev = torch.device("cuda:0")
     insts, wl_name = workload(args.workload)
+    if args.pmc_step:
+        # the same instances with a tenth of their time axes: the size
+        # classes keep their step ratios, so each step of a fused group
+        # carries the same mix of instances as at full length
+        import synth
+        from dataclasses import replace
+        insts = [synth.Instance(replace(i.desc, nt=max(2, i.desc.nt // 10)), i.c0, i.rho0, i.alpha0_db, i.sensors,
+                                i.p0, i.name) for i in insts]
     if args.pmc_probe:
         # same instances and launch geometry, 9 time samples: the per-launch
         # traffic of a pass does not depend on the length of the time axis
@@ -202,6 +226,18 @@ def main():
         probe.time_pass(tdir, tidx, max(p.desc.n[0] for p in plans), 20)  # the roofline phase's launches
         torch.cuda.synchronize()
         log("pmc probe done")
+        return
+    if args.pmc_step:
+        a = torch.ones(256 * 1024 * 1024, device=dev)
+        flush = torch.zeros(256 * 1024 * 1024, device=dev)
+        b = torch.add(a, 1.0)
+        del flush, b, a
+        bs = pat.Batch(plans, chunk=1)
+        d = bs.forward(x_true)
+        bs.adjoint(d)
+        torch.cuda.synchronize()
+        gps = sum(float(p.desc.npoints) * p.desc.nt for p in plans)
+        log(f"pmc step done: {len(plans)} instances, {gps:.6e} grid-point-steps per direction")
         return
     tdir, tidx = (int(v) for v in args.time_pass.split(":"))
     nx_dom = max(p.desc.n[0] for p in plans)  # time the largest grids' launches only
@@ -346,6 +382,7 @@ def main():
             },
             "step_frac": value * b_alg / (HBM_PEAK_GBS * 1e9),
             "bytes_per_gps": b_alg,
+            "step_traffic_bytes_per_gps": step_traffic() if args.workload == "cfg4" else None,
         },
     }
     if not args.no_cpu:
