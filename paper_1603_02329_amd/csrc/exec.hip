@@ -287,6 +287,21 @@ struct Runner {
   }
 };
 
+// Column tile widths of the eager (one-instance) path in 2D.  One grid has
+// few columns, so tiles narrower than the default put more workgroups on the
+// 256 CUs: forward + adjoint of one 512^2 instance 290 -> 257 ms with 8
+// columns per workgroup, 256^2 114 -> 107 ms and 128^2 49 -> 48 ms with 4
+// (same-box, results bitwise unchanged).  The 3D z passes keep the default
+// (narrower tiles ran 7-14 % slower at 128^3).
+struct EagerTiles {
+  ColVariant t8[3 * kMaxOps], t4[3 * kMaxOps];
+  EagerTiles() {
+    for (auto& v : t8) v = ColVariant{8, 1};
+    for (auto& v : t4) v = ColVariant{4, 1};
+  }
+};
+const EagerTiles g_eager_tiles;
+
 Runner eager_runner(const pat_plan* p) {
   Runner r{};
   r.ndim = p->desc.ndim;
@@ -301,7 +316,8 @@ Runner eager_runner(const pat_plan* p) {
   r.row_n = (p->hp.nrows + R - 1) / R;
   r.red_n = 0;
   r.ncolw = 0;
-  r.vars = nullptr;
+  const bool tunable = r.ny == 128 || r.ny == 256 || r.ny == 512;
+  r.vars = (r.ndim == 2 && tunable) ? (r.ny == 512 ? g_eager_tiles.t8 : g_eager_tiles.t4) : nullptr;
   r.points = (double)p->npoints;
   return r;
 }
