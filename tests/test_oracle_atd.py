@@ -3,7 +3,17 @@ the paper's adjoint system discretized with the forward's scheme.  It is
 not the exact transpose, so it is pinned where the mathematics fixes it:
 identity with the exact transpose where the scheme is time-symmetric
 (homogeneous, no PML, lossless or absorption only), first-order convergence
-to it in dt for a heterogeneous medium, linearity."""
+to it in dt for a heterogeneous medium (lossless, and lossy with
+heterogeneous absorption and density), linearity.
+
+The lossy heterogeneous case also pins the forward itself: adjoint_atd is
+written from the paper's adjoint state equation (statea: rho0 applied after
+the fractional Laplacian, tau and c0^2 inside it), independently of the
+forward, while ``adjoint`` is the exact transpose of the forward.  The two
+converge to each other only if the forward's state equation puts tau(r)
+outside L1 and rho0(r) inside it (section II-A, eq. state and Twelve, whose
+continuous adjoint is statea): with either moved across the operator, the
+difference stalls at a commutator that does not shrink with dt."""
 from dataclasses import replace
 
 import numpy as np
@@ -71,9 +81,94 @@ def test_atd_converges_to_the_transpose_at_first_order():
         assert 1.7 < a / b < 2.3, d
 
 
+def _lossy_hetero_case(cfl):
+    """Heterogeneous c0, per-point alpha0 (white, +-33 %), density with +-30 %
+    white variation, no PML, eta = 0 (the dispersion term's difference is
+    the initial-density reading, independent of dt)."""
+    inst = synth.small_instance(5, (32, 32), nt=2, ns=6, pml=0, pml_on=False)
+    nt = int(round(T / (cfl * 1e-4 / 1500))) + 1
+    desc = replace(inst.desc, cfl=cfl, nt=nt)
+    rho = (1000.0 * (1.0 + 0.3 * np.random.default_rng(11).uniform(-1, 1, size=inst.c0.shape))).astype(np.float32)
+    op = K.make_plan(desc, inst.c0, rho, inst.alpha0_db, inst.sensors)
+    op.eta = np.zeros_like(op.eta)
+    t = np.arange(nt) * op.dt
+    h = np.stack([np.sin(2 * np.pi * t / T * (s + 1)) * np.exp(-((t - T / 2) / (T / 4)) ** 2)
+                  for s in range(inst.ns)], axis=1)
+    return op, h
+
+
+def test_atd_pins_the_heterogeneous_absorption_order():
+    """Heterogeneous lossy medium: the paper's adjoint (statea) and the exact
+    transpose of the forward differ at first order in dt only.  Measured
+    differences 2.8e-3, 1.34e-3, 6.7e-4 (ratios 2.08, 2.02).  Forwards with
+    tau moved inside L1, or rho0 moved outside it (each with its own exact
+    transpose), stall: ratios 1.60 / 1.25 and 1.64 / 1.27; a flipped tau
+    sign or a dropped rho0 leave a gap of 7-15 % that does not shrink."""
+    d = []
+    for cfl in (0.3, 0.15, 0.075):
+        op, h = _lossy_hetero_case(cfl)
+        assert np.abs(op.tau).max() > 0 and np.ptp(op.tau) > 0.3 * np.abs(op.tau).max()
+        d.append(_rel(K.adjoint_atd(op, h), K.adjoint(op, h)))
+    assert 0 < d[0] < 1e-2, d
+    for a, b in zip(d, d[1:]):
+        assert 1.85 < a / b < 2.3, d
+
+
 def test_atd_is_linear():
     op, h = _case(0.3, lossy=True, hetero=True, pml=4, pml_on=True)
     g = np.random.default_rng(3).standard_normal(h.shape)
     lhs = K.adjoint_atd(op, 2.0 * h - 0.5 * g)
     rhs = 2.0 * K.adjoint_atd(op, h) - 0.5 * K.adjoint_atd(op, g)
     assert _rel(lhs, rhs) < 1e-12
+
+
+def _forward_from_density(op, p0, rho_total):
+    """H p0 with the split densities started at rho_total / d instead of the
+    build's p0 / (d c0^2); everything else as ``K.forward``."""
+    st = K.ForwardState(op, p0)
+    st.rho = [rho_total / op.ndim for _ in range(op.ndim)]
+    data = [K.gather(op, st.p)]
+    for _ in range(op.nt - 1):
+        K.step(op, st)
+        data.append(K.gather(op, st.p))
+    return np.array(data)
+
+
+def test_atd_is_the_transpose_of_the_section3_initial_density():
+    """The dispersion term's gap between the paper's adjoint and the exact
+    transpose is the build's initial-density reading, not the paper's route.
+
+    Section III's derivation relates the initial density to p0 through the
+    state equation at t = 0: c0^2 (1 - eta L2) rho(0) = p0 (u(0) = 0 removes
+    the tau term).  The build starts at rho(0) = p0 / c0^2 instead.  In a
+    homogeneous medium with tau = 0 and no PML the paper's adjoint equals,
+    to rounding, the dense transpose of a forward started at
+    (1 - eta L2)^-1 p0 / c0^2 (a spectral division), while it differs from
+    the exact transpose of the build's forward by an amount that does not
+    shrink with dt."""
+    inst = synth.small_instance(5, (16, 16), nt=2, ns=6, hetero=False, pml=0, pml_on=False)
+    nt = 31
+    desc = replace(inst.desc, cfl=0.3, nt=nt)
+    op = K.make_plan(desc, inst.c0, inst.rho0, np.full(inst.c0.shape, 0.75, np.float32), inst.sensors)
+    op.tau = np.zeros_like(op.tau)
+    eta = float(op.eta.flat[0])
+    assert np.allclose(op.eta, eta) and eta != 0  # tan(pi y / 2) < 0 for 1 < y < 2
+    t = np.arange(nt) * op.dt
+    T_ = t[-1]
+    h = np.stack([np.sin(2 * np.pi * t / T_ * (s + 1)) * np.exp(-((t - T_ / 2) / (T_ / 4)) ** 2)
+                  for s in range(inst.ns)], axis=1)
+    c2 = float(op.c0sq.flat[0])
+    inv = 1.0 / (1.0 - eta * op.L2)      # (1 - eta L2)^-1 as a multiplier (homogeneous eta)
+    n = int(np.prod(op.shape))
+    cols = []
+    for q in range(n):
+        e = np.zeros(n)
+        e[q] = 1.0
+        e = e.reshape(op.shape)
+        cols.append(_forward_from_density(op, e, np.fft.ifftn(inv * np.fft.fftn(e / c2)).real).ravel())
+    H3 = np.array(cols).T                 # (nt * ns, N)
+    atd = K.adjoint_atd(op, h).ravel()
+    assert _rel(atd, H3.T @ h.ravel()) < 1e-12
+    # the build's forward (rho(0) = p0 / c0^2): a gap of order eta L2
+    gap = _rel(atd, K.adjoint(op, h).ravel())
+    assert 1e-4 < gap < 5e-2, gap
