@@ -164,11 +164,9 @@ def blackman_k(n: int) -> np.ndarray:
     return 0.42 + 0.5 * np.cos(2.0 * math.pi * m / n) + 0.08 * np.cos(4.0 * math.pi * m / n)
 
 
-def smooth_medium(f: np.ndarray) -> np.ndarray:
-    """Spectral smoothing of a medium map (section VI-A: the paper's models
-    ran on maps smoothed against aliasing; the paper does not name the
-    window, this one is a chosen reading): the spectrum times the product over the axes of
-    ``blackman_k``, back-transformed (real part)."""
+def window_filter(f: np.ndarray) -> np.ndarray:
+    """The field's spectrum times the product over the axes of ``blackman_k``,
+    back-transformed (real part)."""
     f = np.asarray(f, dtype=np.float64)
     W = np.ones(f.shape)
     for ax, n in enumerate(f.shape):
@@ -181,22 +179,18 @@ def smooth_medium(f: np.ndarray) -> np.ndarray:
 def smooth_initial(f: np.ndarray) -> np.ndarray:
     """The smoothing S of the initial pressure (section VI-A: the forward
     model filters the high frequencies of p0 with a self-adjoint operator,
-    which the adjoint then includes).  Reading: the spectral window of
-    ``smooth_medium`` -- real and even in k, so that S is a real symmetric
-    matrix and the operator pair stays exactly transposed:
-    H = H0 S, H^T = S H0^T."""
-    return smooth_medium(f)
+    which the adjoint then includes).  Reading (the paper names neither the
+    filter nor its cut-off): ``window_filter``, a spectral window real and
+    even in k, so that S is a real symmetric matrix and the operator pair
+    stays exactly transposed: H = H0 S, H^T = S H0^T."""
+    return window_filter(f)
 
 
 def make_plan(desc, c0, rho0, alpha0_db, sensors) -> OraclePlan:
-    """Derive every coefficient of the scheme in FP64 from the float32 inputs
-    (with ``desc.smooth``, from the smoothed sound speed and density)."""
+    """Derive every coefficient of the scheme in FP64 from the float32 inputs."""
     nd = desc.ndim
     c0 = np.asarray(c0, dtype=np.float64)
     rho0 = np.asarray(rho0, dtype=np.float64)
-    if getattr(desc, "smooth", False):
-        c0 = smooth_medium(c0)
-        rho0 = smooth_medium(rho0)
     shape = c0.shape
     assert shape == tuple(reversed(desc.n[:nd]))
     c_ref = float(c0.max())

@@ -66,7 +66,6 @@ class GridDesc:
     pml_alpha: float = 2.0
     alpha_power: float = 1.5
     pml: bool = True
-    smooth: bool = False  # smooth c0 and rho0 spectrally before use
     smooth_p0: bool = False  # smooth the initial pressure inside H (and H^T)
 
     @property

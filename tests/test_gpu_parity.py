@@ -106,22 +106,6 @@ def test_config5_short_parity():
     assert rel(img, ri) <= 1e-5
 
 
-@pytest.mark.parametrize("n", [(64, 32), (16, 32, 16)])
-def test_smoothed_medium_parity(n):
-    """Plans with the medium smoothed at creation (host float64 FFT) against
-    the oracle's smoothing (numpy FFT): forward and adjoint; the smoothing
-    changes the result (it is applied)."""
-    import dataclasses
-    inst = synth.small_instance(130 + len(n), n, nt=20, ns=6, pml=3, lossy=True)
-    sm = synth.Instance(dataclasses.replace(inst.desc, smooth=True), inst.c0, inst.rho0, inst.alpha0_db,
-                        inst.sensors, inst.p0, inst.name)
-    _, d, img, rd, ri, _ = run_pair(sm)
-    assert rel(d, rd) <= 1e-5
-    assert rel(img, ri) <= 1e-5
-    _, d0, _, _, _, _ = run_pair(inst)
-    assert rel(d0, d) > 1e-4
-
-
 SMOOTH_P0_CASES = [
     dict(n=(64, 32), nt=20, ns=6, pml=3, lossy=True, hetero=True),
     dict(n=(32, 128), nt=12, ns=5, pml=4, lossy=False, hetero=True),

@@ -356,17 +356,17 @@ def test_absorption_unit_conversion():
 
 
 # ---------------------------------------------------------------------------
-# medium smoothing (plan option)
+# the spectral window of the p0 smoothing
 # ---------------------------------------------------------------------------
 
-def test_smooth_medium_by_brute_force_and_modes():
-    """The smoothing filter against an explicit circular convolution with
-    the window's inverse DFT kernel (O(n^2) per axis, no FFT); a constant
-    map is unchanged; a single Fourier mode is scaled by the window and the
-    Nyquist mode removed."""
+def test_window_filter_by_brute_force_and_modes():
+    """The window filter of the initial-pressure smoothing against an
+    explicit circular convolution with the window's inverse DFT kernel
+    (O(n^2) per axis, no FFT); a constant field is unchanged; a single
+    Fourier mode is scaled by the window and the Nyquist mode removed."""
     rng = np.random.default_rng(17)
     f = rng.standard_normal((8, 12))
-    out = K.smooth_medium(f)
+    out = K.window_filter(f)
     ref = f.copy()
     for ax, n in enumerate(f.shape):
         w = K.blackman_k(n)
@@ -381,23 +381,13 @@ def test_smooth_medium_by_brute_force_and_modes():
                 conv[tuple(dst)] += kern[(x - s) % n] * src
         ref = conv
     assert np.max(np.abs(out - ref)) < 1e-12
-    assert np.max(np.abs(K.smooth_medium(np.full((8, 16), 1500.0)) - 1500.0)) < 1e-10
+    assert np.max(np.abs(K.window_filter(np.full((8, 16), 1500.0)) - 1500.0)) < 1e-10
     x = np.arange(16)
     for mode in (0, 3, 8):
         g = np.cos(2 * np.pi * mode * x / 16)[None, :] * np.ones((4, 1))
         expect = K.blackman_k(16)[mode] * K.blackman_k(4)[0] * g
-        assert np.max(np.abs(K.smooth_medium(g) - expect)) < 1e-12
+        assert np.max(np.abs(K.window_filter(g) - expect)) < 1e-12
     assert K.blackman_k(16)[8] == pytest.approx(0.0, abs=1e-15) and K.blackman_k(16)[0] == pytest.approx(1.0)
-
-
-def test_smoothed_plan_uses_the_smoothed_medium():
-    import dataclasses
-    inst = synth.small_instance(18, (16, 16), nt=6, ns=4, pml=2)
-    desc = dataclasses.replace(inst.desc, smooth=True)
-    op = K.make_plan(desc, inst.c0, inst.rho0, inst.alpha0_db, inst.sensors)
-    cs = K.smooth_medium(inst.c0)
-    assert np.max(np.abs(op.c0 - cs)) == 0.0 and op.c_ref == cs.max()
-    assert np.max(np.abs(op.rho0 - K.smooth_medium(inst.rho0))) == 0.0
 
 
 # ---------------------------------------------------------------------------
