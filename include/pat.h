@@ -43,18 +43,14 @@ extern "C" {
 /* ------------------------------------------------------------------ flags */
 #define PAT_NO_PML        0x1u  /* switch the PML off: periodic grid             */
 #define PAT_CHECK_FINITE  0x2u  /* record non-finite pressure; see pat_plan_sync */
-#define PAT_SMOOTH_MEDIUM 0x4u  /* smooth c0 and rho0 spectrally before use (section VI-A:
-                                   the paper's models ran on smoothed maps): each axis'
-                                   spectrum times the Blackman window centred on k = 0,
-                                   0.42 + 0.5 cos(2 pi m/n) + 0.08 cos(4 pi m/n); float64,
-                                   on the host, at plan creation */
 #define PAT_SMOOTH_P0     0x8u  /* filter the initial pressure inside the operators
                                    (section VI-A: a self-adjoint smoothing of p0 in
                                    every forward, included in the adjoint):
                                    H = H0 S, H^T = S H0^T with S = F^-1 w F and w the
-                                   product over the axes of the window above (real and
-                                   even, so S is symmetric); pat_adjoint_atd also ends
-                                   with S */
+                                   product over the axes of the Blackman window centred
+                                   on k = 0, 0.42 + 0.5 cos(2 pi m/n) + 0.08 cos(4 pi m/n)
+                                   (1 at k = 0, 0 at the Nyquist bin; real and even, so S
+                                   is symmetric); pat_adjoint_atd also ends with S */
 
 /* pat_batch_create_ex flags */
 #define PAT_BATCH_NO_FUSE 0x1u  /* keep every size class in launches of its own */
@@ -129,6 +125,27 @@ typedef struct pat_batch pat_batch;
  */
 int pat_plan_create(pat_plan** out, const pat_desc* desc, const float* c0, const float* rho0,
                     const float* alpha0_db, const double* sensor_pos, void* stream);
+
+/*
+ * pat_desc_check -- the host-side checks of pat_plan_create, without a device.
+ *
+ * Runs the descriptor validation, the stability bound of the scheme and the
+ * construction of the linear-interpolation sensor operator (section III,
+ * M w) on the host only: no HIP call is made, so it can run where no GPU is
+ * present.
+ *
+ *  desc        descriptor as for pat_plan_create.
+ *  lossy       non-zero when the plan will be given alpha0_db (checks
+ *              alpha_power).
+ *  sensor_pos  host, n_sensors*ndim doubles, as for pat_plan_create.
+ *  c_max       largest sound speed of the medium [m/s]; > 0 also checks the
+ *              stability bound c_max dt / min dx <= 1/sqrt(ndim) with the
+ *              dt the plan would use; <= 0 skips that check.
+ *
+ * Returns PAT_OK, PAT_EINVAL (descriptor, NULL sensor_pos, sensor outside
+ * the grid or not finite) or PAT_EUNSTABLE.
+ */
+int pat_desc_check(const pat_desc* desc, int32_t lossy, const double* sensor_pos, double c_max);
 
 /* Release a plan and its device memory (NULL is accepted). */
 void pat_plan_destroy(pat_plan* plan);
@@ -383,13 +400,19 @@ int pat_prolong(int32_t ndim, const int32_t n_coarse[3], const float* coarse, fl
  * 1/2 ||Hx - p||^2 and the norms of the multi-grid decision rule (sections
  * IV, V).  Synchronises `stream` and writes the result to *out_host.
  * b == a gives the squared norm.  n may be 0 (result 0).
+ * Scratch: 4 KB of device memory per (device, stream), allocated by the
+ * first reduction on that stream (this call, pat_residual_f64 or
+ * pat_tv_smooth) and kept until the process ends; reductions on different
+ * streams, or from different host threads on different streams, may run
+ * concurrently.
  */
 int pat_dot_f64(const float* a, const float* b, int64_t n, double* out_host, void* stream);
 
 /*
  * pat_residual_f64 -- r = a - b written to device `r` (float32) and
  * 1/2 ||a - b||^2 accumulated in float64 (deterministic), in one pass.
- * Synchronises `stream`; *half_sq_host receives the value.
+ * Synchronises `stream`; *half_sq_host receives the value.  Scratch as
+ * pat_dot_f64.
  */
 int pat_residual_f64(const float* a, const float* b, float* r, int64_t n, double* half_sq_host,
                      void* stream);

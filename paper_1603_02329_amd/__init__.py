@@ -25,7 +25,6 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpat.so")
 PAT_OK, PAT_EINVAL, PAT_EUNSTABLE, PAT_ENOMEM, PAT_EHIP, PAT_ENONFINITE, PAT_ENOSYS = range(7)
 PAT_NO_PML = 0x1
 PAT_CHECK_FINITE = 0x2
-PAT_SMOOTH_MEDIUM = 0x4
 PAT_SMOOTH_P0 = 0x8
 PAT_BATCH_NO_FUSE = 0x1
 PAT_BATCH_NO_STAGGER = 0x2
@@ -39,7 +38,7 @@ EXPORTED = [
     "pat_dot_f64", "pat_residual_f64", "pat_plan_sync", "pat_strerror", "pat_timing_begin",
     "pat_timing_end", "pat_batch_autotune", "pat_tuning_report", "pat_batch_set_tile", "pat_batch_time_pass",
     "pat_tv_smooth", "pat_restrict_lower", "pat_axpby", "pat_project", "pat_forward_batched",
-    "pat_adjoint_batched",
+    "pat_adjoint_batched", "pat_desc_check",
 ]
 
 
@@ -83,6 +82,7 @@ def lib() -> ctypes.CDLL:
     sig = {
         "pat_plan_create": (ctypes.c_int, [pp, ctypes.POINTER(CDesc), vp, vp, vp, vp, vp]),
         "pat_plan_destroy": (None, [vp]),
+        "pat_desc_check": (ctypes.c_int, [ctypes.POINTER(CDesc), i32, vp, f64]),
         "pat_plan_info": (ctypes.c_int, [vp, ctypes.POINTER(CInfo)]),
         "pat_forward": (ctypes.c_int, [vp, vp, vp, vp]),
         "pat_adjoint": (ctypes.c_int, [vp, vp, vp, vp]),
@@ -177,7 +177,6 @@ def make_desc(desc, n_sensors: int, check_finite: bool = False) -> CDesc:
     c.alpha_power = float(desc.alpha_power)
     c.n_sensors = int(n_sensors)
     c.flags = ((0 if getattr(desc, "pml", True) else PAT_NO_PML) | (PAT_CHECK_FINITE if check_finite else 0) |
-               (PAT_SMOOTH_MEDIUM if getattr(desc, "smooth", False) else 0) |
                (PAT_SMOOTH_P0 if getattr(desc, "smooth_p0", False) else 0))
     return c
 

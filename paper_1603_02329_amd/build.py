@@ -1,8 +1,9 @@
 """Build libpat.so for gfx950 with hipcc (no JIT, in-tree output).
 
-Every .hip source under csrc/ is compiled to an object in parallel and the
-objects are linked into paper_1603_02329_amd/libpat.so.  Packed-FP32 VALU
-instructions are disabled on the device side.
+Every .hip source under csrc/ is compiled by hipcc, every host-only .cpp
+source by g++, in parallel, and the objects are linked into
+paper_1603_02329_amd/libpat.so.  Packed-FP32 VALU instructions are disabled
+on the device side.
 """
 from __future__ import annotations
 
@@ -16,6 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpat.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+CXX = os.environ.get("CXX", "g++")
 ARCH = "gfx950"
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -23,16 +25,23 @@ COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno
           "-Wno-unused-variable", "-Wno-unused-but-set-variable", "-I", os.path.join(HERE, "..", "include")]
 
 
+HOST_FLAGS = ["-std=c++17", "-O2", "-fPIC", "-Wall", "-I", os.path.join(HERE, "..", "include")]
+
+
 def sources():
-    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+    return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
 def _compile(src: str) -> str:
-    obj = os.path.join(OBJ, os.path.basename(src)[:-4] + ".o")
-    cmd = [HIPCC, *COMMON, *DEVICE_FLAGS, "-c", src, "-o", obj]
+    stem, ext = os.path.splitext(os.path.basename(src))
+    obj = os.path.join(OBJ, stem + (".o" if ext == ".hip" else ".host.o"))
+    if ext == ".cpp":  # host-only code: no HIP headers, plain C++
+        cmd = [CXX, *HOST_FLAGS, "-c", src, "-o", obj]
+    else:
+        cmd = [HIPCC, *COMMON, *DEVICE_FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr[-8000:]}")
+        raise RuntimeError(f"{cmd[0]} failed on {src}:\n{r.stderr[-8000:]}")
     return obj
 
 

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -337,18 +338,24 @@ __global__ void __launch_bounds__(kRedThreads) k_red_tv(Grid3 g, int ndim, const
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+// Scratch of the float64 reductions (kRedBlocks partials + 1 result), one
+// buffer per (device, stream): calls on one stream run in stream order and
+// share it; calls on different streams, or from different threads on
+// different streams, never do.  Allocated on a stream's first reduction and
+// kept until the process ends (4 KB each).
 std::mutex g_red_mu;
-std::vector<double*> g_red_buf;  // per device: kRedBlocks partials + 1 result
+std::map<std::pair<int, hipStream_t>, double*> g_red_buf;
 
-int red_buffer(double** out) {
+int red_buffer(hipStream_t st, double** out) {
   int dev = 0;
   PAT_TRY_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_red_mu);
-  if ((int)g_red_buf.size() <= dev) g_red_buf.resize(dev + 1, nullptr);
-  if (!g_red_buf[dev]) {
-    if (hipMalloc(&g_red_buf[dev], sizeof(double) * (kRedBlocks + 1)) != hipSuccess) return PAT_ENOMEM;
+  double*& b = g_red_buf[std::make_pair(dev, st)];
+  if (!b && hipMalloc(&b, sizeof(double) * (kRedBlocks + 1)) != hipSuccess) {
+    b = nullptr;
+    return PAT_ENOMEM;
   }
-  *out = g_red_buf[dev];
+  *out = b;
   return PAT_OK;
 }
 
@@ -419,22 +426,18 @@ extern "C" int pat_tv_prox_batched(int32_t count, int32_t ndim, const int32_t* n
   return PAT_OK;
 }
 
-extern "C" int pat_tv_prox(int32_t ndim, const int32_t n[3], const float* z, float* x, double lambda_eff,
-                           int32_t n_iter, const float* lower, void* work, size_t work_bytes, void* stream) {
-  Grid3 g;
-  if (make_grid(ndim, n, g)) return PAT_EINVAL;
-  if (!z || !x || z == x || !(lambda_eff >= 0) || !std::isfinite(lambda_eff) || n_iter < 0) return PAT_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
+namespace {
+
+// The FGP iterations of pat_tv_prox on a workspace of (2 ndim + 1) N floats
+// (dual r, previous dual, primal iterate), which it clears itself.
+int tv_prox_run(const Grid3& g, int ndim, const float* z, float* x, double lambda_eff, int n_iter,
+                const float* lower, float* work, hipStream_t st) {
   const int nb = blocks_for(g.N);
-  if (lambda_eff == 0.0 || n_iter == 0) {
-    if (lambda_eff != 0.0 && n_iter == 0) {
-      // zero iterations of FGP: output is P_C(z - lam L 0) = P_C(z)
-    }
+  if (lambda_eff == 0.0 || n_iter == 0) {  // P_C(z - lam L 0) = P_C(z)
     hipLaunchKernelGGL(k_proj, dim3(nb), dim3(256), 0, st, g.N, z, lower, x);
     return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
   }
-  if (!work || work_bytes < pat_tv_prox_work_bytes(ndim, n)) return PAT_EINVAL;
-  float* r = (float*)work;
+  float* r = work;
   float* pprev = r + (long)ndim * g.N;
   float* xt = pprev + (long)ndim * g.N;
   hipLaunchKernelGGL(k_zero, dim3(blocks_for(2L * ndim * g.N)), dim3(256), 0, st, 2L * ndim * g.N, r);
@@ -450,6 +453,17 @@ extern "C" int pat_tv_prox(int32_t ndim, const int32_t n[3], const float* z, flo
   }
   hipLaunchKernelGGL(k_prox_primal, dim3(nb), dim3(256), 0, st, g, ndim, z, lower, pprev, lam, x);
   return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
+}
+
+}  // namespace
+
+extern "C" int pat_tv_prox(int32_t ndim, const int32_t n[3], const float* z, float* x, double lambda_eff,
+                           int32_t n_iter, const float* lower, void* work, size_t work_bytes, void* stream) {
+  Grid3 g;
+  if (make_grid(ndim, n, g)) return PAT_EINVAL;
+  if (!z || !x || z == x || !(lambda_eff >= 0) || !std::isfinite(lambda_eff) || n_iter < 0) return PAT_EINVAL;
+  if (lambda_eff != 0.0 && n_iter != 0 && (!work || work_bytes < pat_tv_prox_work_bytes(ndim, n))) return PAT_EINVAL;
+  return tv_prox_run(g, ndim, z, x, lambda_eff, n_iter, lower, (float*)work, (hipStream_t)stream);
 }
 
 extern "C" int pat_restrict(int32_t ndim, const int32_t n_fine[3], const float* fine, float* coarse, void* stream) {
@@ -485,7 +499,7 @@ static int reduce_common(int op, const float* a, const float* b, float* r, int64
     return PAT_OK;
   }
   double* buf = nullptr;
-  int rc = red_buffer(&buf);
+  int rc = red_buffer(st, &buf);
   if (rc) return rc;
   if (op == 0)
     hipLaunchKernelGGL(k_red1<0>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, a, b, r, (long)n, buf);
@@ -521,7 +535,7 @@ extern "C" int pat_tv_smooth(int32_t ndim, const int32_t n[3], const float* x, d
   }
   if (value_host) {
     double* buf = nullptr;
-    int rc = red_buffer(&buf);
+    int rc = red_buffer(st, &buf);
     if (rc) return rc;
     hipLaunchKernelGGL(k_red_tv, dim3(kRedBlocks), dim3(kRedThreads), 0, st, g, ndim, x, rho, buf);
     hipLaunchKernelGGL(k_red2, dim3(1), dim3(kRedThreads), 0, st, buf, buf + kRedBlocks);

@@ -10,6 +10,7 @@
 #include <stdint.h>
 
 #include "../../include/pat.h"
+#include "host_plan.h"
 
 namespace pat {
 
@@ -20,25 +21,6 @@ constexpr int TWN = 1024;  // twiddle table length: exp(-2 pi i q / TWN), q < TW
 // that the systematic float32 rounding of the table does not enter the FFT.
 struct alignas(16) Tw {
   float hr, hi, lr, li;
-};
-
-// Linear-interpolation tap of one sensor in one grid row:
-// partial[slot] = w0 * p[row][x0] + w1 * p[row][x0 + 1]
-struct GTap {
-  int32_t x0;
-  int32_t slot;
-  float w0, w1;
-};
-
-// Transposed sensor operator, grouped by node: a row's groups have distinct
-// x, each summing its taps w * h[s] in a fixed order.
-struct SGroup {
-  int32_t x;
-  int32_t beg, end;
-};
-struct STap {
-  int32_t s;
-  float w;
 };
 
 // Everything one instance needs on the device.  Arrays are float32,

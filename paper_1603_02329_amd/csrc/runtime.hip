@@ -21,6 +21,7 @@
 #include <new>
 #include <vector>
 
+#include "host_plan.h"
 #include "pat_internal.h"
 
 namespace pat {
@@ -39,54 +40,6 @@ namespace {
     hipError_t e_ = (x);               \
     if (e_ != hipSuccess) return PAT_EHIP; \
   } while (0)
-
-bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
-
-// In-place iterative radix-2 FFT of length n (a power of two), float64;
-// sign -1 forward, +1 inverse (unnormalised).
-void fft_pow2(std::complex<double>* a, int n, int sign) {
-  for (int i = 1, j = 0; i < n; ++i) {
-    int bit = n >> 1;
-    for (; j & bit; bit >>= 1) j ^= bit;
-    j ^= bit;
-    if (i < j) std::swap(a[i], a[j]);
-  }
-  for (int len = 2; len <= n; len <<= 1) {
-    const double ang = sign * 2.0 * M_PI / len;
-    for (int i = 0; i < n; i += len)
-      for (int k = 0; k < len / 2; ++k) {
-        const std::complex<double> w = std::polar(1.0, ang * k);
-        const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * w;
-        a[i + k] = u + v;
-        a[i + k + len / 2] = u - v;
-      }
-  }
-}
-
-// Spectral smoothing of a medium map (PAT_SMOOTH_MEDIUM): every axis'
-// spectrum multiplied by the Blackman window centred on the zero
-// wavenumber, w(m) = 0.42 + 0.5 cos(2 pi m / n) + 0.08 cos(4 pi m / n),
-// which is 1 at m = 0 and 0 at the Nyquist bin.  The window is a product
-// over the axes, so the filter runs as 1-D passes along each axis.
-void smooth_field(std::vector<double>& f, int nd, const int32_t n[3]) {
-  const int64_t stride[3] = {1, n[0], (int64_t)n[0] * (nd > 1 ? n[1] : 1)};
-  const int64_t N = (int64_t)f.size();
-  for (int j = 0; j < nd; ++j) {
-    const int len = n[j];
-    std::vector<double> w(len);
-    for (int m = 0; m < len; ++m)
-      w[m] = 0.42 + 0.5 * std::cos(2.0 * M_PI * m / len) + 0.08 * std::cos(4.0 * M_PI * m / len);
-    std::vector<std::complex<double>> line(len);
-    for (int64_t base = 0; base < N; ++base) {
-      if ((base / stride[j]) % len != 0) continue;  // one start per line along axis j
-      for (int m = 0; m < len; ++m) line[m] = f[base + m * stride[j]];
-      fft_pow2(line.data(), len, -1);
-      for (int m = 0; m < len; ++m) line[m] *= w[m];
-      fft_pow2(line.data(), len, +1);
-      for (int m = 0; m < len; ++m) f[base + m * stride[j]] = line[m].real() / len;
-    }
-  }
-}
 
 std::mutex g_tw_mu;
 std::vector<int> g_tw_ready;  // per device
@@ -123,126 +76,6 @@ struct Carve {
   }
 };
 
-double pml_factor(int n, int L, double alpha, double c_ref, double dx, double dt, int i, bool stag) {
-  if (L <= 0) return 1.0;
-  const double s = i + (stag ? 0.5 : 0.0);
-  double depth = 0.0;
-  if (s < L) depth = L - s;
-  if (s > (n - 1 - L)) depth = s - (n - 1 - L);
-  const double sigma = alpha * (c_ref / dx) * std::pow(depth / L, 4.0);
-  return std::exp(-sigma * dt / 2.0);
-}
-
-int validate_desc(const pat_desc* d, bool lossy) {
-  if (!d) return PAT_EINVAL;
-  if (d->ndim != 2 && d->ndim != 3) return PAT_EINVAL;
-  for (int j = 0; j < d->ndim; ++j) {
-    const int lim = d->ndim == 3 ? 256 : 1024;
-    if (!is_pow2(d->n[j]) || d->n[j] < 16 || d->n[j] > lim) return PAT_EINVAL;
-    if (!(d->dx[j] > 0) || !std::isfinite(d->dx[j]) || !std::isfinite(d->origin[j])) return PAT_EINVAL;
-    if (d->pml_size[j] < 0 || 2 * d->pml_size[j] >= d->n[j]) return PAT_EINVAL;
-  }
-  if (d->nt < 1) return PAT_EINVAL;
-  if (!std::isfinite(d->dt) || !std::isfinite(d->cfl)) return PAT_EINVAL;
-  if (d->dt <= 0 && !(d->cfl > 0)) return PAT_EINVAL;
-  if (!(d->pml_alpha >= 0) || !std::isfinite(d->pml_alpha)) return PAT_EINVAL;
-  if (lossy && !(d->alpha_power > 0 && d->alpha_power < 3 && d->alpha_power != 1.0)) return PAT_EINVAL;
-  if (d->n_sensors < 1) return PAT_EINVAL;
-  if (d->flags & ~(PAT_NO_PML | PAT_CHECK_FINITE | PAT_SMOOTH_MEDIUM | PAT_SMOOTH_P0)) return PAT_EINVAL;
-  return PAT_OK;
-}
-
-struct SensorOps {
-  std::vector<int32_t> g_ptr, s_ptr, slot_ptr;
-  std::vector<GTap> g_tap;
-  std::vector<SGroup> s_grp;
-  std::vector<STap> s_tap;
-  int nslots = 0;
-};
-
-// Linear-interpolation sensor operator: one gather tap per (sensor, row)
-// with non-zero row weight; the transposed operator grouped by node.
-int build_sensors(const pat_desc& d, const double* pos, SensorOps& so) {
-  const int nd = d.ndim, ns = d.n_sensors;
-  const int nx = d.n[0], ny = d.n[1], nz = nd == 3 ? d.n[2] : 1;
-  const int nrows = ny * nz;
-  struct RowTap {
-    int row, x0, slot, s;
-    double w0, w1;
-  };
-  std::vector<RowTap> taps;
-  so.slot_ptr.assign(ns + 1, 0);
-  int slot = 0;
-  for (int s = 0; s < ns; ++s) {
-    int lo[3] = {0, 0, 0};
-    double fr[3] = {0, 0, 0};
-    for (int j = 0; j < nd; ++j) {
-      const double g = (pos[(size_t)s * nd + j] - d.origin[j]) / d.dx[j];
-      if (!(g >= 0.0) || !(g <= (double)(d.n[j] - 1))) return PAT_EINVAL;
-      const int i0 = std::min((int)std::floor(g), d.n[j] - 2);
-      lo[j] = i0;
-      fr[j] = g - i0;
-    }
-    so.slot_ptr[s] = slot;
-    const int nrow_taps = nd == 3 ? 4 : 2;
-    for (int b = 0; b < nrow_taps; ++b) {
-      const int by = b & 1, bz = (b >> 1) & 1;
-      double w = by ? fr[1] : 1.0 - fr[1];
-      if (nd == 3) w *= bz ? fr[2] : 1.0 - fr[2];
-      if (w == 0.0) continue;
-      const int row = (lo[1] + by) + (nd == 3 ? (lo[2] + bz) * ny : 0);
-      taps.push_back(RowTap{row, lo[0], slot, s, w * (1.0 - fr[0]), w * fr[0]});
-      ++slot;
-    }
-    if (slot == so.slot_ptr[s]) return PAT_EINVAL;  // cannot happen: weights sum to 1
-  }
-  so.slot_ptr[ns] = slot;
-  so.nslots = slot;
-
-  // gather: CSR by row
-  std::stable_sort(taps.begin(), taps.end(), [](const RowTap& a, const RowTap& b) { return a.row < b.row; });
-  so.g_ptr.assign(nrows + 1, 0);
-  so.g_tap.clear();
-  for (const auto& t : taps) {
-    so.g_ptr[t.row + 1]++;
-    so.g_tap.push_back(GTap{t.x0, t.slot, (float)t.w0, (float)t.w1});
-  }
-  for (int r = 0; r < nrows; ++r) so.g_ptr[r + 1] += so.g_ptr[r];
-
-  // scatter: per row, node groups sorted by x, taps by sensor
-  struct NodeTap {
-    int row, x, s;
-    double w;
-  };
-  std::vector<NodeTap> nt;
-  for (const auto& t : taps) {
-    if (t.w0 != 0.0) nt.push_back(NodeTap{t.row, t.x0, t.s, t.w0});
-    if (t.w1 != 0.0) nt.push_back(NodeTap{t.row, t.x0 + 1, t.s, t.w1});
-  }
-  std::sort(nt.begin(), nt.end(), [](const NodeTap& a, const NodeTap& b) {
-    if (a.row != b.row) return a.row < b.row;
-    if (a.x != b.x) return a.x < b.x;
-    return a.s < b.s;
-  });
-  so.s_ptr.assign(nrows + 1, 0);
-  so.s_grp.clear();
-  so.s_tap.clear();
-  for (size_t i = 0; i < nt.size();) {
-    size_t j = i;
-    const int beg = (int)so.s_tap.size();
-    while (j < nt.size() && nt[j].row == nt[i].row && nt[j].x == nt[i].x) {
-      so.s_tap.push_back(STap{nt[j].s, (float)nt[j].w});
-      ++j;
-    }
-    so.s_grp.push_back(SGroup{nt[i].x, beg, (int)so.s_tap.size()});
-    so.s_ptr[nt[i].row + 1]++;
-    i = j;
-  }
-  for (int r = 0; r < nrows; ++r) so.s_ptr[r + 1] += so.s_ptr[r];
-  (void)nx;
-  return PAT_OK;
-}
-
 }  // namespace
 
 // ===================================================================== plan
@@ -271,22 +104,14 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
     if (!(c0[i] > 0) || !std::isfinite(c0[i]) || !(rho0[i] > 0) || !std::isfinite(rho0[i])) return PAT_EINVAL;
     if (lossy && (!(a0db[i] >= 0) || !std::isfinite(a0db[i]))) return PAT_EINVAL;
   }
-  // the medium in float64, spectrally smoothed on request (the sound speed
-  // and density maps, as the paper's models were run on smoothed maps)
   std::vector<double> cd(c0.begin(), c0.end()), rd(rho0.begin(), rho0.end());
-  if (d.flags & PAT_SMOOTH_MEDIUM) {
-    smooth_field(cd, nd, d.n);
-    smooth_field(rd, nd, d.n);
-  }
   double cmax = 0;
   for (int64_t i = 0; i < N; ++i) {
     if (!(cd[i] > 0) || !(rd[i] > 0)) return PAT_EINVAL;
     cmax = std::max(cmax, cd[i]);
   }
-  double dxmin = d.dx[0];
-  for (int j = 1; j < nd; ++j) dxmin = std::min(dxmin, d.dx[j]);
-  const double dt = d.dt > 0 ? d.dt : d.cfl * dxmin / cmax;
-  if (cmax * dt / dxmin > (1.0 / std::sqrt((double)nd)) * (1.0 + 1e-12)) return PAT_EUNSTABLE;
+  const double dt = plan_dt(d, cmax);
+  if ((rc = check_stability(d, cmax, dt))) return rc;
 
   SensorOps so;
   if ((rc = build_sensors(d, sensor_pos, so))) return rc;
@@ -393,13 +218,14 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
       }
     }
   }
-  PAT_TRY_HIP(hipMemcpyAsync(A, hbuf.data(), state_begin, hipMemcpyHostToDevice, st));
+  // from here on every error path releases the arena and the plan
+  rc = hipMemcpyAsync(A, hbuf.data(), state_begin, hipMemcpyHostToDevice, st) == hipSuccess ? PAT_OK : PAT_EHIP;
 
   auto up = [&](size_t off, const void* src, size_t bytes) -> int {
     if (bytes == 0) return PAT_OK;
     return hipMemcpyAsync(A + off, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess ? PAT_OK : PAT_EHIP;
   };
-  rc = up(o_gptr, so.g_ptr.data(), so.g_ptr.size() * 4);
+  if (!rc) rc = up(o_gptr, so.g_ptr.data(), so.g_ptr.size() * 4);
   if (!rc) rc = up(o_gtap, so.g_tap.data(), so.g_tap.size() * sizeof(GTap));
   if (!rc) rc = up(o_sptr, so.s_ptr.data(), so.s_ptr.size() * 4);
   if (!rc) rc = up(o_sgrp, so.s_grp.data(), so.s_grp.size() * sizeof(SGroup));
@@ -469,6 +295,7 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
   if (!rc) rc = up(o_rec, &h, sizeof(DevPlan));
   if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = PAT_EHIP;
   if (rc) {
+    hipStreamSynchronize(st);  // no copy may still read the host tables or write the arena
     hipFree(p->arena);
     delete p;
     return rc;

@@ -15,8 +15,10 @@ comes from the GPU library.  For each case the file holds:
 Usage:  python tests/golden/make_golden.py [case ...]   (default: all)
 Cases: cfg2, cfg3f, cfg3c, cfg4_<i> (i = 0, 1, 16, 17, 32, 33), cfg5, and
 cfg4_short: all 48 instances of the batch workload with the time axis cut to
-a tenth (60 / 120 / 240 samples), one file with arrays per instance
-(``data_<i>``, ``img_<i>``; sensors every 8th, voxels on a stride-8 lattice).
+a third (200 / 400 / 800 samples: long enough for the wave to cross each
+instance's sensor arc, so that every record carries its phantom's signal),
+one file with arrays per instance (``data_<i>``, ``img_<i>``; sensors every
+8th, voxels on a stride-8 lattice).
 """
 from __future__ import annotations
 
@@ -82,31 +84,50 @@ def make(case: str, workers: int) -> None:
     print(f"{case}: {time.time() - t0:.1f} s -> {out} ({os.path.getsize(out) / 1e6:.2f} MB)", flush=True)
 
 
+SHORT_DIV = 3  # time axes of the cfg4_short case: N_t / SHORT_DIV
+
+
 def short_instances():
-    """The 48 batch instances with N_t cut to a tenth."""
+    """The 48 batch instances with N_t cut to a third."""
     from dataclasses import replace
-    return [synth.Instance(replace(i.desc, nt=i.desc.nt // 10), i.c0, i.rho0, i.alpha0_db, i.sensors, i.p0, i.name)
-            for i in synth.config4()]
+    return [synth.Instance(replace(i.desc, nt=i.desc.nt // SHORT_DIV), i.c0, i.rho0, i.alpha0_db, i.sensors, i.p0,
+                           i.name) for i in synth.config4()]
+
+
+_SHORT = None
+
+
+def _short_one(args):
+    global _SHORT
+    k, workers = args
+    K.WORKERS = workers
+    if _SHORT is None:  # once per worker process
+        _SHORT = short_instances()
+    inst = _SHORT[k]
+    op = K.make_plan(inst.desc, inst.c0, inst.rho0, inst.alpha0_db, inst.sensors)
+    data = K.forward(op, inst.p0)
+    seed, h = h_for(f"cfg4_short_{k}", inst)
+    img = K.adjoint(op, h)
+    sidx = np.arange(0, inst.ns, 8)
+    iidx = np.arange(int(np.prod(inst.desc.shape))).reshape(inst.desc.shape)[::8, ::8].ravel()
+    return k, {f"data_{k}": data[:, sidx].astype(np.float32), f"sensor_idx_{k}": sidx.astype(np.int32),
+               f"h_seed_{k}": np.int64(seed), f"img_{k}": img.ravel()[iidx].astype(np.float32),
+               f"img_idx_{k}": iidx.astype(np.int64), f"nt_{k}": np.int64(inst.desc.nt)}
 
 
 def make_short(workers: int) -> None:
-    K.WORKERS = workers
+    """The 48 instances in a pool of processes (ORACLE_PROCS, default 1),
+    each running the oracle with `workers` FFT threads."""
+    from concurrent.futures import ProcessPoolExecutor
+    procs = int(os.environ.get("ORACLE_PROCS", "1"))
     t0 = time.time()
     out = {}
-    for k, inst in enumerate(short_instances()):
-        op = K.make_plan(inst.desc, inst.c0, inst.rho0, inst.alpha0_db, inst.sensors)
-        data = K.forward(op, inst.p0)
-        seed, h = h_for(f"cfg4_short_{k}", inst)
-        img = K.adjoint(op, h)
-        sidx = np.arange(0, inst.ns, 8)
-        iidx = np.arange(int(np.prod(inst.desc.shape))).reshape(inst.desc.shape)[::8, ::8].ravel()
-        out[f"data_{k}"] = data[:, sidx].astype(np.float32)
-        out[f"sensor_idx_{k}"] = sidx.astype(np.int32)
-        out[f"h_seed_{k}"] = np.int64(seed)
-        out[f"img_{k}"] = img.ravel()[iidx].astype(np.float32)
-        out[f"img_idx_{k}"] = iidx.astype(np.int64)
-        out[f"nt_{k}"] = np.int64(inst.desc.nt)
-        print(f"cfg4_short {k}: {time.time() - t0:.1f} s", flush=True)
+    sizes = [int(np.prod(i.desc.shape)) for i in short_instances()]
+    order = sorted(range(len(sizes)), key=lambda k: -sizes[k])  # largest first
+    with ProcessPoolExecutor(procs) as ex:
+        for k, arrs in ex.map(_short_one, [(k, workers) for k in order]):
+            out.update(arrs)
+            print(f"cfg4_short {k}: {time.time() - t0:.1f} s", flush=True)
     path = os.path.join(HERE, "cfg4_short.npz")
     np.savez_compressed(path, **out)
     print(f"cfg4_short -> {path} ({os.path.getsize(path) / 1e6:.2f} MB)", flush=True)

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 def test_strerror_codes():
     L = pat.lib()
     for code in range(7):
-        assert L.pat_strerror(code)
+        assert L.pat_strerror(code) and L.pat_strerror(code) != b"unknown error"
     assert L.pat_strerror(99) == b"unknown error"
 
 
@@ -127,3 +127,59 @@ def test_batch_entry_points_validate_on_host():
     assert L.pat_tuning_report(None, None, 0, ctypes.byref(need)) == pat.PAT_EINVAL
     n = (ctypes.c_int32 * 3)(16, 16, 1)
     assert L.pat_batch_set_tile(None, n, 1, 1, 0, 0, 16, 1) == pat.PAT_EINVAL
+
+
+def _check_desc(desc, sensors, c_max, lossy=True):
+    L = pat.lib()
+    import numpy as np
+    pos = np.ascontiguousarray(np.asarray(sensors, dtype=np.float64))
+    cd = pat.make_desc(desc, pos.shape[0])
+    return L.pat_desc_check(ctypes.byref(cd), 1 if lossy else 0, pos.ctypes.data_as(ctypes.c_void_p), c_max)
+
+
+def test_desc_check_stability_bound():
+    """PAT_EUNSTABLE above c_max dt / min dx = 1/sqrt(d), on the host, for an
+    explicit dt and for the CFL rule; exactly at the bound is accepted."""
+    import math
+    from dataclasses import replace
+
+    import synth
+    for n in ((16, 16), (16, 16, 16)):
+        inst = synth.small_instance(3, n, nt=4)
+        d = inst.desc
+        nd = len(n)
+        dx = d.dx[0]
+        c = 1600.0
+        bound = dx / (c * math.sqrt(nd))
+        assert _check_desc(replace(d, dt=0.99 * bound), inst.sensors, c) == pat.PAT_OK
+        assert _check_desc(replace(d, dt=bound), inst.sensors, c) == pat.PAT_OK
+        assert _check_desc(replace(d, dt=1.01 * bound), inst.sensors, c) == pat.PAT_EUNSTABLE
+        assert _check_desc(replace(d, dt=0.0, cfl=0.3), inst.sensors, c) == pat.PAT_OK
+        assert _check_desc(replace(d, dt=0.0, cfl=1.02 / math.sqrt(nd)), inst.sensors, c) == pat.PAT_EUNSTABLE
+        # c_max <= 0: the stability check is skipped
+        assert _check_desc(replace(d, dt=10 * bound), inst.sensors, 0.0) == pat.PAT_OK
+        assert _check_desc(replace(d, dt=bound), inst.sensors, float("inf")) == pat.PAT_EINVAL
+
+
+def test_desc_check_rejects_sensors_outside_the_grid():
+    """Every grid coordinate (pos - origin)/dx must lie in [0, n - 1]: the
+    edges themselves are accepted, a step beyond either edge, a NaN or an
+    infinite coordinate is PAT_EINVAL, on every axis, 2D and 3D."""
+    import numpy as np
+
+    import synth
+    for n in ((16, 32), (16, 16, 32)):
+        inst = synth.small_instance(4, n, nt=4, ns=3)
+        d = inst.desc
+        nd = len(n)
+        assert _check_desc(d, inst.sensors, 1500.0) == pat.PAT_OK
+        for j in range(nd):
+            lo = d.origin[j]
+            hi = d.origin[j] + (d.n[j] - 1) * d.dx[j]
+            for v, ok in ((lo, True), (hi, True), (lo - 1e-3 * d.dx[j], False), (hi + 1e-3 * d.dx[j], False),
+                          (float("nan"), False), (float("inf"), False)):
+                s = np.array(inst.sensors, dtype=np.float64)
+                s[1, j] = v
+                rc = _check_desc(d, s, 1500.0)
+                assert rc == (pat.PAT_OK if ok else pat.PAT_EINVAL), (n, j, v, rc)
+    assert pat.lib().pat_desc_check(ctypes.byref(pat.make_desc(inst.desc, 3)), 1, None, 1500.0) == pat.PAT_EINVAL

@@ -94,24 +94,14 @@ def test_fullsize_batch48():
 
 
 def test_batch48_short_all_instances():
-    """All 48 instances with the time axis cut to a tenth, through the
-    batched executor (default grouping, graph chunks of 64 steps, autotuned
-    column variants), each checked against the oracle.
-
-    With a tenth of the time axis the wave from many phantoms has not yet
-    reached the sampled sensors (most 512^2 instances: 240 steps carry a wave
-    about 72 points, the sensor arc is 228 points from the centre): their
-    reference data are dispersion tails up to a thousand times weaker than
-    the records where the wave has arrived (norms 1e-3 against 0.5-1.5).  The
-    GPU's error is float32 rounding of the whole wave field, about 2e-6 in
-    norm whatever the record's own strength, so a record's relative error
-    measures how early its sensors are rather than the operator.  The
-    forward error is therefore taken relative to the largest record of the
-    instance's size class (the data scale of the workload); every adjoint
-    image (a full-field quantity) is checked relative to itself."""
+    """All 48 instances with the time axis cut to a third (200 / 400 / 800
+    samples: the wave crosses each instance's sensor arc within that time),
+    through the batched executor (default grouping, graph chunks of 64
+    steps, autotuned column variants), each forward record set and each
+    adjoint image checked against the oracle relative to its own norm."""
     from dataclasses import replace
     g = _load("cfg4_short")
-    insts = [synth.Instance(replace(i.desc, nt=i.desc.nt // 10), i.c0, i.rho0, i.alpha0_db, i.sensors, i.p0, i.name)
+    insts = [synth.Instance(replace(i.desc, nt=i.desc.nt // 3), i.c0, i.rho0, i.alpha0_db, i.sensors, i.p0, i.name)
              for i in synth.config4()]
     plans = [pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=DEV) for i in insts]
     batch = pat.Batch(plans)
@@ -123,16 +113,43 @@ def test_batch48_short_all_instances():
         (inst.desc.nt, inst.ns)).astype(np.float32)).to(DEV) for k, inst in enumerate(insts)]
     imgs = batch.adjoint(hs)
     torch.cuda.synchronize()
-    worst = 0.0
-    norms = [float(np.linalg.norm(g[f"data_{k}"])) for k in range(len(insts))]
+    worst = (0.0, -1, "")
     for k, inst in enumerate(insts):
         assert int(g[f"nt_{k}"]) == inst.desc.nt
-        ref = g[f"data_{k}"]
-        big = max(norms[j] for j in range(len(insts)) if insts[j].desc.n == inst.desc.n)
-        err = np.linalg.norm(datas[k].cpu().numpy()[:, g[f"sensor_idx_{k}"]].astype(np.float64) - ref)
-        ed = float(err / big)
+        ed = _rel(datas[k].cpu().numpy()[:, g[f"sensor_idx_{k}"]], g[f"data_{k}"])
         ei = _rel(imgs[k].cpu().numpy().ravel()[g[f"img_idx_{k}"]], g[f"img_{k}"])
-        worst = max(worst, ed, ei)
+        for e, what in ((ed, "forward"), (ei, "adjoint")):
+            if e > worst[0]:
+                worst = (e, k, what)
         assert ed <= TOL and ei <= TOL, (k, ed, ei)
-    print(f"cfg4_short: worst rel-L2 over 48 instances {worst:.3e}", flush=True)
+    print(f"cfg4_short: worst rel-L2 over 48 instances {worst[0]:.3e} (instance {worst[1]}, {worst[2]})",
+          flush=True)
     batch.close()
+
+
+def test_cfg5_autograd_with_checkpoints():
+    """The 128^3 workload through torch.autograd with the forward run in
+    checkpointed segments of 50 steps: the segmented forward equals the
+    one-piece pat_forward bitwise and matches the oracle on the stored
+    sensors; the backward of <H p0, h> (h the stored seeded data) is H^T h
+    and matches the oracle adjoint on the stored voxels."""
+    from paper_1603_02329_amd.autograd import PatOperator, replay_segment
+    g = _load("cfg5")
+    inst = synth.config5()
+    plan = pat.Plan(inst.desc, inst.c0, inst.rho0, inst.alpha0_db, inst.sensors, device=DEV)
+    x = torch.from_numpy(inst.p0).to(DEV).requires_grad_(True)
+    h = torch.from_numpy(_h(g, inst)).to(DEV)
+    plain = plan.forward(x.detach()).clone()
+    with torch.enable_grad():
+        d = PatOperator.apply(x, plan, 50)
+        loss = (d.double() * h.double()).sum()
+    assert torch.equal(d, plain)
+    loss.backward()
+    torch.cuda.synchronize()
+    _check("cfg5 autograd/ckpt50", inst, d.detach().cpu().numpy(), x.grad.cpu().numpy(), g)
+    assert torch.equal(x.grad, plan.adjoint(h))
+    # a segment replayed from the snapshot at 750 is bitwise the recorded one
+    ckpts = d.grad_fn.checkpoints  # the snapshots the Function kept on its context
+    assert [n for n, _ in ckpts] == list(range(50, 800, 50))
+    seg = replay_segment(plan, ckpts, x.detach(), 760, 800)
+    assert torch.equal(seg, plain[760:800])
