@@ -113,6 +113,18 @@ def step_traffic():
     return float(fields["traffic_bytes_per_gps"]) if fields and "traffic_bytes_per_gps" in fields else None
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo), or the platform string."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(insts, seconds_target=15.0):
     """The FP64 oracle on a bounded sample: one instance of each grid size,
     a shortened time axis, forward + adjoint."""
@@ -147,6 +159,7 @@ def cpu_baseline(insts, seconds_target=15.0):
     t1 = time.perf_counter() - t0
     K.WORKERS = cores
     return {"value": gps / t_total, "unit": "grid-point-steps/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "cpu_count": os.cpu_count(),
             "sample": f"FP64 oracle forward+adjoint of one instance per size ({sizes}) with N_t={nts} "
                       f"instead of the full time axis; {t_total:.1f} s on {cores} threads (scipy.fft workers)",
             "single_core": {"value": 2.0 * small.desc.npoints * nts / t1, "unit": "grid-point-steps/s",
@@ -161,6 +174,7 @@ def main():
     ap.add_argument("--workload", default="cfg4")
     ap.add_argument("--chunk", type=int, default=64, help="graph chunk (steps per captured graph; 1 = eager)")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=3, help="timed steps of the plain path (after 1 warm-up)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default column tile widths")
     ap.add_argument("--parts", type=int, default=0, help="groups per size class (0: the library default)")
@@ -261,6 +275,27 @@ def main():
         f"{k_bytes / (k_ms / 1e3) / 1e9:.0f} GB/s")
     if args.roofline_only:
         return
+
+    def every_pass(reps=50):
+        """Every pass of a forward and an adjoint step timed on its own the
+        same way, the column passes in the widths the autotuner picks for
+        this one-stream batch (after the roofline phase, untimed for the
+        benchmark): {(dir, pass): (us per launch, algorithmic bytes per
+        launch)}."""
+        out = {}
+        b1 = pat.Batch(plans, chunk=1, parts=1, lanes=1)
+        b1.autotune(reps=10)  # the column passes in their tuned launch shapes
+        for d in (0, 1):
+            for k in range(16):
+                try:
+                    b1.time_pass(d, k, nx_dom, 10)
+                    out[(d, k)] = b1.time_pass(d, k, nx_dom, reps)
+                except pat.PatError:
+                    continue  # no such pass (or not timeable alone)
+        b1.close()
+        return out
+
+    pass_times = every_pass() if ndim == 2 else {}
     batch = pat.Batch(plans, chunk=args.chunk, parts=args.parts, lanes=args.lanes)
     targets = [d.clone() for d in batch.forward(x_true)]
     tiles = []
@@ -299,32 +334,37 @@ def main():
         return sum(PatLeastSquares.apply(x, t, p) for x, t, p in zip(leaves, targets, plans))
 
     def timed(fns, steps, warmup, label):
+        """Mean ms per step over `steps` steps between two synchronisations
+        (the value the benchmark reports), and the per-step times from HIP
+        events between the steps (their median is reported beside it)."""
         for _ in range(warmup):
             step(fns)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         t0 = time.perf_counter()
-        e0.record()
-        for _ in range(steps):
+        evs[0].record()
+        for i in range(steps):
             step(fns)
-        e1.record()
+            evs[i + 1].record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        ms = e0.elapsed_time(e1) / steps
-        log(f"{label}: {ms:.1f} ms/step (host wall {wall / steps * 1e3:.1f} ms/step), "
+        per = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+        ms = evs[0].elapsed_time(evs[steps]) / steps
+        med = float(np.median(per))
+        log(f"{label}: {ms:.1f} ms/step (median {med:.1f}, host wall {wall / steps * 1e3:.1f} ms/step), "
             f"{total_gps / (ms / 1e3) / 1e9:.2f} G gps/s")
-        return ms
+        return ms, med, per
 
 
     # main timed region: the batched executor (graph-captured chunks; the
     # steps left over by the chunking run eagerly between the chunks and
     # are event-timed there, sharing the GPU with the other streams)
     pat.timing_begin(tdir, tidx, nx_dom)
-    ms = timed(batched, args.steps, args.warmup, f"batched(chunk={args.chunk})")
+    ms, ms_med, ms_all = timed(batched, args.steps, args.warmup, f"batched(chunk={args.chunk})")
     s_ms, s_n, s_bytes = pat.timing_end()
-    plain_ms = None
+    plain_ms = plain_med = None
     if not args.no_plain:
-        plain_ms = timed(plain, 1, 0, "plain (one instance at a time, eager)")
+        plain_ms, plain_med, _ = timed(plain, args.plain_steps, 1, "plain (one instance at a time, eager)")
     value = total_gps / (ms / 1e3)
     achieved = k_bytes / (k_ms / 1e3) / 1e9 if k_ms > 0 else 0.0
     names = {(0, 0): "col gradient", (0, 1): "row velocity", (0, 2): "col divergence", (0, 3): "row density",
@@ -333,6 +373,56 @@ def main():
              (1, 4): "row adj-velocity", (1, 5): "col adj-divergence"}
     if ndim == 3:
         names = {(0, 3): "row velocity", (0, 7): "row density", (0, 11): "row state+gather"}
+    step_bytes = value * b_alg / 1e9  # algorithmic GB/s of the whole step
+    st_bpg = step_traffic() if args.workload == "cfg4" else None
+    dom_name = names.get((tdir, tidx), f"{tdir}:{tidx}")
+    dominant = {
+        "kernel": dom_name,
+        "kernel_symbol": row_kernel_name(plans, 1) if dom_name == "row velocity" else None,
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": counter_traffic(row_kernel_name(plans, 1)) if dom_name == "row velocity" else None,
+        "launches": k_n,
+        "avg_launch_us": (k_ms / k_n * 1e3) if k_n else None,
+        "measured_in": "back-to-back launches of the pass over a one-stream batch before the timed region, "
+                       "after an untimed burst of 100 (each launch: " +
+                       ("every instance of the batch, its size classes fused" if fused_batch(plans)
+                        else "every instance of the largest size") + "; GPU to itself)",
+        "in_timed_region": {
+            "launches": s_n,
+            "avg_launch_us": (s_ms / s_n * 1e3) if s_n else None,
+            "achieved": (s_bytes / (s_ms / 1e3) / 1e9) if s_ms > 0 else None,
+            "note": "eager steps between graph chunks, concurrent with the other streams' passes",
+        },
+    }
+    passes = {}
+    for (d, k), (us, by) in sorted(pass_times.items()):
+        gbs = by / us * 1e-3
+        passes[names.get((d, k), f"{d}:{k}")] = {"avg_launch_us": us, "achieved": gbs,
+                                                  "frac": gbs / HBM_PEAK_GBS, "bytes_per_launch": by}
+    cols = {k: v for k, v in passes.items() if k.startswith("col")}
+    worst_col = min(cols.items(), key=lambda kv: kv[1]["frac"]) if cols else None
+    roofline = {
+        # headline: the whole gradient step (forward + adjoint of every
+        # instance, all passes, both streams) against the algorithmic bytes
+        # per grid-point-step
+        "bound": "hbm",
+        "kernel": "whole step: batched forward + adjoint, every pass of every instance",
+        "achieved": step_bytes,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": step_bytes / HBM_PEAK_GBS,
+        "bytes_per_gps": b_alg,
+        "traffic": (st_bpg * total_gps) if st_bpg else None,
+        "traffic_bytes_per_gps": st_bpg,
+        "target_frac": 0.60,
+        "target_met": step_bytes / HBM_PEAK_GBS >= 0.60,
+        "dominant_kernel": dominant,
+        "worst_column_pass": ({"pass": worst_col[0], **worst_col[1]} if worst_col else None),
+        "passes_isolated": passes,
+    }
     out = {
         "metric": METRIC,
         "value": value,
@@ -355,35 +445,14 @@ def main():
             "col_tiles": {f"{e['n'][0]}x{e['n'][1]}x{e['n'][2]}:{e['dir']}:{e['pass']}": e["tile"] for e in tiles},
             "col_tile_policy": (tiles[0].get("policy") if tiles else None),
             "col_tile_policy_us": (tiles[0].get("policy_us") if tiles else None),
+            "ms_per_step_median": ms_med,
+            "ms_per_step_all": ms_all,
             "plain_ms_per_step": plain_ms,
+            "plain_ms_per_step_median": plain_med,
+            "plain_steps": (args.plain_steps if plain_ms else None),
             "batched_over_plain": (plain_ms / ms) if plain_ms else None,
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": names.get((tdir, tidx), f"{tdir}:{tidx}"),
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "kernel_symbol": row_kernel_name(plans, 1) if names.get((tdir, tidx)) == "row velocity" else None,
-            "traffic": (counter_traffic(row_kernel_name(plans, 1)) if names.get((tdir, tidx)) == "row velocity"
-                        else None),
-            "launches": k_n,
-            "avg_launch_us": (k_ms / k_n * 1e3) if k_n else None,
-            "measured_in": "back-to-back launches of the pass over a one-stream batch before the timed "
-                           "region, after an untimed burst of 100 (each launch: " + ("every instance of the batch, its size classes fused"
-                                                      if fused_batch(plans) else "every instance of the largest "
-                                                      "size") + "; GPU to itself)",
-            "in_timed_region": {
-                "launches": s_n,
-                "avg_launch_us": (s_ms / s_n * 1e3) if s_n else None,
-                "achieved": (s_bytes / (s_ms / 1e3) / 1e9) if s_ms > 0 else None,
-                "note": "eager steps between graph chunks, concurrent with the other streams' passes",
-            },
-            "step_frac": value * b_alg / (HBM_PEAK_GBS * 1e9),
-            "bytes_per_gps": b_alg,
-            "step_traffic_bytes_per_gps": step_traffic() if args.workload == "cfg4" else None,
-        },
+        "roofline": roofline,
     }
     if not args.no_cpu:
         log("timing the FP64 oracle on a bounded sample ...")
