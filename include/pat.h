@@ -39,6 +39,7 @@ extern "C" {
 #define PAT_EHIP        4  /* a HIP runtime call failed                           */
 #define PAT_ENONFINITE  5  /* a non-finite pressure was seen (PAT_CHECK_FINITE)   */
 #define PAT_ENOSYS      6  /* combination not supported by this library           */
+#define PAT_ETOOBIG     7  /* larger than the fixed scratch of pat_tv_prox_noalloc */
 
 /* ------------------------------------------------------------------ flags */
 #define PAT_NO_PML        0x1u  /* switch the PML off: periodic grid             */
@@ -367,6 +368,30 @@ int pat_batch_set_tile(pat_batch* batch, const int32_t n[3], int32_t nt, int32_t
  *  work        device scratch of at least pat_tv_prox_work_bytes(ndim, n) bytes.
  */
 size_t pat_tv_prox_work_bytes(int32_t ndim, const int32_t n[3]);
+
+/*
+ * pat_tv_prox_noalloc -- pat_tv_prox without a workspace argument and
+ * without any allocation, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, arithmetic and result as pat_tv_prox (bitwise
+ * equal), except that the FGP workspace is a fixed array in the library's
+ * device memory instead of `work`:
+ *   PAT_TV_PROX_NOALLOC_FLOATS floats (16 MiB) per device, held by every GPU
+ *   the library runs on until the process ends.  (2 ndim + 1) * N must not
+ *   exceed it (2D up to 838,860 points, e.g. 1024 x 512; 3D up to 599,186,
+ *   e.g. 128 x 128 x 32); larger grids return PAT_ETOOBIG before anything
+ *   is enqueued.
+ * Every call on one GPU uses that GPU's one array: calls that overlap on a
+ * GPU (two streams, or two host threads) race on it and give wrong results;
+ * serialise them (one stream, or events).  The call clears the part of the
+ * array it reads before writing it (a fill kernel, no hipMemset), so the
+ * array's contents from an earlier call never matter.  Enqueues kernels
+ * only: nothing synchronises, so the call can be captured into a graph.
+ * Errors: PAT_EINVAL as pat_tv_prox, PAT_ETOOBIG, PAT_EHIP.
+ */
+#define PAT_TV_PROX_NOALLOC_FLOATS (1L << 22)
+int pat_tv_prox_noalloc(int32_t ndim, const int32_t n[3], const float* z, float* x, double lambda_eff,
+                        int32_t n_iter, const float* lower, void* stream);
 int pat_tv_prox(int32_t ndim, const int32_t n[3], const float* z, float* x, double lambda_eff,
                 int32_t n_iter, const float* lower, void* work, size_t work_bytes, void* stream);
 /*

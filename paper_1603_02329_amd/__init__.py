@@ -22,7 +22,7 @@ __all__ = ["lib", "PatError", "Plan", "Batch", "tv_prox", "restrict", "prolong",
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpat.so")
 
-PAT_OK, PAT_EINVAL, PAT_EUNSTABLE, PAT_ENOMEM, PAT_EHIP, PAT_ENONFINITE, PAT_ENOSYS = range(7)
+PAT_OK, PAT_EINVAL, PAT_EUNSTABLE, PAT_ENOMEM, PAT_EHIP, PAT_ENONFINITE, PAT_ENOSYS, PAT_ETOOBIG = range(8)
 PAT_NO_PML = 0x1
 PAT_CHECK_FINITE = 0x2
 PAT_SMOOTH_P0 = 0x8
@@ -38,7 +38,7 @@ EXPORTED = [
     "pat_dot_f64", "pat_residual_f64", "pat_plan_sync", "pat_strerror", "pat_timing_begin",
     "pat_timing_end", "pat_batch_autotune", "pat_tuning_report", "pat_batch_set_tile", "pat_batch_time_pass",
     "pat_tv_smooth", "pat_restrict_lower", "pat_axpby", "pat_project", "pat_forward_batched",
-    "pat_adjoint_batched", "pat_desc_check",
+    "pat_adjoint_batched", "pat_desc_check", "pat_tv_prox_noalloc",
 ]
 
 
@@ -97,6 +97,7 @@ def lib() -> ctypes.CDLL:
         "pat_adjoint_batched": (ctypes.c_int, [pp, i32, pp, pp, vp]),
         "pat_tv_prox_work_bytes": (sz, [i32, ctypes.POINTER(i32)]),
         "pat_tv_prox": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, f64, i32, vp, vp, sz, vp]),
+        "pat_tv_prox_noalloc": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, f64, i32, vp, vp]),
         "pat_tv_prox_batched": (ctypes.c_int, [i32, i32, ctypes.POINTER(i32), pp, pp, ctypes.POINTER(f64), i32, pp,
                                                pp, ctypes.POINTER(sz), vp]),
         "pat_restrict": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, vp]),

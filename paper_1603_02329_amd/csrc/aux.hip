@@ -455,6 +455,30 @@ int tv_prox_run(const Grid3& g, int ndim, const float* z, float* x, double lambd
   return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
 }
 
+// Workspace of pat_tv_prox_noalloc: one copy per device, held until the
+// process ends.  Host code never passes the array's name to a kernel; it
+// uses the device address hipGetSymbolAddress returns for the current
+// device (noalloc_scratch()).
+constexpr long kNoallocFloats = PAT_TV_PROX_NOALLOC_FLOATS;
+static __device__ __align__(256) float scratch[kNoallocFloats];
+
+std::mutex g_scratch_mu;
+std::vector<float*> g_scratch_ptr;  // per device: address of `scratch`
+
+int noalloc_scratch(float** out) {
+  int dev = 0;
+  PAT_TRY_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PAT_EHIP;
+    g_scratch_ptr[dev] = (float*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PAT_OK;
+}
+
 }  // namespace
 
 extern "C" int pat_tv_prox(int32_t ndim, const int32_t n[3], const float* z, float* x, double lambda_eff,
@@ -464,6 +488,18 @@ extern "C" int pat_tv_prox(int32_t ndim, const int32_t n[3], const float* z, flo
   if (!z || !x || z == x || !(lambda_eff >= 0) || !std::isfinite(lambda_eff) || n_iter < 0) return PAT_EINVAL;
   if (lambda_eff != 0.0 && n_iter != 0 && (!work || work_bytes < pat_tv_prox_work_bytes(ndim, n))) return PAT_EINVAL;
   return tv_prox_run(g, ndim, z, x, lambda_eff, n_iter, lower, (float*)work, (hipStream_t)stream);
+}
+
+extern "C" int pat_tv_prox_noalloc(int32_t ndim, const int32_t n[3], const float* z, float* x, double lambda_eff,
+                                   int32_t n_iter, const float* lower, void* stream) {
+  Grid3 g;
+  if (make_grid(ndim, n, g)) return PAT_EINVAL;
+  if (!z || !x || z == x || !(lambda_eff >= 0) || !std::isfinite(lambda_eff) || n_iter < 0) return PAT_EINVAL;
+  if ((long)(2 * ndim + 1) * g.N > kNoallocFloats) return PAT_ETOOBIG;
+  float* work = nullptr;
+  const int rc = noalloc_scratch(&work);
+  if (rc) return rc;
+  return tv_prox_run(g, ndim, z, x, lambda_eff, n_iter, lower, work, (hipStream_t)stream);
 }
 
 extern "C" int pat_restrict(int32_t ndim, const int32_t n_fine[3], const float* fine, float* coarse, void* stream) {

@@ -345,6 +345,7 @@ extern "C" const char* pat_strerror(int code) {
     case PAT_EHIP: return "HIP runtime error";
     case PAT_ENONFINITE: return "non-finite pressure produced";
     case PAT_ENOSYS: return "not supported by this library";
+    case PAT_ETOOBIG: return "larger than the fixed scratch of the no-allocation entry point";
   }
   return "unknown error";
 }

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_strerror_codes():
     L = pat.lib()
-    for code in range(7):
+    for code in range(8):
         assert L.pat_strerror(code) and L.pat_strerror(code) != b"unknown error"
     assert L.pat_strerror(99) == b"unknown error"
 
