@@ -826,17 +826,26 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
     // of that instance left in that XCD's L2.
     const int ninst = (int)c.plans.size();
     // runs of up to eight instances of one grid shape (a fused group lists
-    // its instances by shape); tiles_of(instance) work items each
+    // its instances by shape, largest grid first); tiles_of(instance) work
+    // items each.  The runs enter the table in reverse, smallest grid first:
+    // blocks are dispatched in table order, so the small instances' blocks
+    // start first and finish under the large grid's blocks instead of
+    // forming the tail of the launch.
     auto interleave = [&](std::vector<int2>& tab, auto tiles_of) {
+      std::vector<std::pair<int, int>> runs;  // (first instance, count)
       for (int g0 = 0; g0 < ninst;) {
         int gn = 1;
         while (g0 + gn < ninst && gn < kXcds && c.plans[g0 + gn]->hp.n[0] == c.plans[g0]->hp.n[0] &&
                c.plans[g0 + gn]->hp.n[1] == c.plans[g0]->hp.n[1])
           ++gn;
+        runs.emplace_back(g0, gn);
+        g0 += gn;
+      }
+      for (auto r = runs.rbegin(); r != runs.rend(); ++r) {
+        const int g0 = r->first, gn = r->second;
         const int tiles = tiles_of(c.plans[g0]);
         for (int t = 0; t < tiles; ++t)
           for (int l = 0; l < gn; ++l) tab.push_back(make_int2(g0 + l, t));
-        g0 += gn;
       }
     };
     if (c.fused) {
