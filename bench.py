@@ -187,6 +187,9 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="counter probe: a 1 GiB device copy (calibration) and a burst of the roofline "
                          "phase's launches; run under rocprofv3 --pmc")
+    ap.add_argument("--sync-probe", action="store_true",
+                    help="diagnostic: cost of a grid-wide barrier in a cooperative launch against a kernel "
+                         "boundary (stream and graph), for several grid sizes and amounts of work; no JSON line")
     ap.add_argument("--pmc-step", action="store_true",
                     help="counter probe of a whole step: the calibration copy, then one forward and one "
                          "adjoint of the workload with the time axes cut to a tenth, every pass launched "
@@ -202,6 +205,23 @@ def main():
 
     import paper_1603_02329_amd as pat
     dev = torch.device("cuda:0")
+    if args.sync_probe:
+        import ctypes
+        L = pat.lib()
+        torch.zeros(1, device=dev)
+        print("blocks/CU  floats/block  cg grid sync (us/iter)  atomic barrier (us/iter)  stream launch (us)  "
+              "graph launch (us)")
+        for bpc in (1, 2, 4):
+            for fpb in (0, 2048, 16384):
+                g, at, st, gr = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+                rc = L.pat_diag_sync_costs(bpc, fpb, 1000, ctypes.byref(g), ctypes.byref(at), ctypes.byref(st),
+                                           ctypes.byref(gr))
+                if rc:
+                    print(f"{bpc:9d}  {fpb:12d}  error {rc}")
+                    continue
+                print(f"{bpc:9d}  {fpb:12d}  {g.value:22.2f}  {at.value:24.2f}  {st.value:18.2f}  {gr.value:17.2f}",
+                      flush=True)
+        return
     insts, wl_name = workload(args.workload)
     if args.pmc_step:
         # the same instances with a tenth of their time axes: the size

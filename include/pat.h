@@ -512,6 +512,27 @@ int pat_timing_end(double* total_ms, int64_t* launches, double* alg_bytes);
 /* Static description of a return code. */
 const char* pat_strerror(int code);
 
+/*
+ * pat_diag_sync_costs -- diagnostic: what one pass boundary costs in each
+ * launch structure the batched executor could use (its per-pass launches
+ * rest on this comparison).  On the current device, with a grid of
+ * blocks_per_cu x (compute units) blocks of 256 threads each doing
+ * floats_per_block floats of streaming read-modify-write:
+ *   *us_grid_barrier   time per iteration of one cooperative launch whose
+ *                      blocks repeat (work, grid-wide barrier) iters times,
+ *                      the barrier being HIP's cooperative-groups grid sync;
+ *   *us_atomic_barrier the same with a hand-written barrier (one atomic add
+ *                      per block and a generation word); every wait is
+ *                      bounded, and a wait that gives up yields -1;
+ *   *us_stream_launch  time per launch of iters back-to-back launches;
+ *   *us_graph_launch   the same launches replayed from a captured graph.
+ * Synchronous.  Allocates and frees its own buffer, stream and graph.
+ * Errors: PAT_EINVAL (blocks_per_cu above what can be co-resident, bad
+ * sizes, NULL outputs), PAT_ENOSYS (no cooperative launch), PAT_EHIP.
+ */
+int pat_diag_sync_costs(int32_t blocks_per_cu, int32_t floats_per_block, int32_t iters, double* us_grid_barrier,
+                        double* us_atomic_barrier, double* us_stream_launch, double* us_graph_launch);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,7 +38,7 @@ EXPORTED = [
     "pat_dot_f64", "pat_residual_f64", "pat_plan_sync", "pat_strerror", "pat_timing_begin",
     "pat_timing_end", "pat_batch_autotune", "pat_tuning_report", "pat_batch_set_tile", "pat_batch_time_pass",
     "pat_tv_smooth", "pat_restrict_lower", "pat_axpby", "pat_project", "pat_forward_batched",
-    "pat_adjoint_batched", "pat_desc_check", "pat_tv_prox_noalloc",
+    "pat_adjoint_batched", "pat_desc_check", "pat_tv_prox_noalloc", "pat_diag_sync_costs",
 ]
 
 
@@ -97,6 +97,8 @@ def lib() -> ctypes.CDLL:
         "pat_adjoint_batched": (ctypes.c_int, [pp, i32, pp, pp, vp]),
         "pat_tv_prox_work_bytes": (sz, [i32, ctypes.POINTER(i32)]),
         "pat_tv_prox": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, f64, i32, vp, vp, sz, vp]),
+        "pat_diag_sync_costs": (ctypes.c_int, [i32, i32, i32, ctypes.POINTER(f64), ctypes.POINTER(f64),
+                                                ctypes.POINTER(f64), ctypes.POINTER(f64)]),
         "pat_tv_prox_noalloc": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, f64, i32, vp, vp]),
         "pat_tv_prox_batched": (ctypes.c_int, [i32, i32, ctypes.POINTER(i32), pp, pp, ctypes.POINTER(f64), i32, pp,
                                                pp, ctypes.POINTER(sz), vp]),
