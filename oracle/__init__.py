@@ -14,9 +14,12 @@ transfer  restriction / prolongation (section V) and FP64 reductions
 solver    ISTA / FISTA and the two-level MG-FISTA (sections IV and V)
 
 Parity status: every function is pinned by tests in ``tests/test_oracle_*.py``
-against closed forms, invariants, brute force or library routines, except
-the PML's profile and placement and heterogeneous lossy propagation, which
-are pinned only structurally (transpose, linearity, lossless limit).
+against closed forms, invariants, brute force or library routines.  The
+heterogeneous lossy terms (tau and eta with per-point c0, alpha0 and rho0)
+are pinned by the first-order convergence of the paper's own
+adjoint-then-discretize system to the exact transpose.  The PML's profile
+and placement are pinned only structurally (transpose, linearity, the
+lossless limit and the decay it causes).
 """
 from . import kspace, prox, solver, transfer  # noqa: F401
 from .kspace import make_plan, forward, adjoint  # noqa: F401

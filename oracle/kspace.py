@@ -37,6 +37,12 @@ with the data injected as a mass source and the output rho*(T)/rho0 of
 equation adjj); its defining property is equation adj2, the dot-product
 identity, which the tests pin.
 
+Initial density.  By default the lossy start is rho_j(0) = p0 / (d c0^2).
+With ``section3_density`` the start follows section III's equation of state
+at t = 0 instead, c0^2 (1 - eta L2) rho(0) = p0, solved by a fixed-point
+iteration (``solve_dispersion``); the paper's adjoint-then-discretize system
+is the transpose of that forward up to O(dt).
+
 Array layout: numpy C order with x fastest, shape (ny, nx) or (nz, ny, nx).
 Physical axis j (x=0, y=1, z=2) is numpy axis ndim-1-j.
 """
@@ -50,7 +56,7 @@ import numpy as np
 import scipy.fft as sfft
 
 __all__ = ["OraclePlan", "make_plan", "forward", "adjoint", "forward_states", "db_to_neper",
-           "sensor_weights", "pml_profile", "WORKERS"]
+           "sensor_weights", "pml_profile", "solve_dispersion", "WORKERS"]
 
 #: threads handed to scipy.fft (set by callers that time the oracle)
 WORKERS = 1
@@ -148,6 +154,7 @@ class OraclePlan:
     w: np.ndarray
     nt: int
     smooth_p0: bool = False      # S in H = H0 S and H^T = S H0^T (``smooth_initial``)
+    section3_density: bool = False  # initial density from section III's t = 0 relation
 
 
 def _bcast(v: np.ndarray, ndim: int, j: int) -> np.ndarray:
@@ -240,7 +247,8 @@ def make_plan(desc, c0, rho0, alpha0_db, sensors) -> OraclePlan:
     return OraclePlan(desc=desc, ndim=nd, shape=shape, dt=dt, c_ref=c_ref, lossy=lossy, c0=c0,
                       rho0=rho0, c0sq=c0 ** 2, tau=tau, eta=eta, rho0_sg=rho0_sg, a=a, b=b, L1=L1,
                       L2=L2, Q=Q, Qsg=Qsg, idx=idx, w=w, nt=int(desc.nt),
-                      smooth_p0=bool(getattr(desc, "smooth_p0", False)))
+                      smooth_p0=bool(getattr(desc, "smooth_p0", False)),
+                      section3_density=bool(getattr(desc, "section3_density", False)))
 
 
 # --------------------------------------------------------------------------
@@ -265,6 +273,29 @@ def scatter(plan: OraclePlan, h: np.ndarray) -> np.ndarray:
     return out.reshape(plan.shape)
 
 
+def solve_dispersion(plan: OraclePlan, b: np.ndarray, transpose: bool = False) -> np.ndarray:
+    """x = (I - eta L2)^-1 b, or with transpose (I - L2 eta)^-1 b (L2 is real
+    and symmetric, eta diagonal), by the fixed-point iteration
+    x <- b + eta L2 x (resp. b + L2 (eta x)), iterated to a relative change
+    below 1e-15.  It converges because |eta| |k|^(y-1) << 1 on any grid the
+    stability bound admits (1e-2 on the test grids); a slower contraction
+    raises."""
+    b = np.asarray(b, dtype=np.float64)
+    x = b.copy()
+    prev = np.inf
+    for _ in range(200):
+        ex = plan.eta * spectral(plan.L2, x) if not transpose else spectral(plan.L2, plan.eta * x)
+        nx = b + ex
+        d = float(np.linalg.norm(nx - x))
+        x = nx
+        if d <= 1e-15 * float(np.linalg.norm(x)):
+            return x
+        if d > 0.5 * prev:
+            raise ValueError("dispersion solve does not contract")
+        prev = d
+    raise ValueError("dispersion solve did not converge")
+
+
 # --------------------------------------------------------------------------
 # forward
 # --------------------------------------------------------------------------
@@ -282,8 +313,14 @@ class ForwardState:
         P = _fft(p0)
         self.n = 0
         self.p = p0.copy()
-        # rho_j = p0 / (d c0^2): the split densities add up to p0 / c0^2
-        self.rho = [p0 / (nd * plan.c0sq) for _ in range(nd)]
+        if plan.section3_density and plan.lossy:
+            # section III's t = 0 relation c0^2 (1 - eta L2) rho(0) = p0 (the tau
+            # term vanishes with u(0) = 0), split equally over the axes
+            r0 = solve_dispersion(plan, p0 / plan.c0sq)
+            self.rho = [r0 / nd for _ in range(nd)]
+        else:
+            # rho_j = p0 / (d c0^2): the split densities add up to p0 / c0^2
+            self.rho = [p0 / (nd * plan.c0sq) for _ in range(nd)]
         # symmetric start: u_j(-dt/2) = (dt/2) (1/rho0_sg) D+_j p0, so that the
         # first update gives u_j(+dt/2) = -u_j(-dt/2) (u = 0 at t = 0 in the mean)
         self.u = [(plan.dt / 2.0) / plan.rho0_sg[j] * _ifft(plan.a[j] * P).real for j in range(nd)]
@@ -367,7 +404,11 @@ def adjoint(plan: OraclePlan, h: np.ndarray, nsteps_done: Optional[Callable] = N
             ubar[j] = plan.Qsg[j] * plan.Qsg[j] * ubar[j]
         if nsteps_done is not None:
             nsteps_done(n)
-    img = pbar + sum(rbar) / (nd * plan.c0sq)
+    if plan.section3_density and plan.lossy:
+        # transpose of rho_j(0) = (1 - eta L2)^-1 (p0 / c0^2) / d
+        img = pbar + solve_dispersion(plan, sum(rbar) / nd, transpose=True) / plan.c0sq
+    else:
+        img = pbar + sum(rbar) / (nd * plan.c0sq)
     img = img - (dt / 2.0) * sum(spectral(plan.b[j], ubar[j] / plan.rho0_sg[j]) for j in range(nd))
     return smooth_initial(img) if plan.smooth_p0 else img     # S^T = S
 

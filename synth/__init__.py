@@ -67,6 +67,7 @@ class GridDesc:
     alpha_power: float = 1.5
     pml: bool = True
     smooth_p0: bool = False  # smooth the initial pressure inside H (and H^T)
+    section3_density: bool = False  # initial density from section III's t = 0 relation
 
     @property
     def shape(self) -> Tuple[int, ...]:

@@ -166,6 +166,21 @@ def test_p4_adjoint_is_dense_transpose(n, nt, ns):
     assert np.abs(A.T - AT).max() <= 1e-13 * np.abs(A).max()
 
 
+@pytest.mark.parametrize("n,nt,ns", [((8, 8), 12, 5), ((4, 4, 4), 6, 3)])
+def test_p4_section3_density_pair_is_dense_transpose(n, nt, ns):
+    """The forward started at section III's initial density (1 - eta L2)^-1
+    p0 / c0^2 and its adjoint, with PML, absorption and heterogeneity, are
+    exact transposes (dense, column by column); the start differs from the
+    build's p0 / c0^2 (the option is applied)."""
+    inst = synth.small_instance(19, n, nt=nt, ns=ns, pml=1 if len(n) == 3 else 2, lossy=True, hetero=True)
+    plan = _plan(inst, section3_density=True)
+    A, AT = _dense(plan, plan.shape, nt, ns)
+    assert np.abs(A.T - AT).max() <= 1e-13 * np.abs(A).max()
+    A0, _ = _dense(_plan(inst), plan.shape, nt, ns)
+    assert np.abs(A - A0).max() > 1e-6 * np.abs(A).max()
+    assert np.abs(A[:ns] - A0[:ns]).max() <= 1e-13 * np.abs(A).max()  # the first sample is p0 in both
+
+
 def test_p4_nt1_is_sensor_transpose():
     """nt = 1: H = W and H^T = W^T."""
     inst = synth.small_instance(18, (8, 8), nt=1, ns=4)
