@@ -253,6 +253,85 @@ __device__ __forceinline__ void fft_last(float2 (&v)[E], int t, const Tw* tw) {
   FftStage<M, E, SIGN, fft_last_span(M, E), WaveSync, 1, LAY, PAD>::run(v, nullptr, t, tw);
 }
 
+// K transforms of length M carried by the same threads, stage by stage
+// (column passes with several fields): the K butterflies of a stage share
+// its twiddles, the K exchanges share its barriers, and the K independent
+// instruction streams hide each other's LDS and arithmetic latency.
+// Transform q exchanges through the region at lds + q * QS; otherwise as
+// FftStage (staged or strided twiddles with TWS = 1).
+template <int K, int QS, int M, int E, int SIGN, int L, class Sync, int LAY, bool PAD, int STOP = M>
+struct FftStageK {
+  static constexpr int T = M / E;
+  static constexpr int R = fft_radix(M, E, L);
+  static constexpr int NB = E / R;
+  static constexpr bool LAST = (L * R == M);
+
+  __device__ __forceinline__ static int at(int a) { return PAD ? pad8(a) : a; }
+
+  __device__ __forceinline__ static void run(float2 (&v)[K][E], float2* lds, int t, const Tw* tw) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int k = t + T * b;
+      const int j = k & (L - 1);
+      float2 x[K][R];
+#pragma unroll
+      for (int q = 0; q < K; ++q)
+#pragma unroll
+        for (int i = 0; i < R; ++i) x[q][i] = v[q][b + i * NB];
+      if constexpr (L > 1) {
+#pragma unroll
+        for (int i = 1; i < R; ++i) {
+          const Tw w = (LAY == TwStaged) ? tw[staged_off(M, E, L) + (i - 1) * L + j] : tw[(i * j) * (M / (L * R))];
+#pragma unroll
+          for (int q = 0; q < K; ++q) x[q][i] = twmul<SIGN>(x[q][i], w);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < K; ++q) Dft<R, SIGN>::run(x[q]);
+      if constexpr (LAST) {
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+#pragma unroll
+          for (int i = 0; i < R; ++i) v[q][b + i * NB] = x[q][i];
+      } else {
+        const int base = (k - j) * R + j;
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+#pragma unroll
+          for (int i = 0; i < R; ++i) lds[q * QS + at(base + i * L)] = x[q][i];
+      }
+    }
+    if constexpr (!LAST && L * R != STOP) {
+      Sync::sync();
+#pragma unroll
+      for (int q = 0; q < K; ++q)
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[q][m] = lds[q * QS + at(t + T * m)];
+      Sync::sync();
+      FftStageK<K, QS, M, E, SIGN, L * R, Sync, LAY, PAD, STOP>::run(v, lds, t, tw);
+    }
+  }
+};
+// the pieces of fft_head / fft_tail / fft_body / fft_last for K transforms
+template <int K, int QS, int M, int E, int SIGN, int LAY, bool PAD>
+__device__ __forceinline__ void fft_head_k(float2 (&v)[K][E], float2* lds, int t) {
+  static_assert(fft_radix(M, E, 1) < M, "the transform has a single stage");
+  FftStageK<K, QS, M, E, SIGN, 1, WaveSync, LAY, PAD, fft_radix(M, E, 1)>::run(v, lds, t, nullptr);
+}
+template <int K, int QS, int M, int E, int SIGN, class Sync, int LAY, bool PAD>
+__device__ __forceinline__ void fft_tail_k(float2 (&v)[K][E], float2* lds, int t, const Tw* tw) {
+  FftStageK<K, QS, M, E, SIGN, fft_radix(M, E, 1), Sync, LAY, PAD>::run(v, lds, t, tw);
+}
+template <int K, int QS, int M, int E, int SIGN, class Sync, int LAY, bool PAD>
+__device__ __forceinline__ void fft_body_k(float2 (&v)[K][E], float2* lds, int t, const Tw* tw) {
+  static_assert(fft_radix(M, E, 1) < M, "the transform has a single stage");
+  FftStageK<K, QS, M, E, SIGN, 1, Sync, LAY, PAD, fft_last_span(M, E)>::run(v, lds, t, tw);
+}
+template <int K, int QS, int M, int E, int SIGN, int LAY, bool PAD>
+__device__ __forceinline__ void fft_last_k(float2 (&v)[K][E], int t, const Tw* tw) {
+  FftStageK<K, QS, M, E, SIGN, fft_last_span(M, E), WaveSync, LAY, PAD>::run(v, nullptr, t, tw);
+}
+
 // Fill a TwStaged table for transforms of length M (E values per thread)
 // from the global length-TWN table; NTH threads of the block take part.
 template <int M, int E, int NTH, int L = 1>

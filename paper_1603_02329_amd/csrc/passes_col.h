@@ -209,31 +209,67 @@ struct SyncOf<true> {
   using type = WaveSync;
 };
 
-// LDS of one column-pass block: the tile's column regions (padded
-// exchange, odd stride), the spectrum of packed column 0 (source of its
-// mirror bins) and the staged twiddles
+// Fields a column pass transforms side by side (FftStageK): the forward
+// transforms of mode 1 (FPB fields) and of a two-input mode 2, the inverse
+// transforms of mode 1 and of a two-output mode 0.  Three-field passes (3D)
+// take their fields one at a time.
+// Tiles whose two sets of regions would take more than 80 KB of LDS (512
+// points, 16 columns) transform one field at a time.
 template <int NA, int TW>
+constexpr bool col_pair_fits() { return ColGeo<NA, TW>::TILE * (NA + NA / 8 + 1) * 16 <= 81920; }
+template <int NA, int TW, int MODE, int NF, int FPB>
+constexpr int col_kf() {
+  return !col_pair_fits<NA, TW>() ? 1 : MODE == 1 ? FPB : (MODE == 2 && NF == 2 ? 2 : 1);
+}
+template <int NA, int TW, int MODE, int NF, int FPB>
+constexpr int col_ki() {
+  return !col_pair_fits<NA, TW>() ? 1 : MODE == 1 ? FPB : (MODE == 0 && NF == 2 ? 2 : 1);
+}
+template <int NA, int TW, int MODE, int NF, int FPB>
+constexpr int col_k() {
+  return col_kf<NA, TW, MODE, NF, FPB>() > col_ki<NA, TW, MODE, NF, FPB>() ? col_kf<NA, TW, MODE, NF, FPB>()
+                                                                            : col_ki<NA, TW, MODE, NF, FPB>();
+}
+
+// The spectrum of packed column 0 (the source of its mirror bins) is kept in
+// that column's own region of each set, free between the forward and the
+// inverse transforms, unless a mode-0 pass needs it across several groups of
+// inverse transforms: then in an array of its own.
+template <int NA, int TW, int MODE, int NF, int FPB>
+constexpr bool col_sep_mirror() { return MODE == 0 && NF > col_ki<NA, TW, MODE, NF, FPB>(); }
+
+// LDS of one column-pass block: K sets of the tile's column regions (padded
+// exchange; the odd stride spreads the columns over the banks), the mirror
+// spectrum when kept apart, and the staged twiddles.  Two sets of a 512-point
+// tile of 8 columns with their twiddles take 81,776 bytes: two blocks fit
+// in a compute unit's 160 KB.
+template <int NA, int TW, int K = 1, bool SEPMIR = false>
 struct ColLds {
-  static constexpr int LDT = NA + NA / 8 + 1;
+  static constexpr int LDT = NA + NA / 8 - 1;            // pad8(NA - 1) + 1
+  static constexpr int QS = ColGeo<NA, TW>::TILE * LDT;  // one set of regions
   static constexpr int TWL = staged_len(NA, ColGeo<NA, TW>::E);
-  float2 lds[ColGeo<NA, TW>::TILE * LDT];
-  float2 lmir[NA];
+  float2 lds[K * QS];
+  float2 lmir[SEPMIR ? NA : 1];
   Tw tws[TWL > 0 ? TWL : 1];
 };
+template <int NA, int TW, int MODE, int NF, int FPB>
+using ColLdsOf = ColLds<NA, TW, col_k<NA, TW, MODE, NF, FPB>(), col_sep_mirror<NA, TW, MODE, NF, FPB>()>;
 
 // One column pass over tile `tile_index` of instance P (ColGeo<NA, TW>::NTH
 // threads); the field of a per-field pass is blockIdx.y.
 template <int NA, int MODE, int NF, int FAM, int TW, int FPB>
 __device__ __forceinline__ void colm_pass(const DevPlan& P, int tile_index, const ColSpec& spec,
-                                          ColLds<NA, TW>& sh) {
+                                          ColLdsOf<NA, TW, MODE, NF, FPB>& sh) {
   using G = ColGeo<NA, TW>;
   constexpr int E = G::E, TC = G::TC, TILE = G::TILE;
-  constexpr int LDT = ColLds<NA, TW>::LDT;
+  using Sh = ColLdsOf<NA, TW, MODE, NF, FPB>;
+  constexpr int LDT = Sh::LDT, QS = Sh::QS;
+  constexpr bool SEPMIR = col_sep_mirror<NA, TW, MODE, NF, FPB>();
+  constexpr int KF = col_kf<NA, TW, MODE, NF, FPB>(), KI = col_ki<NA, TW, MODE, NF, FPB>();
   using Sync = typename SyncOf<(TC <= 64)>::type;
   constexpr int NIN = (MODE == 0) ? 1 : (MODE == 1 ? FPB : NF);  // input fields per block
   constexpr bool UPFRONT = NIN <= 2;
   float2* const lds = sh.lds;
-  float2* const lmir = sh.lmir;
   Tw* const tws = sh.tws;
   load_staged_twiddles<NA, E, G::NTH>(tws, g_tw);
   // mapping A (memory): column ca, position ta; mapping B (transforms): column cb, lane tb
@@ -246,6 +282,9 @@ __device__ __forceinline__ void colm_pass(const DevPlan& P, int tile_index, cons
   float2* Lb = lds + cb * LDT;
   const bool special = q.tile0 && q.selfpair;  // block holds a packed column 0 (block-uniform)
   const bool fix = q.col0 && q.selfpair;       // this lane's column is it
+  // mirror spectrum of transform r: column 0's region of set r (only column
+  // 0's lanes touch it between the transforms), or the separate array
+  auto mir = [&](int r) -> float2* { return SEPMIR ? sh.lmir : lds + r * QS; };
 
   // input k of this block, output i
   const int fbase = (MODE == 1) ? spec.f0 + (int)blockIdx.y * FPB : spec.f0;
@@ -271,124 +310,186 @@ __device__ __forceinline__ void colm_pass(const DevPlan& P, int tile_index, cons
   const float k2y = q.along_y ? 0.f : gld(P.ksq[1], kyf);
   const float k2fix = xb.k2 + k2y, k2fixN = xbN.k2 + k2y;
   const int ax_last = q.along_y ? 1 : 2;
-  float k2v[E];
+  // Every operand of the multipliers is read, and the per-element factors
+  // formed, here, before the transforms: their loads then overlap the input
+  // loads.  Read where they are used, after the forward transform, each
+  // table load's latency would stall the block (the LDS barriers keep the
+  // compiler from hoisting them).
+  const float kap2 = P.kap2, scale = P.scale, ym2h = P.ym2h, ym1h = P.ym1h, inv_dt = P.inv_dt;
+  constexpr bool DERIV = (FAM == F_A || FAM == F_B), SA = (FAM != F_B);
+  auto k2at = [&](int m) { return gld(P.ksq[ax_last], tb + TC * m); };
+  // derivatives: kappa/N at this column's elements, the staggered shift along
+  // the transform axis, and (3D, along z) the y shift of this column;
+  // Laplacians: |k|^2 along the axis
+  float gv[(DERIV || FAM == F_ABS) ? E : 1];
+  float2 shv[DERIV ? E : 1];
+  float2 shyf = f2(0.f, 0.f);
+  if constexpr (DERIV) {
+    const float2* sht = SA ? P.shA[ax_last] : P.shB[ax_last];
 #pragma unroll
-  for (int m = 0; m < E; ++m) k2v[m] = gld(P.ksq[ax_last], tb + TC * m);
+    for (int m = 0; m < E; ++m) {
+      shv[m] = gld(sht, tb + TC * m);
+      gv[m] = sinc_sqrt(kap2 * (k2fix + k2at(m))) * scale;
+    }
+    if (!q.along_y) shyf = gld(SA ? P.shA[1] : P.shB[1], kyf);
+  } else if constexpr (FAM == F_ABS) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) gv[m] = k2at(m);
+  }
   // window family: the x (and, along z, the y) factor of this column, the
   // x factor at x-bin nx/2 for the packed column 0, and the along-axis one
   float wfix = 1.f, wfixN = 1.f, wv[E];
   if constexpr (FAM == F_WIN) {
     const float wy = q.along_y ? 1.f : gld(P.win[1], kyf);
-    wfix = gld(P.win[0], unpackedB ? q.M : q.kxi) * wy * P.scale;
-    wfixN = gld(P.win[0], q.M) * wy * P.scale;
+    wfix = gld(P.win[0], unpackedB ? q.M : q.kxi) * wy * scale;
+    wfixN = gld(P.win[0], q.M) * wy * scale;
 #pragma unroll
     for (int m = 0; m < E; ++m) wv[m] = gld(P.win[ax_last], tb + TC * m);
   }
-  // factor g of element m (kappa/N, or the Laplacian factor)
-  auto factor = [&](float k2, int which) -> float {
-    if constexpr (FAM == F_ABS) {
-      return (which == M_L1DT ? kpow(k2, P.ym2h) * P.inv_dt : kpow(k2, P.ym1h)) * P.scale;
-    } else {
-      return sinc_sqrt(P.kap2 * k2) * P.scale;
-    }
+  // Laplacian factor of element m
+  auto lapl = [&](float k2, int which) -> float {
+    return (which == M_L1DT ? kpow(k2, ym2h) * inv_dt : kpow(k2, ym1h)) * scale;
   };
   // staggered shift of derivative axis `axis` at element m, for this
   // column's x-bin (nyq: at x-bin nx/2)
   auto shift = [&](int axis, int m, bool nyq) -> float2 {
-    constexpr bool SA = (FAM != F_B);
     if (axis == 0) return nyq ? (SA ? xbN.sa : xbN.sb) : (SA ? xb.sa : xb.sb);
-    if (axis == 1 && !q.along_y) return gld(SA ? P.shA[1] : P.shB[1], kyf);
-    return gld(SA ? P.shA[axis] : P.shB[axis], tb + TC * m);
+    if (axis == 1 && !q.along_y) return shyf;
+    return shv[DERIV ? m : 0];
   };
+  // multiplier of element m (nyq: at x-bin nx/2, for the packed column 0)
   auto mult = [&](int which, int m, bool nyq) -> float2 {
-    if constexpr (FAM == F_WIN) return f2((nyq ? wfixN : wfix) * wv[m], 0.f);
-    const float g = factor((nyq ? k2fixN : k2fix) + k2v[m], which);
-    if constexpr (FAM == F_ABS) return f2(g, 0.f);
-    else return scl2(g, shift(which, m, nyq));
+    if constexpr (FAM == F_WIN) {
+      return f2((nyq ? wfixN : wfix) * wv[m], 0.f);
+    } else if constexpr (FAM == F_ABS) {
+      return f2(lapl((nyq ? k2fixN : k2fix) + gv[m], which), 0.f);
+    } else {
+      const float g = nyq ? sinc_sqrt(kap2 * (k2fixN + k2at(m))) * scale : gv[m];
+      return scl2(g, shift(which, m, nyq));
+    }
   };
   // acc += mult * s.  The packed column 0 holds C = A + iB (x-bins 0 and
   // nx/2): there the product is 1/2 (m0 + mN) C + 1/2 (m0 - mN) conj(C(-k)),
-  // with the mirror bins read from the column's spectrum in LDS.
-  auto apply = [&](int which, const float2 (&s)[E], float2 (&acc)[E]) {
+  // with the mirror bins read from the spectrum of transform r in LDS.
+  auto apply = [&](int which, const float2 (&s)[E], float2 (&acc)[E], int r) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const float2 mv = mult(which, m, false);
       if (fix) {
         const float2 mN = mult(which, m, true);
-        const float2 vm = conjf2(lmir[(NA - (tb + TC * m)) & (NA - 1)]);
+        const float2 vm = conjf2(mir(r)[(NA - (tb + TC * m)) & (NA - 1)]);
         acc[m] = acc[m] + cmul(0.5f * (mv + mN), s[m]) + cmul(0.5f * (mv - mN), vm);
       } else {
         acc[m] = acc[m] + cmul(mv, s[m]);
       }
     }
   };
-  // Forward transform of one input (mapping A in, spectrum in mapping B
-  // out): the first stage runs in mapping A, where each thread already holds
-  // the eight values of its butterfly, and its exchange carries the values
-  // over to mapping B; a block holding column 0 keeps that column's spectrum
-  // in LDS for its mirror bins.  v is overwritten.
-  auto forward = [&](float2 (&v)[E], float2 (&s)[E]) {
-    __syncthreads();  // earlier readers of the regions are done
-    fft_head<NA, E, -1, TwStaged, true>(v, La, ta);
+  // Forward transforms of K inputs side by side (mapping A in, spectra in
+  // mapping B out): the first stage runs in mapping A, where each thread
+  // already holds the eight values of its butterfly, and its exchange
+  // carries the values over to mapping B; a block holding column 0 keeps
+  // that column's spectra in LDS for their mirror bins.  v is overwritten.
+  // The block's first transform finds the regions unused and skips the
+  // barrier that waits for their earlier readers.
+  auto forward = [&](auto& v, auto& s, bool first) {
+    constexpr int K = sizeof(v) / sizeof(v[0]);
+    if (!first) __syncthreads();  // earlier readers of the regions are done
+    fft_head_k<K, QS, NA, E, -1, TwStaged, true>(v, La, ta);
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < E; ++m) s[m] = Lb[pad8(tb + TC * m)];
-    Sync::sync();  // the transform reuses the region
-    fft_tail<NA, E, -1, Sync, TwStaged, true>(s, Lb, tb, tws);
+    for (int r = 0; r < K; ++r)
+#pragma unroll
+      for (int m = 0; m < E; ++m) s[r][m] = Lb[r * QS + pad8(tb + TC * m)];
+    Sync::sync();  // the transforms reuse the regions
+    fft_tail_k<K, QS, NA, E, -1, Sync, TwStaged, true>(s, Lb, tb, tws);
     if (special) {
       if (fix) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) lmir[tb + TC * m] = s[m];
+        for (int r = 0; r < K; ++r)
+#pragma unroll
+          for (int m = 0; m < E; ++m) mir(r)[tb + TC * m] = s[r][m];
       }
       Sync::sync();
     }
   };
-  // inverse transform (mapping B in) and store (mapping A): every stage but
-  // the last in mapping B, whose final exchange carries the values over to
-  // mapping A for the last stage
-  auto inverse_store = [&](float2 (&acc)[E], float2* __restrict__ dst) {
-    fft_body<NA, E, +1, Sync, TwStaged, true>(acc, Lb, tb, tws);
+  // Inverse transforms of K outputs side by side (mapping B in) and their
+  // stores (mapping A): every stage but the last in mapping B, whose final
+  // exchange carries the values over to mapping A for the last stage.
+  // After the block's last transform no barrier releases the regions.
+  auto inverse_store = [&](auto& acc, auto dst, bool last) {
+    constexpr int K = sizeof(acc) / sizeof(acc[0]);
+    if (!SEPMIR && special) Sync::sync();  // the mirror reads precede the region's reuse
+    fft_body_k<K, QS, NA, E, +1, Sync, TwStaged, true>(acc, Lb, tb, tws);
     __syncthreads();
-    float2 v[E];
+    float2 v[K][E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = La[pad8(ta + TC * m)];
-    __syncthreads();  // the regions are free for the next transform
-    fft_last<NA, E, +1, TwStaged, true>(v, ta, tws);
-    col_store<NA, TC>(dst, qa, ta, v);
+    for (int r = 0; r < K; ++r)
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[r][m] = La[r * QS + pad8(ta + TC * m)];
+    if (!last) __syncthreads();  // the regions are free for the next transform
+    fft_last_k<K, QS, NA, E, +1, TwStaged, true>(v, ta, tws);
+#pragma unroll
+    for (int r = 0; r < K; ++r) col_store<NA, TC>(dst(r), qa, ta, v[r]);
+  };
+
+  // inputs k .. k + KF - 1 of the block, from the up-front loads or loaded now
+  auto take = [&](int k, float2 (&v)[KF][E]) {
+#pragma unroll
+    for (int r = 0; r < KF; ++r) {
+      if constexpr (UPFRONT) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) v[r][m] = vin[k + r][m];
+      } else {
+        col_load<NA, TC>(in_ptr(k + r), qa, ta, v[r]);
+      }
+    }
   };
 
   if constexpr (MODE == 2) {
-    float2 acc[E];
+    // NF inputs, KF at a time, summed into one output
+    float2 acc[1][E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) acc[0][m] = f2(0.f, 0.f);
 #pragma unroll
-    for (int k = 0; k < NF; ++k) {
-      float2 s[E];
-      if constexpr (UPFRONT) {
-        forward(vin[k], s);
-      } else {
-        float2 v[E];
-        col_load<NA, TC>(in_ptr(k), qa, ta, v);
-        forward(v, s);
-      }
-      apply(which_of(k), s, acc);
+    for (int k = 0; k < NF; k += KF) {
+      float2 v[KF][E], s[KF][E];
+      take(k, v);
+      forward(v, s, k == 0);
+#pragma unroll
+      for (int r = 0; r < KF; ++r) apply(which_of(k + r), s[r], acc[0], r);
     }
-    inverse_store(acc, out_ptr(0));
-  } else {
-    // mode 0: one input, NF outputs; mode 1: FPB inputs, one output each
+    inverse_store(acc, [&](int) { return out_ptr(0); }, true);
+  } else if constexpr (MODE == 1) {
+    // FPB fields, each to its own output, KF side by side
 #pragma unroll
-    for (int k = 0; k < NIN; ++k) {
-      float2 s[E];
-      forward(vin[k], s);
-      constexpr int NOUT = (MODE == 0) ? NF : 1;
+    for (int k = 0; k < FPB; k += KF) {
+      float2 v[KF][E], s[KF][E];
+      take(k, v);
+      forward(v, s, k == 0);
+      float2 acc[KF][E];
 #pragma unroll
-      for (int i = 0; i < NOUT; ++i) {
-        float2 acc[E];
+      for (int r = 0; r < KF; ++r) {
 #pragma unroll
-        for (int m = 0; m < E; ++m) acc[m] = f2(0.f, 0.f);
-        apply(which_of(MODE == 0 ? i : (int)blockIdx.y * FPB + k), s, acc);
-        inverse_store(acc, out_ptr(MODE == 0 ? i : k));
+        for (int m = 0; m < E; ++m) acc[r][m] = f2(0.f, 0.f);
+        apply(which_of((int)blockIdx.y * FPB + k + r), s[r], acc[r], r);
       }
+      inverse_store(acc, [&](int r) { return out_ptr(k + r); }, k + KF >= FPB);
+    }
+  } else {
+    // mode 0: one input, NF outputs, KI at a time
+    float2 v[1][E], s[1][E];
+    take(0, v);
+    forward(v, s, true);
+#pragma unroll
+    for (int i = 0; i < NF; i += KI) {
+      float2 acc[KI][E];
+#pragma unroll
+      for (int r = 0; r < KI; ++r) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) acc[r][m] = f2(0.f, 0.f);
+        apply(which_of(i + r), s[0], acc[r], 0);
+      }
+      inverse_store(acc, [&](int r) { return out_ptr(i + r); }, i + KI >= NF);
     }
   }
 }
@@ -396,7 +497,7 @@ __device__ __forceinline__ void colm_pass(const DevPlan& P, int tile_index, cons
 template <int NA, int MODE, int NF, int FAM, int TW, int FPB>
 __global__ void __launch_bounds__((ColGeo<NA, TW>::NTH)) k_colm(const DevPlan* __restrict__ plans,
                                                                const int2* __restrict__ table, ColSpec spec) {
-  __shared__ ColLds<NA, TW> sh;
+  __shared__ ColLdsOf<NA, TW, MODE, NF, FPB> sh;
   const int2 job = table ? table[blockIdx.x] : make_int2(0, (int)blockIdx.x);
   colm_pass<NA, MODE, NF, FAM, TW, FPB>(plans[job.x], job.y, spec, sh);
 }

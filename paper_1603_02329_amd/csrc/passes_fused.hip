@@ -48,7 +48,10 @@ template <int NTH, int MODE, int NF, int FAM, int FPB>
 __global__ void __launch_bounds__(NTH) k_colf(const DevPlan* __restrict__ plans, const int2* __restrict__ table,
                                               ColSpec spec, StepArg sa) {
   constexpr int T512 = NTH / 64, T256 = NTH / 32, T128 = NTH / 16;
-  constexpr int B = cmax(sizeof(ColLds<512, T512>), cmax(sizeof(ColLds<256, T256>), sizeof(ColLds<128, T128>)));
+  using L5 = ColLdsOf<512, T512, MODE, NF, FPB>;
+  using L2 = ColLdsOf<256, T256, MODE, NF, FPB>;
+  using L1 = ColLdsOf<128, T128, MODE, NF, FPB>;
+  constexpr int B = cmax(sizeof(L5), cmax(sizeof(L2), sizeof(L1)));
   __shared__ __align__(16) unsigned char raw[B];
   const int2 job = table[blockIdx.x];
   const DevPlan& P = plans[job.x];
@@ -56,13 +59,13 @@ __global__ void __launch_bounds__(NTH) k_colf(const DevPlan* __restrict__ plans,
   if (!fused_step(P, sa, it)) return;  // block-uniform
   switch (P.n[1]) {
     case 512:
-      colm_pass<512, MODE, NF, FAM, T512, FPB>(P, job.y, spec, *reinterpret_cast<ColLds<512, T512>*>(raw));
+      colm_pass<512, MODE, NF, FAM, T512, FPB>(P, job.y, spec, *reinterpret_cast<L5*>(raw));
       break;
     case 256:
-      colm_pass<256, MODE, NF, FAM, T256, FPB>(P, job.y, spec, *reinterpret_cast<ColLds<256, T256>*>(raw));
+      colm_pass<256, MODE, NF, FAM, T256, FPB>(P, job.y, spec, *reinterpret_cast<L2*>(raw));
       break;
     case 128:
-      colm_pass<128, MODE, NF, FAM, T128, FPB>(P, job.y, spec, *reinterpret_cast<ColLds<128, T128>*>(raw));
+      colm_pass<128, MODE, NF, FAM, T128, FPB>(P, job.y, spec, *reinterpret_cast<L1*>(raw));
       break;
     default: break;
   }
