@@ -332,20 +332,37 @@ __device__ __forceinline__ void fft_last_k(float2 (&v)[K][E], int t, const Tw* t
   FftStageK<K, QS, M, E, SIGN, fft_last_span(M, E), WaveSync, LAY, PAD>::run(v, nullptr, t, tw);
 }
 
-// Fill a TwStaged table for transforms of length M (E values per thread)
-// from the global length-TWN table; NTH threads of the block take part.
-template <int M, int E, int NTH, int L = 1>
-__device__ __forceinline__ void load_staged_twiddles(Tw* dst, const Tw* __restrict__ g) {
+// Source in the global length-TWN table of entry q of a TwStaged table for
+// transforms of length M (E values per thread), q counted from stage L's
+// first entry.  The entries of the first stage (L = 1) are exp(0) = 1.
+template <int M, int E, int L = 1>
+__device__ __forceinline__ int staged_src(int q) {
   constexpr int R = fft_radix(M, E, L);
-  if constexpr (L > 1) {
-    constexpr int OFF = staged_off(M, E, L), STRIDE = TWN / (L * R);
-    static_assert(TWN % (L * R) == 0, "stage longer than the global table");
-    for (int q = threadIdx.x; q < (R - 1) * L; q += NTH) {
-      const int i = q / L + 1, j = q % L;
-      dst[OFF + q] = g[(i * j) * STRIDE];
-    }
+  if constexpr (L * R < M) {
+    if (q >= (R - 1) * L) return staged_src<M, E, L * R>(q - (R - 1) * L);
   }
-  if constexpr (L * R < M) load_staged_twiddles<M, E, NTH, L * R>(dst, g);
+  static_assert(TWN % (L * R) == 0, "stage longer than the global table");
+  return ((q / L + 1) * (q % L)) * (TWN / (L * R));
+}
+
+// Copy NTOT entries from the global table into an LDS table, entry q from
+// g[src(q)], NTH threads taking part.  Each thread issues all its global
+// loads before its first LDS write, so the table costs one memory round
+// trip.  Called after a pass has issued its own loads, it overlaps them.
+template <int NTOT, int NTH, class Src>
+__device__ __forceinline__ void load_table(Tw* dst, const Tw* __restrict__ g, Src src) {
+  constexpr int PER = (NTOT + NTH - 1) / NTH;
+  Tw v[PER];
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int q = (int)threadIdx.x + NTH * r;
+    v[r] = g[src(q < NTOT ? q : NTOT - 1)];
+  }
+#pragma unroll
+  for (int r = 0; r < PER; ++r) {
+    const int q = (int)threadIdx.x + NTH * r;
+    if (q < NTOT) dst[q] = v[r];
+  }
 }
 
 // Copy the length-TL twiddle table (from the global length-TWN one) into LDS.

@@ -111,10 +111,15 @@ __device__ __forceinline__ ColPos col_pos(const DevPlan& P, int tile_index, int 
   return q;
 }
 
+// loads are issued for every lane (kxi is a valid column for all) and
+// zeroed for lanes past the tile's width: no branch between them
 template <int NA, int TC, int E>
 __device__ __forceinline__ void col_load(const float2* __restrict__ src, const ColPos& q, int t, float2 (&v)[E]) {
 #pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = q.cvalid ? gld(src, q.obase + (t + TC * m) * q.stride + q.kxi) : f2(0.f, 0.f);
+  for (int m = 0; m < E; ++m) {
+    const float2 x = gld(src, q.obase + (t + TC * m) * q.stride + q.kxi);
+    v[m] = q.cvalid ? x : f2(0.f, 0.f);
+  }
 }
 template <int NA, int TC, int E>
 __device__ __forceinline__ void col_store(float2* __restrict__ dst, const ColPos& q, int t, const float2 (&v)[E]) {
@@ -216,7 +221,7 @@ struct SyncOf<true> {
 // Tiles whose two sets of regions would take more than 80 KB of LDS (512
 // points, 16 columns) transform one field at a time.
 template <int NA, int TW>
-constexpr bool col_pair_fits() { return ColGeo<NA, TW>::TILE * (NA + NA / 8 + 1) * 16 <= 81920; }
+constexpr bool col_pair_fits() { return ColGeo<NA, TW>::TILE * (NA + NA / 8 - 1) * 16 <= 81920; }
 template <int NA, int TW, int MODE, int NF, int FPB>
 constexpr int col_kf() {
   return !col_pair_fits<NA, TW>() ? 1 : MODE == 1 ? FPB : (MODE == 2 && NF == 2 ? 2 : 1);
@@ -271,7 +276,6 @@ __device__ __forceinline__ void colm_pass(const DevPlan& P, int tile_index, cons
   constexpr bool UPFRONT = NIN <= 2;
   float2* const lds = sh.lds;
   Tw* const tws = sh.tws;
-  load_staged_twiddles<NA, E, G::NTH>(tws, g_tw);
   // mapping A (memory): column ca, position ta; mapping B (transforms): column cb, lane tb
   const int ca = threadIdx.x % TILE, ta = threadIdx.x / TILE;
   const int cb = threadIdx.x / TC, tb = threadIdx.x % TC;
@@ -346,6 +350,9 @@ __device__ __forceinline__ void colm_pass(const DevPlan& P, int tile_index, cons
 #pragma unroll
     for (int m = 0; m < E; ++m) wv[m] = gld(P.win[ax_last], tb + TC * m);
   }
+  // the staged twiddles, after the block's own loads (first read after the
+  // barrier that ends the first transform's first stage)
+  load_table<Sh::TWL, G::NTH>(tws, g_tw, [](int i) { return staged_src<NA, E>(i); });
   // Laplacian factor of element m
   auto lapl = [&](float k2, int which) -> float {
     return (which == M_L1DT ? kpow(k2, ym2h) * inv_dt : kpow(k2, ym1h)) * scale;

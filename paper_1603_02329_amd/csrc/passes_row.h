@@ -48,11 +48,15 @@ struct RowTw {
   Tw u[N / 2];
   Tw s[RowGeo<N>::TWS > 0 ? RowGeo<N>::TWS : 1];
 };
+// Both tables in one pass (u then s, contiguous in RowTw): one memory round
+// trip, issued after the pass's own loads.
 template <int N, int NTH = RowGeo<N>::NTH>
 __device__ __forceinline__ void load_row_twiddles(RowTw<N>& tw, const Tw* __restrict__ g) {
   using G = RowGeo<N>;
-  for (int q = threadIdx.x; q < G::M; q += NTH) tw.u[q] = g[q * (TWN / N)];
-  load_staged_twiddles<G::M, G::E, NTH>(tw.s, g);
+  static_assert(sizeof(RowTw<N>) == sizeof(Tw) * (G::M + (G::TWS > 0 ? G::TWS : 1)), "RowTw is not contiguous");
+  load_table<G::M + G::TWS, NTH>(reinterpret_cast<Tw*>(&tw), g, [](int q) {
+    return q < G::M ? q * (TWN / N) : staged_src<G::M, G::E>(q - G::M);
+  });
 }
 
 // Packed half spectrum of one row -> real row, as pairs (x[2n], x[2n+1]) at
@@ -178,13 +182,21 @@ struct RowIo {
   const long base;
   const int t;
   const bool valid;
+  // loads are issued for every lane (base is that of a valid row) and
+  // zeroed for lanes past the last row: no branch between them
   __device__ __forceinline__ void ld(const float* a, float2 (&v)[E]) const {
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = valid ? ld2(a, base + t + T * m) : f2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) {
+      const float2 x = ld2(a, base + t + T * m);
+      v[m] = valid ? x : f2(0.f, 0.f);
+    }
   }
   __device__ __forceinline__ void ld(const float2* a, float2 (&v)[E]) const {
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = valid ? gld(a, base + t + T * m) : f2(0.f, 0.f);
+    for (int m = 0; m < E; ++m) {
+      const float2 x = gld(a, base + t + T * m);
+      v[m] = valid ? x : f2(0.f, 0.f);
+    }
   }
   // 1-D x table (PML factor along x), pairs at n = t + T m
   __device__ __forceinline__ void ldx(const float* a, float2 (&v)[E]) const {
@@ -209,7 +221,6 @@ template <int N, int D, int K, int ROWS>
 __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, float2* lds, RowTw<N>& tws) {
   using G = RowGeo<N>;
   constexpr int M = G::M, E = G::E, T = G::T;
-  load_row_twiddles<N, ROWS * T>(tws, g_tw);
   const int rl = threadIdx.x / T, t = threadIdx.x % T;
   const int row = tile * ROWS + rl;
   const bool valid = row < P.nrows;
@@ -235,7 +246,8 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
     if constexpr (K == R_FWD_INIT) io.ld(P.in, p);
     else io.ld(P.S[0], p);  // the windowed spectrum of p0
     io.ld(P.inv_dc2, ic);
-    __syncthreads();  // twiddles
+    load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
+    __syncthreads();
     if constexpr (K == R_FWD_INIT_F) {
       c2r<N>(p, L, t, tws);  // the smoothed p0 (the window pass holds the 1/N)
       WaveSync::sync();
@@ -260,7 +272,8 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
     io.ld(P.B[j], b);
     if (first) io.zero(u); else io.ld(P.u[j], u);
     if (j == 0) io.ldx(P.Qsg[0], qx);
-    __syncthreads();  // twiddles
+    load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
+    __syncthreads();
     c2r<N>(d, L, t, tws);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -290,7 +303,8 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
     io.ld(P.dtr0, dr);
     if constexpr (K == R_FWD_2LL) io.ld(P.c2, c2);
     io.ldx(P.Q[0], qx);
-    __syncthreads();  // twiddles
+    load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < D; ++j) c2r<N>(g[j], L, t, tws);
     float2 sdiv[E], srho[E];
@@ -328,7 +342,8 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
     float2 a1[E], a2[E], rs[E], c2[E];
     io.ld(P.S[1], a1);
     io.ld(P.S[2], a2);
-    __syncthreads();  // twiddles
+    load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
+    __syncthreads();
     c2r<N>(a1, L, t, tws);
     c2r<N>(a2, L, t, tws);
     io.ld(P.r[0], rs);
@@ -390,7 +405,8 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
         if (first) io.zero(rb[j]); else io.ld(P.r[j], rb[j]);
       }
     }
-    __syncthreads();  // twiddles
+    load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
+    __syncthreads();
     if (!first) c2r<N>(v, L, t, tws);
 #pragma unroll
     for (int m = 0; m < E; ++m) L[t + T * m] = v[m];
@@ -432,7 +448,8 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
     float2 a2[E], a1[E], q[E], dr[E], qx[E];
     io.ld(P.S[1], a2);
     io.ld(P.S[2], a1);
-    __syncthreads();  // twiddles
+    load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
+    __syncthreads();
     c2r<N>(a2, L, t, tws);
     c2r<N>(a1, L, t, tws);
     io.ld(P.q, q);
@@ -472,7 +489,8 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
     io.ld(P.dtr0, dr);
     io.ld(P.c2, c2);
     io.ldx(P.Q[0], qx);
-    __syncthreads();  // twiddles
+    load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < D; ++j) c2r<N>(g[j], L, t, tws);
 #pragma unroll
@@ -526,7 +544,8 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
     float2 a1[E], a2[E], rs[E], c2[E], dr[E];
     io.ld(P.S[1], a1);
     io.ld(P.S[2], a2);
-    __syncthreads();  // twiddles
+    load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
+    __syncthreads();
     c2r<N>(a1, L, t, tws);
     c2r<N>(a2, L, t, tws);
     io.ld(P.r[0], rs);
@@ -561,12 +580,14 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
     // x-spectrum of a real field: p0 (forward) or the image (adjoint)
     float2 v[E];
     io.ld(K == R_FILT_IN ? P.in : P.out, v);
-    __syncthreads();  // twiddles
+    load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
+    __syncthreads();
     r2c<N>(v, P.S[0] + io.base, L, t, valid, tws);
   } else if constexpr (K == R_FILT_OUT) {
     float2 v[E];
     io.ld(P.S[0], v);
-    __syncthreads();  // twiddles
+    load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
+    __syncthreads();
     c2r<N>(v, L, t, tws);
     io.st(P.out, v);
   } else if constexpr (K == R_ADJ_FINAL || K == R_ADJ_SCATTER_ONLY) {
@@ -585,7 +606,8 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
     } else {
       io.zero(v);
     }
-    __syncthreads();  // twiddles
+    load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
+    __syncthreads();
     if constexpr (K == R_ADJ_FINAL) c2r<N>(v, L, t, tws);
 #pragma unroll
     for (int m = 0; m < E; ++m) L[t + T * m] = v[m];
