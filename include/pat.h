@@ -443,6 +443,29 @@ int pat_residual_f64(const float* a, const float* b, float* r, int64_t n, double
                      void* stream);
 
 /*
+ * pat_residual_f64_batched -- the residuals of `count` pairs at once, with
+ * nothing returned to the host and no synchronisation: the gradient-step
+ * residuals H_i x_i - p_i of a batch of problems (section IV, eq. Six) and
+ * their objective, left on the device for the adjoint that follows.
+ *   count      1 .. 4096 pairs.
+ *   a, b, r    host arrays of `count` device pointers: r_i = a_i - b_i
+ *              (float32, n[i] elements each; r_i may alias a_i or b_i).
+ *   n          host array of `count` element counts (>= 0; pointers may be
+ *              NULL where n[i] = 0).
+ *   work_dev   device scratch of pat_residual_batched_work_bytes(count)
+ *              bytes, owned by the caller; calls that overlap on the GPU
+ *              need their own.
+ *   out_dev    device, count + 1 doubles: out_dev[i] = 1/2 ||a_i - b_i||^2,
+ *              accumulated in float64 with pat_residual_f64's fixed
+ *              partition (equal to that call's value bitwise), and
+ *              out_dev[count] = their sum in index order.
+ * Returns PAT_EINVAL for a bad count, a NULL array or a negative count.
+ */
+size_t pat_residual_batched_work_bytes(int32_t count);
+int pat_residual_f64_batched(int32_t count, const float* const* a, const float* const* b, float* const* r,
+                             const int64_t* n, double* work_dev, double* out_dev, void* stream);
+
+/*
  * Operators of the two-level iteration (section V, Alg. FISTAMG).
  *
  * pat_tv_smooth -- the smoothed TV of equation Thirty-two,

@@ -15,7 +15,7 @@ from typing import Optional, Sequence
 
 import numpy as np
 
-__all__ = ["lib", "PatError", "Plan", "Batch", "tv_prox", "restrict", "prolong", "dot_f64", "residual_f64",
+__all__ = ["lib", "PatError", "Plan", "Batch", "tv_prox", "restrict", "prolong", "dot_f64", "residual_f64", "residual_f64_batched",
            "tv_smooth", "restrict_lower", "axpby", "project", "tv_prox_batched", "forward_batched",
            "adjoint_batched",
            "LIB_PATH", "EXPORTED"]
@@ -35,7 +35,7 @@ EXPORTED = [
     "pat_forward_range", "pat_batch_create", "pat_batch_create_ex", "pat_batch_destroy", "pat_batch_forward",
     "pat_batch_adjoint", "pat_tv_prox_work_bytes", "pat_tv_prox", "pat_tv_prox_batched", "pat_restrict",
     "pat_prolong",
-    "pat_dot_f64", "pat_residual_f64", "pat_plan_sync", "pat_strerror", "pat_timing_begin",
+    "pat_dot_f64", "pat_residual_f64", "pat_residual_f64_batched", "pat_residual_batched_work_bytes", "pat_plan_sync", "pat_strerror", "pat_timing_begin",
     "pat_timing_end", "pat_batch_autotune", "pat_tuning_report", "pat_batch_set_tile", "pat_batch_time_pass",
     "pat_tv_smooth", "pat_restrict_lower", "pat_axpby", "pat_project", "pat_forward_batched",
     "pat_adjoint_batched", "pat_desc_check", "pat_tv_prox_noalloc", "pat_diag_sync_costs",
@@ -106,6 +106,8 @@ def lib() -> ctypes.CDLL:
         "pat_prolong": (ctypes.c_int, [i32, ctypes.POINTER(i32), vp, vp, vp]),
         "pat_dot_f64": (ctypes.c_int, [vp, vp, i64, ctypes.POINTER(f64), vp]),
         "pat_residual_f64": (ctypes.c_int, [vp, vp, vp, i64, ctypes.POINTER(f64), vp]),
+        "pat_residual_f64_batched": (ctypes.c_int, [i32, vp, vp, vp, vp, vp, vp, vp]),
+        "pat_residual_batched_work_bytes": (ctypes.c_size_t, [i32]),
         "pat_plan_sync": (ctypes.c_int, [vp, vp]),
         "pat_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "pat_timing_begin": (ctypes.c_int, [i32, i32, i32]),
@@ -538,6 +540,31 @@ def residual_f64(a, b, r=None):
     _check(lib().pat_residual_f64(_dev_f32(a, "a"), _dev_f32(b, "b", a.numel()), _dev_f32(r, "r", a.numel()),
                                   a.numel(), ctypes.byref(out), _stream()), "pat_residual_f64")
     return r, out.value
+
+
+def residual_f64_batched(As, Bs, Rs=None, work=None, out=None):
+    """(list of r_i = a_i - b_i, device float64 tensor out of len(As) + 1:
+    out[i] = 1/2 ||a_i - b_i||^2, out[-1] their sum), with no host
+    synchronisation (pat_residual_f64_batched).  work: a uint8 device
+    tensor of at least pat_residual_batched_work_bytes(len(As)) bytes
+    (allocated when None)."""
+    torch = _torch()
+    count = len(As)
+    if Rs is None:
+        Rs = [torch.empty_like(a) for a in As]
+    need = int(lib().pat_residual_batched_work_bytes(count))
+    if work is None or work.numel() < need:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=As[0].device)
+    if out is None:
+        out = torch.empty(count + 1, dtype=torch.float64, device=As[0].device)
+    vpa = ctypes.c_void_p * count
+    pa = vpa(*[_dev_f32(a, "a").value for a in As])
+    pb = vpa(*[_dev_f32(b, "b", a.numel()).value for a, b in zip(As, Bs)])
+    pr = vpa(*[_dev_f32(r, "r", a.numel()).value for a, r in zip(As, Rs)])
+    ns = (ctypes.c_int64 * count)(*[a.numel() for a in As])
+    _check(lib().pat_residual_f64_batched(count, pa, pb, pr, ns, ctypes.c_void_p(work.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()), _stream()), "pat_residual_f64_batched")
+    return Rs, out
 
 
 def tv_smooth(x, rho: float, grad=None, scale: float = 1.0, value: bool = True):

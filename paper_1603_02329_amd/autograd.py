@@ -21,7 +21,7 @@ from typing import List, Optional, Tuple
 
 import torch
 
-from . import Plan, residual_f64
+from . import Plan, residual_f64, residual_f64_batched
 
 __all__ = ["PatOperator", "PatLeastSquares", "PatBatchLeastSquares", "forward_checkpointed", "replay_segment"]
 
@@ -118,18 +118,17 @@ class PatBatchLeastSquares(torch.autograd.Function):
     @staticmethod
     def forward(ctx, batch, targets, *p0s):
         datas = batch.forward([p.detach().contiguous() for p in p0s])
-        res, total = [], 0.0
-        for d, t in zip(datas, targets):
-            r, half = residual_f64(d, t.detach().contiguous())
-            res.append(r)
-            total += half
+        # all residuals and the objective in one call that leaves them on the
+        # device: the adjoint is queued behind them without a host round trip
+        res, out = residual_f64_batched(datas, [t.detach().contiguous() for t in targets])
         ctx.batch = batch
         ctx.save_for_backward(*res)
-        return torch.tensor(total, dtype=torch.float64, device=p0s[0].device)
+        return out[-1].clone()
 
     @staticmethod
     def backward(ctx, grad_f):
         grads = ctx.batch.adjoint(list(ctx.saved_tensors))
-        if float(grad_f) != 1.0:
-            grads = [g * grad_f.to(torch.float32) for g in grads]
+        # scaled on the device (exact for the usual 1): reading grad_f on the
+        # host would wait for the whole forward
+        torch._foreach_mul_(grads, grad_f.to(torch.float32))
         return (None, None, *grads)

@@ -294,7 +294,7 @@ __global__ void __launch_bounds__(kRedThreads) k_red1(const float* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void __launch_bounds__(kRedThreads) k_red2(const double* __restrict__ part, double* __restrict__ out) {
+__device__ __forceinline__ void k_red2_body(const double* __restrict__ part, double* __restrict__ out) {
   __shared__ double sh[kRedThreads];
   double acc = 0.0;
   for (int i = threadIdx.x; i < kRedBlocks; i += kRedThreads) acc += part[i];
@@ -305,6 +305,53 @@ __global__ void __launch_bounds__(kRedThreads) k_red2(const double* __restrict__
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = sh[0];
+}
+__global__ void __launch_bounds__(kRedThreads) k_red2(const double* __restrict__ part, double* __restrict__ out) {
+  k_red2_body(part, out);
+}
+
+// Batched residuals: block (b, i) runs k_red1<1>'s block b on pair i, so
+// that every pair's value equals the unbatched call's bitwise.
+constexpr int kResMax = 64;  // pairs per launch (kernel arguments)
+struct ResPairs {
+  const float* a[kResMax];
+  const float* b[kResMax];
+  float* r[kResMax];
+  long n[kResMax];
+};
+__global__ void __launch_bounds__(kRedThreads) k_res1_b(ResPairs P, double* __restrict__ part) {
+  const int i = blockIdx.y;
+  __shared__ double sh[kRedThreads];
+  const long n = P.n[i];
+  const float* __restrict__ a = P.a[i];
+  const float* __restrict__ b = P.b[i];
+  float* __restrict__ r = P.r[i];
+  const long chunk = (n + kRedBlocks - 1) / kRedBlocks;
+  const long beg = (long)blockIdx.x * chunk;
+  const long end = beg + chunk < n ? beg + chunk : n;
+  double acc = 0.0;
+  for (long k = beg + threadIdx.x; k < end; k += kRedThreads) {
+    const float d = a[k] - b[k];
+    r[k] = d;
+    acc += 0.5 * (double)d * (double)d;
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long)i * kRedBlocks + blockIdx.x] = sh[0];
+}
+// out[i] = k_red2 over pair i's partials; block i
+__global__ void __launch_bounds__(kRedThreads) k_res2_b(const double* __restrict__ part, double* __restrict__ out) {
+  k_red2_body(part + (long)blockIdx.x * kRedBlocks, out + blockIdx.x);
+}
+// out[count] = sum of out[0 .. count) in index order
+__global__ void k_res_sum(double* __restrict__ out, int count) {
+  double s = 0.0;
+  for (int i = 0; i < count; ++i) s += out[i];
+  out[count] = s;
 }
 
 // sum_j sqrt(|Lt x|_j^2 + rho^2) - rho, same fixed partition as k_red1
@@ -555,6 +602,34 @@ extern "C" int pat_dot_f64(const float* a, const float* b, int64_t n, double* ou
 extern "C" int pat_residual_f64(const float* a, const float* b, float* r, int64_t n, double* half_sq_host,
                                 void* stream) {
   return reduce_common(1, a, b, r, n, half_sq_host, (hipStream_t)stream);
+}
+
+extern "C" size_t pat_residual_batched_work_bytes(int32_t count) {
+  return count < 1 ? 0 : (size_t)count * kRedBlocks * sizeof(double);
+}
+
+extern "C" int pat_residual_f64_batched(int32_t count, const float* const* a, const float* const* b, float* const* r,
+                                        const int64_t* n, double* work_dev, double* out_dev, void* stream) {
+  if (count < 1 || count > 4096 || !a || !b || !r || !n || !work_dev || !out_dev) return PAT_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (n[i] < 0 || (n[i] > 0 && (!a[i] || !b[i] || !r[i]))) return PAT_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  for (int i0 = 0; i0 < count; i0 += kResMax) {
+    const int m = count - i0 < kResMax ? count - i0 : kResMax;
+    ResPairs P{};
+    for (int i = 0; i < m; ++i) {
+      P.a[i] = a[i0 + i];
+      P.b[i] = b[i0 + i];
+      P.r[i] = r[i0 + i];
+      P.n[i] = (long)n[i0 + i];
+    }
+    double* part = work_dev + (long)i0 * kRedBlocks;
+    hipLaunchKernelGGL(k_res1_b, dim3(kRedBlocks, m), dim3(kRedThreads), 0, st, P, part);
+    hipLaunchKernelGGL(k_res2_b, dim3(m), dim3(kRedThreads), 0, st, part, out_dev + i0);
+  }
+  hipLaunchKernelGGL(k_res_sum, dim3(1), dim3(1), 0, st, out_dev, count);
+  PAT_TRY_HIP(hipGetLastError());
+  return PAT_OK;
 }
 
 extern "C" int pat_tv_smooth(int32_t ndim, const int32_t n[3], const float* x, double rho, double scale, float* grad,

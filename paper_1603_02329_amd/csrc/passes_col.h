@@ -42,11 +42,6 @@ __device__ __forceinline__ float sinc_sqrt(float s) {
   return fmaf(p, s, 1.0f);
 }
 
-// |k|^(2e) from |k|^2 (e = (y-2)/2 or (y-1)/2): the absorption terms are
-// small corrections, so the hardware log2/exp2 suffice.
-__device__ __forceinline__ float kpow(float k2, float e) {
-  return k2 > 0.f ? __builtin_amdgcn_exp2f(e * __builtin_amdgcn_logf(k2)) : 0.f;
-}
 
 // the x-bin part of the multipliers, constant per column
 struct XBin {
@@ -337,8 +332,9 @@ __device__ __forceinline__ void colm_pass(const DevPlan& P, int tile_index, cons
     }
     if (!q.along_y) shyf = gld(SA ? P.shA[1] : P.shB[1], kyf);
   } else if constexpr (FAM == F_ABS) {
+    // log2 |k|^2 (-inf at k = 0, where both Laplacians vanish)
 #pragma unroll
-    for (int m = 0; m < E; ++m) gv[m] = k2at(m);
+    for (int m = 0; m < E; ++m) gv[m] = __builtin_amdgcn_logf(k2fix + k2at(m));
   }
   // window family: the x (and, along z, the y) factor of this column, the
   // x factor at x-bin nx/2 for the packed column 0, and the along-axis one
@@ -353,9 +349,13 @@ __device__ __forceinline__ void colm_pass(const DevPlan& P, int tile_index, cons
   // the staged twiddles, after the block's own loads (first read after the
   // barrier that ends the first transform's first stage)
   load_table<Sh::TWL, G::NTH>(tws, g_tw, [](int i) { return staged_src<NA, E>(i); });
-  // Laplacian factor of element m
-  auto lapl = [&](float k2, int which) -> float {
-    return (which == M_L1DT ? kpow(k2, ym2h) * inv_dt : kpow(k2, ym1h)) * scale;
+  // Laplacian factor |k|^(2e) = exp2(e log2 |k|^2), e = (y-2)/2 or (y-1)/2,
+  // times 1/dt for L1, from lk = log2 |k|^2: the absorption terms are small
+  // corrections, so the hardware log2/exp2 suffice
+  auto lapl = [&](float lk, int which) -> float {
+    const float e = which == M_L1DT ? ym2h : ym1h;
+    const float v = lk > -INFINITY ? __builtin_amdgcn_exp2f(e * lk) : 0.f;
+    return (which == M_L1DT ? v * inv_dt : v) * scale;
   };
   // staggered shift of derivative axis `axis` at element m, for this
   // column's x-bin (nyq: at x-bin nx/2)
@@ -369,7 +369,7 @@ __device__ __forceinline__ void colm_pass(const DevPlan& P, int tile_index, cons
     if constexpr (FAM == F_WIN) {
       return f2((nyq ? wfixN : wfix) * wv[m], 0.f);
     } else if constexpr (FAM == F_ABS) {
-      return f2(lapl((nyq ? k2fixN : k2fix) + gv[m], which), 0.f);
+      return f2(lapl(nyq ? __builtin_amdgcn_logf(k2fixN + k2at(m)) : gv[m], which), 0.f);
     } else {
       const float g = nyq ? sinc_sqrt(kap2 * (k2fixN + k2at(m))) * scale : gv[m];
       return scl2(g, shift(which, m, nyq));

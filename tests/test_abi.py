@@ -100,6 +100,19 @@ def test_null_plan_calls_are_rejected():
     out = ctypes.c_double(7.0)
     assert L.pat_dot_f64(None, None, 0, ctypes.byref(out), None) == pat.PAT_OK and out.value == 0.0
     assert L.pat_dot_f64(None, None, 5, ctypes.byref(out), None) == pat.PAT_EINVAL
+    # batched residuals: rejected before any device access
+    assert L.pat_residual_batched_work_bytes(48) == 48 * 512 * 8 and L.pat_residual_batched_work_bytes(0) == 0
+    ptrs = (ctypes.c_void_p * 2)(None, None)
+    ns = (ctypes.c_int64 * 2)(0, 0)
+    w = ctypes.c_void_p(8)  # never dereferenced: every call below fails its checks first
+    assert L.pat_residual_f64_batched(0, ptrs, ptrs, ptrs, ns, w, w, None) == pat.PAT_EINVAL
+    assert L.pat_residual_f64_batched(4097, ptrs, ptrs, ptrs, ns, w, w, None) == pat.PAT_EINVAL
+    assert L.pat_residual_f64_batched(2, None, ptrs, ptrs, ns, w, w, None) == pat.PAT_EINVAL
+    assert L.pat_residual_f64_batched(2, ptrs, ptrs, ptrs, ns, None, w, None) == pat.PAT_EINVAL
+    bad = (ctypes.c_int64 * 2)(0, -1)
+    assert L.pat_residual_f64_batched(2, ptrs, ptrs, ptrs, bad, w, w, None) == pat.PAT_EINVAL
+    some = (ctypes.c_int64 * 2)(0, 5)  # n > 0 with NULL pointers
+    assert L.pat_residual_f64_batched(2, ptrs, ptrs, ptrs, some, w, w, None) == pat.PAT_EINVAL
 
 
 def test_batch_entry_points_validate_on_host():

@@ -108,4 +108,6 @@ def test_batched_autograd_matches_the_oracle():
     torch.cuda.synchronize()
     for k in range(len(insts)):
         assert torch.equal(imgs[k], xs[k].grad), k
+    # the loss is the sum of the per-instance residual norms in index order
+    assert float(loss.detach()) == sum(pat.residual_f64(d, t)[1] for d, t in zip(datas, targets))
     batch.close()

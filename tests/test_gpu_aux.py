@@ -64,6 +64,31 @@ def test_dot_f64(n):
     assert abs(half - 0.5 * OT.norm2(a - b)) <= 1e-13 * half
 
 
+def test_residual_f64_batched_equals_single_calls():
+    """70 pairs (two launches of at most 64) of uneven sizes, empty ones
+    included: every r_i and 1/2 ||a_i - b_i||^2 equals pat_residual_f64's
+    bitwise, the last entry is their sum in index order, and nothing is
+    read back in between (one synchronisation at the end)."""
+    rng = np.random.default_rng(12)
+    sizes = [0, 1, 7, 511, 512, 513, 100_000, 614_400] + [int(x) for x in rng.integers(1, 200_000, size=62)]
+    As = [torch.from_numpy(rng.standard_normal(n).astype(np.float32)).to(DEV) for n in sizes]
+    Bs = [torch.from_numpy(rng.standard_normal(n).astype(np.float32)).to(DEV) for n in sizes]
+    Rs, out = pat.residual_f64_batched(As, Bs)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    total = 0.0
+    for k, (a, b) in enumerate(zip(As, Bs)):
+        r, half = pat.residual_f64(a, b)
+        assert torch.equal(Rs[k], r), k
+        assert out[k] == half, (k, out[k], half)
+        total += half
+    assert out[len(sizes)] == total
+    # a second call reuses a caller-provided workspace and output
+    work = torch.empty(pat.lib().pat_residual_batched_work_bytes(len(sizes)), dtype=torch.uint8, device=DEV)
+    _, out2 = pat.residual_f64_batched(As, Bs, work=work)
+    assert np.array_equal(out2.cpu().numpy(), out)
+
+
 @pytest.mark.parametrize("ndim", [2, 3])
 def test_tv_prox_batched_equals_single(ndim):
     """The batched prox (more images than one launch takes, mixed sizes,
