@@ -59,6 +59,27 @@ __device__ __forceinline__ void load_row_twiddles(RowTw<N>& tw, const Tw* __rest
   });
 }
 
+// The mirror bins of a row's packed spectrum: for element k = t + T m
+// (k != 0), element M - k, held by lane (T - t) mod T of the row's T lanes in
+// register E - 1 - m (t != 0), or by this lane in register (E - m) mod E
+// (t = 0).  Fetched by a cross-lane permute within the wavefront
+// (ds_bpermute) rather than a round trip through the row's LDS region.
+// Every lane of the wavefront must call it; the rows' lanes are aligned to
+// T within the wavefront.
+template <int T, int E>
+__device__ __forceinline__ void row_mirror(const float2 (&r)[E], float2 (&y)[E], int t) {
+  static_assert(T <= 64 && (T & (T - 1)) == 0 && (E & (E - 1)) == 0, "row lanes must tile the wavefront");
+  const int lane = (int)(threadIdx.x & 63);
+  const int src = ((lane & ~(T - 1)) | ((T - t) & (T - 1))) << 2;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const float2 v = r[E - 1 - m];
+    const float px = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v.x)));
+    const float py = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(v.y)));
+    y[m] = (t == 0) ? r[(E - m) & (E - 1)] : f2(px, py);
+  }
+}
+
 // Packed half spectrum of one row -> real row, as pairs (x[2n], x[2n+1]) at
 // n = t + T m.  Unnormalised inverse real DFT.
 // r holds the packed bins X[t + T m] on entry (already loaded) and the real
@@ -67,23 +88,22 @@ template <int N>
 __device__ __forceinline__ void c2r(float2 (&r)[RowGeo<N>::E], float2* L, int t, const RowTw<N>& tw) {
   using G = RowGeo<N>;
   constexpr int M = G::M, E = G::E, T = G::T;
-#pragma unroll
-  for (int m = 0; m < E; ++m) L[t + T * m] = r[m];
-  WaveSync::sync();
+  float2 y[E];
+  row_mirror<T, E>(r, y, t);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = t + T * m;
-    const float2 X = L[k];
+    const float2 X = r[m];
     if (k == 0) {
       r[m] = f2(X.x + X.y, X.x - X.y);
     } else {
-      const float2 Y = conjf2(L[M - k]);
+      const float2 Y = conjf2(y[m]);
       const float2 A = X + Y;
       const float2 B = twmul<+1>(X - Y, tw.u[k]);
       r[m] = A + mul_si<+1>(B);
     }
   }
-  WaveSync::sync();
+  WaveSync::sync();  // earlier readers of the row's region are done
   fft<M, E, +1, WaveSync, 1, TwStaged, true>(r, L, t, tw.s);
 }
 
@@ -94,18 +114,17 @@ __device__ __forceinline__ void r2c(float2 (&r)[RowGeo<N>::E], float2* __restric
   using G = RowGeo<N>;
   constexpr int M = G::M, E = G::E, T = G::T;
   fft<M, E, -1, WaveSync, 1, TwStaged, true>(r, L, t, tw.s);
-#pragma unroll
-  for (int m = 0; m < E; ++m) L[t + T * m] = r[m];
-  WaveSync::sync();
+  float2 y[E];
+  row_mirror<T, E>(r, y, t);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = t + T * m;
-    const float2 Z = L[k];
+    const float2 Z = r[m];
     float2 X;
     if (k == 0) {
       X = f2(Z.x + Z.y, Z.x - Z.y);
     } else {
-      const float2 Y = conjf2(L[M - k]);
+      const float2 Y = conjf2(y[m]);
       const float2 A = Z + Y;
       const float2 B = twmul<-1>(Z - Y, tw.u[k]);
       X = 0.5f * (A + mul_si<-1>(B));
@@ -298,15 +317,15 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
     float2 g[D][E], r[D][E], dr[E], c2[E], qx[E];
 #pragma unroll
     for (int j = 0; j < D; ++j) io.ld(P.S[1 + j], g[j]);
+    load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < D; ++j) c2r<N>(g[j], L, t, tws);
 #pragma unroll
     for (int j = 0; j < D; ++j) io.ld(P.r[j], r[j]);
     io.ld(P.dtr0, dr);
     if constexpr (K == R_FWD_2LL) io.ld(P.c2, c2);
     io.ldx(P.Q[0], qx);
-    load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < D; ++j) c2r<N>(g[j], L, t, tws);
     float2 sdiv[E], srho[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
