@@ -181,6 +181,9 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="streams for the groups (0: one per group)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="run only the isolated kernel-timing phase (for profiling it); no JSON line")
+    ap.add_argument("--passes-only", action="store_true",
+                    help="run the roofline phase and the isolated timing of every pass (for profiling "
+                         "them); prints the per-pass table, no JSON line")
     ap.add_argument("--time-pass", default=None,
                     help="direction:pass_index timed with HIP events (default: the forward velocity row pass, "
                          "0:1 in 2D, 0:3 in 3D)")
@@ -316,6 +319,10 @@ def main():
         return out
 
     pass_times = every_pass() if ndim == 2 else {}
+    if args.passes_only:
+        for (d, k), (us, by) in sorted(pass_times.items()):
+            log(f"pass {d}:{k}: {us:.2f} us/launch, {by / 1e6:.1f} MB, {by / (us * 1e-6) / 1e9:.0f} GB/s")
+        return
     batch = pat.Batch(plans, chunk=args.chunk, parts=args.parts, lanes=args.lanes)
     targets = [d.clone() for d in batch.forward(x_true)]
     tiles = []
