@@ -394,10 +394,12 @@ def main():
         plain_ms, plain_med, _ = timed(plain, args.plain_steps, 1, "plain (one instance at a time, eager)")
     value = total_gps / (ms / 1e3)
     achieved = k_bytes / (k_ms / 1e3) / 1e9 if k_ms > 0 else 0.0
+    # adjoint passes are named for the forward pass they transpose (the
+    # divergence's transpose carries the a_j multipliers, the gradient's b_j)
     names = {(0, 0): "col gradient", (0, 1): "row velocity", (0, 2): "col divergence", (0, 3): "row density",
              (0, 4): "col absorption", (0, 5): "row state+gather", (1, 0): "row adj-state+scatter",
-             (1, 1): "col adj-absorption", (1, 2): "row adj-density", (1, 3): "col adj-gradient",
-             (1, 4): "row adj-velocity", (1, 5): "col adj-divergence"}
+             (1, 1): "col adj-absorption", (1, 2): "row adj-density", (1, 3): "col adj-divergence",
+             (1, 4): "row adj-velocity", (1, 5): "col adj-gradient"}
     if ndim == 3:
         names = {(0, 3): "row velocity", (0, 7): "row density", (0, 11): "row state+gather"}
     step_bytes = value * b_alg / 1e9  # algorithmic GB/s of the whole step
