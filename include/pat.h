@@ -52,6 +52,15 @@ extern "C" {
                                    on k = 0, 0.42 + 0.5 cos(2 pi m/n) + 0.08 cos(4 pi m/n)
                                    (1 at k = 0, 0 at the Nyquist bin; real and even, so S
                                    is symmetric); pat_adjoint_atd also ends with S */
+#define PAT_EOS_INIT      0x10u /* lossy plans: start the density from the equation of
+                                   state at t = 0 (section III: with u(0) = 0 the tau term
+                                   vanishes, c0^2 (1 - eta L2) rho(0) = p0) instead of
+                                   rho(0) = p0 / c0^2; solved by six fixed-point steps
+                                   x <- p0/c0^2 + eta L2 x, and pat_adjoint applies their
+                                   exact transpose.  pat_plan_create returns PAT_EINVAL
+                                   when max |eta| |k|^(y-1) over the medium and the grid
+                                   exceeds 0.05 (six steps then no longer reach float
+                                   rounding).  Ignored for lossless plans and N_t = 1. */
 
 /* pat_batch_create_ex flags */
 #define PAT_BATCH_NO_FUSE 0x1u  /* keep every size class in launches of its own */
@@ -73,7 +82,7 @@ extern "C" {
  *  alpha_power  power-law exponent y of the absorption (section II-A-2);
  *               0 < y < 3, y != 1.  Ignored when alpha0_db is NULL.
  *  n_sensors    number of point detectors (>= 1).
- *  flags        PAT_NO_PML | PAT_CHECK_FINITE.
+ *  flags        PAT_NO_PML | PAT_CHECK_FINITE | PAT_SMOOTH_P0 | PAT_EOS_INIT.
  */
 typedef struct {
   int32_t ndim;

@@ -26,6 +26,7 @@ PAT_OK, PAT_EINVAL, PAT_EUNSTABLE, PAT_ENOMEM, PAT_EHIP, PAT_ENONFINITE, PAT_ENO
 PAT_NO_PML = 0x1
 PAT_CHECK_FINITE = 0x2
 PAT_SMOOTH_P0 = 0x8
+PAT_EOS_INIT = 0x10
 PAT_BATCH_NO_FUSE = 0x1
 PAT_BATCH_NO_STAGGER = 0x2
 
@@ -182,7 +183,8 @@ def make_desc(desc, n_sensors: int, check_finite: bool = False) -> CDesc:
     c.alpha_power = float(desc.alpha_power)
     c.n_sensors = int(n_sensors)
     c.flags = ((0 if getattr(desc, "pml", True) else PAT_NO_PML) | (PAT_CHECK_FINITE if check_finite else 0) |
-               (PAT_SMOOTH_P0 if getattr(desc, "smooth_p0", False) else 0))
+               (PAT_SMOOTH_P0 if getattr(desc, "smooth_p0", False) else 0) |
+               (PAT_EOS_INIT if getattr(desc, "section3_density", False) else 0))
     return c
 
 

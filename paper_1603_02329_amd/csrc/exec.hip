@@ -257,12 +257,45 @@ struct Runner {
     if (!rc) rc = launch_col_w(ColSpec{4, 1, {0, 0, 0}, 0}, ColVariant{0, 1}, st, nullptr, nullptr);
     return rc;
   }
-  // the forward's initial state, from S p0 when the plans smooth p0
-  int init(bool smooth, hipStream_t st) const {
-    if (!smooth) return row(R_FWD_INIT, StepArg{nullptr, 0}, st);
-    int rc = row(R_FILT_IN, StepArg{nullptr, 0}, st);
-    if (!rc) rc = window(st);
-    if (!rc) rc = row(R_FWD_INIT_F, StepArg{nullptr, 0}, st);
+  // S1 <- L2 S1 (|k|^(y-1) with the transforms' 1/N): one column pass in 2D,
+  // a y pass, the z pass and an inverse y pass in 3D
+  int lap2(hipStream_t st) const {
+    const ColSpec l{1, 1, {M_L2, 0, 0}, 1};
+    if (ndim == 2) return launch_col_w(l, ColVariant{0, 1}, st, nullptr, nullptr);
+    int rc = launch_col_w(ColSpec{3, 1, {0, 0, 0}, 1}, ColVariant{0, 1}, st, nullptr, nullptr);
+    if (!rc) rc = launch_col_w(l, ColVariant{0, 1}, st, nullptr, nullptr);
+    if (!rc) rc = launch_col_w(ColSpec{4, 1, {0, 0, 0}, 1}, ColVariant{0, 1}, st, nullptr, nullptr);
+    return rc;
+  }
+  // kEosSteps fixed-point steps of the t = 0 equation of state, forward
+  // (dir 0: the initial density) or transposed (dir 1: before the adjoint's
+  // final assembly)
+  int eos(int dir, hipStream_t st) const {
+    int rc = row(dir == 0 ? R_EOS_FWD_IN : R_EOS_ADJ_IN, StepArg{nullptr, 0}, st);
+    for (int k = 0; k < kEosSteps && !rc; ++k) {
+      rc = lap2(st);
+      if (!rc) rc = row(dir == 0 ? R_EOS_FWD : R_EOS_ADJ, StepArg{nullptr, k == kEosSteps - 1 ? 1 : 0}, st);
+    }
+    return rc;
+  }
+  // the forward's initial state, from S p0 when the plans smooth p0, the
+  // density from the t = 0 equation of state when they ask for it
+  int init(bool smooth, bool eos_init, hipStream_t st) const {
+    int rc;
+    if (!smooth) {
+      rc = row(R_FWD_INIT, StepArg{nullptr, 0}, st);
+    } else {
+      rc = row(R_FILT_IN, StepArg{nullptr, 0}, st);
+      if (!rc) rc = window(st);
+      if (!rc) rc = row(R_FWD_INIT_F, StepArg{nullptr, 0}, st);
+    }
+    if (!rc && eos_init) rc = eos(0, st);
+    return rc;
+  }
+  // the adjoint's final assembly (image from the transposed initial state)
+  int adj_final(bool eos_init, hipStream_t st) const {
+    int rc = eos_init ? eos(1, st) : PAT_OK;
+    if (!rc) rc = row(R_ADJ_FINAL, StepArg{nullptr, 0}, st);
     return rc;
   }
   // image <- S image (the adjoint's last operator when the plans smooth p0)
@@ -330,6 +363,11 @@ int set_io(const pat_plan* p, const float* in, float* out, hipStream_t st) {
 int reduce_blocks(long nsamples, long ns) { return (int)((nsamples * ns + 255) / 256); }
 
 bool smooths_p0(const pat_plan* p) { return (p->desc.flags & PAT_SMOOTH_P0) != 0; }
+// the density starts from the t = 0 equation of state (lossy plans with
+// PAT_EOS_INIT and more than one time sample)
+bool eos_init(const pat_plan* p) { return (p->desc.flags & PAT_EOS_INIT) && p->lossy && p->desc.nt > 1; }
+// the initial and final passes a plan needs (plans that share launches must agree)
+int ends_of(const pat_plan* p) { return (smooths_p0(p) ? 1 : 0) | (eos_init(p) ? 2 : 0); }
 
 }  // namespace
 }  // namespace pat
@@ -342,7 +380,7 @@ extern "C" int pat_forward(pat_plan* p, const float* p0, float* data, void* stre
   hipStream_t st = (hipStream_t)stream;
   const Runner R = eager_runner(p);
   int rc = set_io(p, p0, data, st);
-  if (!rc) rc = R.init(smooths_p0(p), st);
+  if (!rc) rc = R.init(smooths_p0(p), eos_init(p), st);
   if (!rc) rc = R.steps(0, 0, p->desc.nt - 1, st);
   if (!rc) rc = R.reduce(0, 0, st, reduce_blocks(p->desc.nt, p->desc.n_sensors));
   return rc;
@@ -358,7 +396,7 @@ extern "C" int pat_adjoint(pat_plan* p, const float* data, float* img, void* str
     rc = R.row(R_ADJ_SCATTER_ONLY, StepArg{nullptr, 0}, st);
   } else {
     rc = R.steps(1, 0, p->desc.nt - 1, st);
-    if (!rc) rc = R.row(R_ADJ_FINAL, StepArg{nullptr, 0}, st);
+    if (!rc) rc = R.adj_final(eos_init(p), st);
   }
   if (!rc) rc = R.smooth_out(smooths_p0(p), st);
   return rc;
@@ -393,7 +431,7 @@ extern "C" int pat_forward_range(pat_plan* p, const float* p0, float* data, int3
   if (rc) return rc;
   int s0;
   if (n_begin == 0) {
-    rc = R.init(smooths_p0(p), st);
+    rc = R.init(smooths_p0(p), eos_init(p), st);
     s0 = 0;
   } else {
     if (hipMemcpyAsync(state, state_io, p->state_bytes, hipMemcpyDeviceToDevice, st) != hipSuccess) return PAT_EHIP;
@@ -445,6 +483,7 @@ namespace {
 struct BatchClass {
   int ndim, nx, ny, nz, nt, lossy, ns_max;
   bool smooth_p0 = false;  // the instances smooth p0 (all or none of a class)
+  bool eos = false;        // ... start the density from the t = 0 equation of state
   // fused group: instances of several 2D sizes in every launch (nx, ny the
   // largest, nt - 1 = span = the most steps of any instance)
   int fused = 0;
@@ -642,7 +681,7 @@ int batch_run(pat_batch* b, int dir, const float* const* in, float* const* out, 
     hipEvent_t lead = (stagger && k == 0) ? b->lead : nullptr;
     const bool follow = stagger && (k & 1);
     if (dir == 0) {
-      rc = R.init(c.smooth_p0, c.st);
+      rc = R.init(c.smooth_p0, c.eos, c.st);
       if (!rc && follow && hipStreamWaitEvent(c.st, b->lead, 0) != hipSuccess) rc = PAT_EHIP;
       if (!rc) rc = run_steps(b, c, 0, c.nt - 1, lead);
       if (!rc) rc = R.reduce(0, 0, c.st, c.red_n);
@@ -652,7 +691,7 @@ int batch_run(pat_batch* b, int dir, const float* const* in, float* const* out, 
     } else {
       if (follow && hipStreamWaitEvent(c.st, b->lead, 0) != hipSuccess) rc = PAT_EHIP;
       if (!rc) rc = run_steps(b, c, 1, c.nt - 1, lead);
-      if (!rc) rc = R.row(R_ADJ_FINAL, StepArg{nullptr, 0}, c.st);
+      if (!rc) rc = R.adj_final(c.eos, c.st);
       if (!rc) rc = R.smooth_out(c.smooth_p0, c.st);
     }
     if (rc) return rc;
@@ -697,7 +736,7 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
     std::vector<std::vector<int>> shape_groups;
     for (int i = 0; i < nb; ++i) {
       const pat_plan* p = plans[i];
-      const auto key = std::make_tuple(p->hp.n[0], p->hp.n[1], p->hp.n[2], p->desc.nt, p->lossy, (int)smooths_p0(p));
+      const auto key = std::make_tuple(p->hp.n[0], p->hp.n[1], p->hp.n[2], p->desc.nt, p->lossy, ends_of(p));
       auto it = key2grp.find(key);
       if (it == key2grp.end()) {
         it = key2grp.emplace(key, (int)shape_groups.size()).first;
@@ -716,13 +755,13 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
     auto area = [&](const std::vector<int>& g) { return (long)plans[g[0]]->hp.n[0] * plans[g[0]]->hp.n[1]; };
     // the classes of one fused group share the pass sequence: the same
     // physics (lossy or not) and the same initial and final passes
-    for (int phys = 0; phys < 4; ++phys) {
+    for (int phys = 0; phys < 8; ++phys) {
       const int lossy = phys & 1;
-      const bool smooth = phys >> 1;
+      const int ends = phys >> 1;
       std::vector<int> fs;
       for (size_t k = 0; k < shape_groups.size(); ++k) {
         const pat_plan* p = plans[shape_groups[k][0]];
-        if (p->lossy == lossy && smooths_p0(p) == smooth && fusable(shape_groups[k])) fs.push_back((int)k);
+        if (p->lossy == lossy && ends_of(p) == ends && fusable(shape_groups[k])) fs.push_back((int)k);
       }
       if (fs.size() < 2) continue;
       std::stable_sort(fs.begin(), fs.end(), [&](int x, int y) {
@@ -763,6 +802,7 @@ extern "C" int pat_batch_create_ex(pat_batch** out, pat_plan* const* plans, int3
     c.nt = p0->desc.nt;
     c.lossy = p0->lossy;
     c.smooth_p0 = smooths_p0(p0);
+    c.eos = eos_init(p0);
     c.fused = group_fused[gi];
     c.ns_max = 0;
     for (int i : g) {

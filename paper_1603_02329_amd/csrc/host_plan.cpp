@@ -25,7 +25,7 @@ int validate_desc(const pat_desc* d, bool lossy) {
   if (!(d->pml_alpha >= 0) || !std::isfinite(d->pml_alpha)) return PAT_EINVAL;
   if (lossy && !(d->alpha_power > 0 && d->alpha_power < 3 && d->alpha_power != 1.0)) return PAT_EINVAL;
   if (d->n_sensors < 1) return PAT_EINVAL;
-  if (d->flags & ~(PAT_NO_PML | PAT_CHECK_FINITE | PAT_SMOOTH_P0)) return PAT_EINVAL;
+  if (d->flags & ~(PAT_NO_PML | PAT_CHECK_FINITE | PAT_SMOOTH_P0 | PAT_EOS_INIT)) return PAT_EINVAL;
   return PAT_OK;
 }
 

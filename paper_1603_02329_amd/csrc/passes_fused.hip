@@ -109,6 +109,10 @@ hipError_t launch_row_fused(RowKind kind, const Launch& L, StepArg s) {
     PAT_ROWF_CASE(R_FWD_INIT_F)
     PAT_ROWF_CASE(R_FILT_RE)
     PAT_ROWF_CASE(R_FILT_OUT)
+    PAT_ROWF_CASE(R_EOS_FWD_IN)
+    PAT_ROWF_CASE(R_EOS_FWD)
+    PAT_ROWF_CASE(R_EOS_ADJ_IN)
+    PAT_ROWF_CASE(R_EOS_ADJ)
     default: return hipErrorInvalidValue;
   }
 #undef PAT_ROWF_CASE
@@ -137,6 +141,8 @@ hipError_t launch_colf(const ColSpec& spec, int fpb, const Launch& L, StepArg s)
     PAT_COLF(2, 2, F_B, 1, 1);
   } else if (spec.mode == 1 && spec.nfield == 1 && fam == F_WIN && fpb == 1) {
     PAT_COLF(1, 1, F_WIN, 1, 1);
+  } else if (spec.mode == 1 && spec.nfield == 1 && fam == F_ABS && fpb == 1) {
+    PAT_COLF(1, 1, F_ABS, 1, 1);  // L2 alone: the initial density's fixed-point steps
   } else {
     return hipErrorInvalidValue;
   }

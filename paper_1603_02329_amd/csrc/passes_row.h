@@ -609,6 +609,84 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
     __syncthreads();
     c2r<N>(v, L, t, tws);
     io.st(P.out, v);
+  } else if constexpr (K == R_EOS_FWD_IN || K == R_EOS_FWD || K == R_EOS_ADJ_IN || K == R_EOS_ADJ) {
+    // eta = (c0^2 eta) / c0^2 at this row's points
+    auto eta_row = [&](float2 (&e)[E]) {
+      float2 c2[E], ce[E];
+      io.ld(P.c2, c2);
+      if (P.alpha_uniform) {
+        float2 ct[E];
+        absorption_coefs<E>(P, c2, ct, ce);
+      } else {
+        io.ld(P.c2eta, ce);
+      }
+#pragma unroll
+      for (int m = 0; m < E; ++m) e[m] = f2(ce[m].x / c2[m].x, ce[m].y / c2[m].y);
+    };
+    const bool last = (it == 1);
+    float2 x[E];
+    if constexpr (K == R_EOS_FWD_IN) {
+      io.ld(P.r[0], x);
+    } else if constexpr (K == R_EOS_ADJ_IN) {
+      io.ld(P.r[0], x);
+#pragma unroll
+      for (int j = 1; j < D; ++j) {
+        float2 rj[E];
+        io.ld(P.r[j], rj);
+#pragma unroll
+        for (int m = 0; m < E; ++m) x[m] = x[m] + rj[m];
+      }
+#pragma unroll
+      for (int m = 0; m < E; ++m) x[m] = (1.f / (float)D) * x[m];
+      io.st(P.q, x);
+      io.st(P.r[0], x);
+    } else {
+      io.ld(P.S[1], x);
+    }
+    load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
+    __syncthreads();
+    if constexpr (K == R_EOS_FWD || K == R_EOS_ADJ) {
+      // x <- b + [eta] F_x^-1 S1, b = r_1 (forward: p0 / (d c0^2)) or q
+      c2r<N>(x, L, t, tws);
+      float2 b[E];
+      io.ld(K == R_EOS_FWD ? P.r[1] : P.q, b);
+      if constexpr (K == R_EOS_FWD) {
+        float2 e[E];
+        eta_row(e);
+#pragma unroll
+        for (int m = 0; m < E; ++m) x[m] = b[m] + mul2(e[m], x[m]);
+      } else {
+#pragma unroll
+        for (int m = 0; m < E; ++m) x[m] = b[m] + x[m];
+      }
+      if (last) {
+        if constexpr (K == R_EOS_FWD) {
+#pragma unroll
+          for (int j = 0; j < D; ++j) io.st(P.r[j], x);
+        } else {
+          float2 z[E];
+#pragma unroll
+          for (int m = 0; m < E; ++m) {
+            z[m] = f2(0.f, 0.f);
+            x[m] = (float)D * x[m];
+          }
+          io.st(P.r[0], x);
+#pragma unroll
+          for (int j = 1; j < D; ++j) io.st(P.r[j], z);
+        }
+        return;  // block-uniform (it)
+      }
+      io.st(P.r[0], x);
+    }
+    // S1 <- F_x x (forward) or F_x (eta x) (adjoint)
+    if constexpr (K == R_EOS_ADJ_IN || K == R_EOS_ADJ) {
+      float2 e[E];
+      eta_row(e);
+#pragma unroll
+      for (int m = 0; m < E; ++m) x[m] = mul2(e[m], x[m]);
+    }
+    WaveSync::sync();
+    r2c<N>(x, P.S[1] + io.base, L, t, valid, tws);
   } else if constexpr (K == R_ADJ_FINAL || K == R_ADJ_SCATTER_ONLY) {
     float2 v[E], rs[E], ic[E];
     if constexpr (K == R_ADJ_FINAL) {

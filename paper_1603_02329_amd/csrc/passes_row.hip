@@ -80,6 +80,10 @@ static hipError_t launch_row_nd(RowKind kind, const Launch& L, StepArg s) {
     PAT_ROW_CASE(R_FWD_INIT_F)
     PAT_ROW_CASE(R_FILT_RE)
     PAT_ROW_CASE(R_FILT_OUT)
+    PAT_ROW_CASE(R_EOS_FWD_IN)
+    PAT_ROW_CASE(R_EOS_FWD)
+    PAT_ROW_CASE(R_EOS_ADJ_IN)
+    PAT_ROW_CASE(R_EOS_ADJ)
     default: return hipErrorInvalidValue;
   }
 #undef PAT_ROW_CASE

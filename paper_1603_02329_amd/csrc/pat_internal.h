@@ -15,6 +15,11 @@
 namespace pat {
 
 constexpr int kMaxDim = 3;
+// fixed-point steps of the t = 0 equation of state (PAT_EOS_INIT); plans
+// whose contraction max |eta| |k|^(y-1) exceeds kEosMaxContraction are
+// rejected: 0.05^7 < 1e-9, below float rounding
+constexpr int kEosSteps = 6;
+constexpr double kEosMaxContraction = 0.05;
 constexpr int TWN = 1024;  // twiddle table length: exp(-2 pi i q / TWN), q < TWN
 
 // Twiddle stored as an unevaluated float sum hi + lo (per component), so
@@ -154,7 +159,15 @@ enum RowKind : int32_t {
   R_FWD_INIT_F = 16, // R_FWD_INIT from the filtered p0 = F_x^-1 S0
   R_FILT_RE = 17,    // S0 <- F_x out        (adjoint: the image)
   R_FILT_OUT = 18,   // out <- F_x^-1 S0
-  R_COUNT = 19
+  // initial density from the equation of state at t = 0 (PAT_EOS_INIT),
+  // c0^2 (1 - eta L2) rho(0) = p0, by fixed-point steps x <- b + eta L2 x
+  // (forward) and y <- b + L2 (eta y) (adjoint), L2 applied by a column pass
+  // on S1 between two row passes; step_of() = 1 marks the last step
+  R_EOS_FWD_IN = 19,  // S1 <- F_x r_0 (r_j = p0 / (d c0^2) after R_FWD_INIT)
+  R_EOS_FWD = 20,     // r_0 <- r_1 + eta F_x^-1 S1; then S1 <- F_x r_0, or (last) every r_j <- r_0
+  R_EOS_ADJ_IN = 21,  // q <- sum_j r_j / d; r_0 <- q; S1 <- F_x (eta r_0)
+  R_EOS_ADJ = 22,     // r_0 <- q + F_x^-1 S1; then S1 <- F_x (eta r_0), or (last) r_0 <- d r_0, r_j <- 0 (j > 0)
+  R_COUNT = 23
 };
 
 hipError_t launch_row(RowKind kind, int ndim, int nx, const Launch& L, StepArg s);

@@ -176,6 +176,7 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
   const double y = d.alpha_power;
   const double a_conv = 100.0 * std::pow(1e-6 / (2.0 * M_PI), y) / (20.0 * std::log10(std::exp(1.0)));
   const double tan_y = std::tan(M_PI * y / 2.0);
+  double max_eta = 0.0;  // max |eta| over the medium (PAT_EOS_INIT's contraction)
   for (int64_t i = 0; i < N; ++i) {
     const double c = cd[i], r = rd[i];
     for (int j = 0; j < nd; ++j) {
@@ -192,6 +193,23 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
       const double eta = 2.0 * a0 * std::pow(c, y) * tan_y;
       hf(o_c2tau)[i] = (float)(c * c * tau);
       hf(o_c2eta)[i] = (float)(c * c * eta);
+      max_eta = std::max(max_eta, std::fabs(eta));
+    }
+  }
+  // PAT_EOS_INIT: the fixed-point steps x <- b + eta L2 x contract by at most
+  // max |eta| max_k |k|^(y-1) (|k| at the grid's corner for y > 1, the
+  // lowest nonzero |k| for y < 1)
+  if ((d.flags & PAT_EOS_INIT) && lossy && d.nt > 1) {
+    double kmax2 = 0.0, kmin = 1e300;
+    for (int j = 0; j < nd; ++j) {
+      kmax2 += (M_PI / d.dx[j]) * (M_PI / d.dx[j]);
+      kmin = std::min(kmin, 2.0 * M_PI / (d.n[j] * d.dx[j]));
+    }
+    const double kf = std::pow(y > 1.0 ? std::sqrt(kmax2) : kmin, y - 1.0);
+    if (!(max_eta * kf <= kEosMaxContraction)) {
+      hipFree(p->arena);
+      delete p;
+      return PAT_EINVAL;
     }
   }
   const bool pml_on = !(d.flags & PAT_NO_PML);

@@ -133,7 +133,9 @@ int main() {
       e = d; e.cfl = 0; CHECK(validate_desc(&e, true) == PAT_EINVAL, "cfl");
       e = d; e.alpha_power = 1.0; CHECK(validate_desc(&e, true) == PAT_EINVAL && validate_desc(&e, false) == PAT_OK, "y");
       e = d; e.n_sensors = 0; CHECK(validate_desc(&e, true) == PAT_EINVAL, "ns");
-      e = d; e.flags = 0x10; CHECK(validate_desc(&e, true) == PAT_EINVAL, "flags");
+      e = d; e.flags = 0x20; CHECK(validate_desc(&e, true) == PAT_EINVAL, "flags");
+      e = d; e.flags = 0x4; CHECK(validate_desc(&e, true) == PAT_EINVAL, "flags 0x4");
+      e = d; e.flags = PAT_EOS_INIT | PAT_SMOOTH_P0; CHECK(validate_desc(&e, true) == PAT_OK, "flags eos");
       e = d; e.ndim = 4; CHECK(validate_desc(&e, true) == PAT_EINVAL, "ndim");
       CHECK(validate_desc(nullptr, true) == PAT_EINVAL, "null");
       // stability

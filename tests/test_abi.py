@@ -72,12 +72,17 @@ def test_plan_create_rejects_bad_descriptors_on_host():
     dummy = ctypes.c_void_p(16)
     assert L.pat_plan_create(ctypes.byref(h), ctypes.byref(cd), dummy, dummy, dummy, (ctypes.c_double * 6)(),
                              None) == pat.PAT_EINVAL
-    # unknown plan flag (0x10 is the lowest undefined bit)
-    cd = pat.make_desc(base, 3)
-    cd.flags = pat.PAT_SMOOTH_P0 << 1
-    assert L.pat_plan_create(ctypes.byref(h), ctypes.byref(cd), dummy, dummy, None, (ctypes.c_double * 6)(),
-                             None) == pat.PAT_EINVAL
+    # unknown plan flags (0x4 and 0x20 are undefined)
+    for bad in (0x4, pat.PAT_EOS_INIT << 1):
+        cd = pat.make_desc(base, 3)
+        cd.flags = bad
+        assert L.pat_plan_create(ctypes.byref(h), ctypes.byref(cd), dummy, dummy, None, (ctypes.c_double * 6)(),
+                                 None) == pat.PAT_EINVAL
+        assert L.pat_desc_check(ctypes.byref(cd), 0, (ctypes.c_double * 6)(), 0.0) == pat.PAT_EINVAL
     assert pat.make_desc(replace(base, smooth_p0=True), 3).flags == pat.PAT_SMOOTH_P0
+    cd = pat.make_desc(replace(base, section3_density=True), 3)
+    assert cd.flags == pat.PAT_EOS_INIT
+    assert L.pat_desc_check(ctypes.byref(cd), 0, (ctypes.c_double * 6)(), 0.0) == pat.PAT_OK
     # NULL arguments
     cd = pat.make_desc(base, 3)
     assert L.pat_plan_create(ctypes.byref(h), ctypes.byref(cd), None, dummy, None, (ctypes.c_double * 6)(),

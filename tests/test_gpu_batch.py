@@ -129,26 +129,33 @@ def test_fused_mixed_physics_bitwise():
 
 @pytest.mark.parametrize("fuse", [True, False])
 def test_smoothed_p0_batch_bitwise(fuse):
-    """Plans that filter p0 beside plans that do not: the batch groups them
-    apart (their first and last passes differ), fuses the filtered 2D
-    classes among themselves, and equals the eager path bitwise; nt = 1
-    runs the filter after the sensor transpose.  A 3D batch likewise."""
+    """Plans that filter p0, or start the density from the t = 0 equation of
+    state, beside plans that do neither: the batch groups them apart (their
+    first and last passes differ), fuses the 2D classes that agree, and
+    equals the eager path bitwise; nt = 1 runs the filter after the sensor
+    transpose (and has no density).  A 3D batch likewise."""
     specs2 = [dict(n=(128, 128), nt=7, ns=5, pml=6, lossy=True, sm=True),
               dict(n=(256, 256), nt=11, ns=6, pml=8, lossy=True, sm=True),
               dict(n=(128, 128), nt=9, ns=4, pml=6, lossy=True, sm=False),
               dict(n=(256, 128), nt=5, ns=5, pml=6, lossy=False, sm=True),
               dict(n=(64, 64), nt=8, ns=4, pml=4, lossy=True, sm=True),
-              dict(n=(64, 64), nt=1, ns=4, pml=4, lossy=True, sm=True)]
+              dict(n=(64, 64), nt=1, ns=4, pml=4, lossy=True, sm=True),
+              dict(n=(128, 128), nt=7, ns=5, pml=6, lossy=True, sm=False, eos=True),
+              dict(n=(256, 256), nt=5, ns=3, pml=8, lossy=True, sm=False, eos=True),
+              dict(n=(128, 256), nt=6, ns=4, pml=6, lossy=True, sm=True, eos=True),
+              dict(n=(64, 64), nt=1, ns=4, pml=4, lossy=True, sm=False, eos=True)]
     specs3 = [dict(n=(16, 32, 16), nt=6, ns=5, pml=3, lossy=True, sm=True),
               dict(n=(16, 32, 16), nt=6, ns=4, pml=3, lossy=True, sm=False),
-              dict(n=(32, 16, 16), nt=5, ns=4, pml=2, lossy=False, sm=True)]
+              dict(n=(32, 16, 16), nt=5, ns=4, pml=2, lossy=False, sm=True),
+              dict(n=(16, 32, 16), nt=6, ns=4, pml=3, lossy=True, sm=False, eos=True)]
     for specs, seed in ((specs2, 900), (specs3, 920)):
         insts, plans = [], []
         for i, sp in enumerate(specs):
             sp = dict(sp)
             sm = sp.pop("sm")
+            eos = sp.pop("eos", False)
             inst = synth.small_instance(seed + i, **sp)
-            desc = replace(inst.desc, smooth_p0=sm)
+            desc = replace(inst.desc, smooth_p0=sm, section3_density=eos)
             insts.append(inst)
             plans.append(pat.Plan(desc, inst.c0, inst.rho0, inst.alpha0_db, inst.sensors, device=DEV))
         p0 = [torch.from_numpy(i.p0).to(DEV) for i in insts]

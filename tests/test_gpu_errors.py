@@ -67,3 +67,35 @@ def test_plan_create_rejects_bad_medium():
         with pytest.raises(pat.PatError) as e:
             pat.Plan(inst.desc, arrs["c0"], arrs["rho0"], arrs["alpha0_db"], inst.sensors, device=DEV)
         assert e.value.code == pat.PAT_EINVAL, field
+
+
+def _eos_contraction(inst):
+    """max |eta| max_k |k|^(y-1) of a lossy instance (eq. Twelve; the bound
+    the plan checks for PAT_EOS_INIT), in float64."""
+    d = inst.desc
+    y = d.alpha_power
+    a_conv = 100.0 * (1e-6 / (2 * math.pi)) ** y / (20.0 * math.log10(math.e))
+    a0 = inst.alpha0_db.astype(np.float64) * a_conv
+    eta = 2.0 * a0 * inst.c0.astype(np.float64) ** y * math.tan(math.pi * y / 2)
+    kmax = math.sqrt(sum((math.pi / dx) ** 2 for dx in d.dx))
+    return float(np.abs(eta).max()) * kmax ** (y - 1.0)
+
+
+@pytest.mark.parametrize("n", [(32, 32), (16, 16, 16)])
+def test_eos_init_rejects_slow_contraction(n):
+    """PAT_EOS_INIT: a medium whose max |eta| |k|^(y-1) exceeds 0.05 is
+    PAT_EINVAL (six fixed-point steps would not reach float rounding); just
+    below the bound the plan is created, and without the flag the strong
+    absorption is accepted."""
+    inst = synth.small_instance(43, n, nt=4, ns=3, lossy=True)
+    q = _eos_contraction(inst)
+    for f, ok in ((0.95, True), (1.05, False)):
+        a = (inst.alpha0_db.astype(np.float64) * (f * 0.05 / q)).astype(np.float32)
+        eos = synth.Instance(replace(inst.desc, section3_density=True), inst.c0, inst.rho0, a, inst.sensors, inst.p0)
+        if ok:
+            _create(eos).close()
+        else:
+            with pytest.raises(pat.PatError) as e:
+                _create(eos)
+            assert e.value.code == pat.PAT_EINVAL
+            _create(synth.Instance(inst.desc, inst.c0, inst.rho0, a, inst.sensors, inst.p0)).close()

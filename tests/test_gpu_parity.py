@@ -137,6 +137,34 @@ def test_smoothed_p0_parity(case):
         assert rel(ia, K.adjoint_atd(op, h)) <= 1e-5
 
 
+EOS_CASES = [
+    dict(n=(64, 32), nt=20, ns=6, pml=3, lossy=True, hetero=True),
+    dict(n=(16, 16), nt=2, ns=5, pml=3, lossy=True, hetero=True),
+    dict(n=(32, 32), nt=25, ns=6, pml=0, lossy=True, hetero=True, pml_on=False),
+    dict(n=(16, 32, 16), nt=10, ns=6, pml=3, lossy=True, hetero=True),
+]
+
+
+@pytest.mark.parametrize("case", EOS_CASES,
+                         ids=[f"{c['n']}-nt{c['nt']}{'-nopml' if c.get('pml_on') is False else ''}" for c in EOS_CASES])
+def test_eos_initial_density_parity(case):
+    """Plans whose density starts from the t = 0 equation of state
+    (PAT_EOS_INIT: six fixed-point steps of x <- p0/c0^2 + eta L2 x on the
+    GPU, their transpose in the adjoint) against the oracle's option, which
+    iterates to convergence: forward and adjoint; the option changes the
+    result."""
+    inst = synth.small_instance(170 + EOS_CASES.index(case), **case)
+    eo = synth.Instance(replace(inst.desc, section3_density=True), inst.c0, inst.rho0, inst.alpha0_db,
+                        inst.sensors, inst.p0, inst.name)
+    print("case", case, flush=True)
+    plan, d, img, rd, ri, h = run_pair(eo)
+    assert rel(d, rd) <= 1e-5
+    assert rel(img, ri) <= 1e-5
+    _, d0, img0, _, _, _ = run_pair(inst)
+    print("change", rel(d0, d), rel(img0, img), flush=True)
+    assert rel(d0, d) > 1e-5 and rel(img0, img) > 1e-5
+
+
 def test_smoothed_p0_segmented_forward_is_bitwise():
     """The filter runs in the first segment of a checkpointed forward: any
     split of the time axis reproduces the unsegmented data bitwise."""
@@ -153,20 +181,20 @@ def test_smoothed_p0_segmented_forward_is_bitwise():
     assert torch.equal(seg, full)
 
 
-@pytest.mark.parametrize("case", ["2d", "2d-smooth-p0", "3d"])
+@pytest.mark.parametrize("case", ["2d", "2d-smooth-p0", "2d-eos", "3d", "3d-eos"])
 def test_gpu_adjoint_is_dense_transpose_of_gpu_forward(case):
     """The GPU adjoint against the GPU forward itself: H built column by
     column from pat_forward on unit images, H^T row by row from pat_adjoint
     on unit data (lossy, heterogeneous, with PML); they agree entrywise to
     float32 rounding.  3D: 96 sampled columns of the 4096."""
-    if case == "3d":
+    if case.startswith("3d"):
         inst = synth.small_instance(160, (16, 16, 16), nt=5, ns=3, pml=2, lossy=True)
     else:
         inst = synth.small_instance(161, (16, 16), nt=6, ns=3, pml=3, lossy=True)
-    desc = replace(inst.desc, smooth_p0=(case == "2d-smooth-p0"))
+    desc = replace(inst.desc, smooth_p0=(case == "2d-smooth-p0"), section3_density=case.endswith("eos"))
     plan = pat.Plan(desc, inst.c0, inst.rho0, inst.alpha0_db, inst.sensors, device=DEV)
     N, M = plan.npoints, inst.desc.nt * inst.ns
-    cols = np.arange(N) if case != "3d" else np.sort(np.random.default_rng(4).choice(N, 96, replace=False))
+    cols = np.arange(N) if not case.startswith("3d") else np.sort(np.random.default_rng(4).choice(N, 96, replace=False))
     A = np.zeros((M, len(cols)))
     for j, i in enumerate(cols):
         e = torch.zeros(N, device=DEV)
