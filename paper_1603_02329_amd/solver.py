@@ -33,8 +33,8 @@ from typing import List, Optional
 
 from . import Batch, Plan, axpby, dot_f64, project, prolong, residual_f64, restrict, restrict_lower, tv_prox, tv_smooth
 
-__all__ = ["Level", "MGParams", "MGRecord", "power_iteration", "fista", "fista_batched", "coarse_fista", "coarse_mg",
-           "mg_fista"]
+__all__ = ["Level", "MGParams", "MGRecord", "IterState", "save_state", "load_state", "power_iteration", "fista",
+           "fista_batched", "coarse_fista", "coarse_mg", "mg_fista"]
 
 
 class Level:
@@ -102,15 +102,61 @@ def _direct(level: Level, y, prox_iter: int, g=None):
     return tv_prox(z, level.alpha * level.lam, prox_iter)
 
 
+@dataclass
+class IterState:
+    """What a FISTA or MG-FISTA run resumes from after its iteration k: the
+    iterate x_k (``x_prev``), the extrapolated point y_{k+1}, the momentum
+    t_{k+1} (Alg. FISTA), the history, and for MG-FISTA the counters K_d,
+    K_r and the last recursion point y-tilde (Alg. FISTAMG, eq.
+    conditions).  Every later iterate depends on these alone, so a resumed
+    run reproduces an uninterrupted one bitwise."""
+    k: int
+    x_prev: object
+    y: object
+    t: float
+    hist: list
+    k_d: int = 0
+    k_r: int = 0
+    y_tilde: object = None
+
+
+def save_state(path: str, state: IterState) -> None:
+    """Write an IterState to `path` (tensors and plain numbers only: it loads
+    with ``torch.load(weights_only=True)``)."""
+    import torch
+    hist = [r.__dict__.copy() if isinstance(r, MGRecord) else float(r) for r in state.hist]
+    blob = {"k": int(state.k), "x_prev": state.x_prev.detach().cpu(), "y": state.y.detach().cpu(), "t": float(state.t),
+            "hist": hist, "k_d": int(state.k_d), "k_r": int(state.k_r),
+            "y_tilde": None if state.y_tilde is None else state.y_tilde.detach().cpu()}
+    torch.save(blob, path)
+
+
+def load_state(path: str, device) -> IterState:
+    """Read an IterState written by ``save_state``, tensors on `device`."""
+    import torch
+    blob = torch.load(path, map_location="cpu", weights_only=True)
+    hist = [MGRecord(**r) if isinstance(r, dict) else float(r) for r in blob["hist"]]
+    yt = blob["y_tilde"]
+    return IterState(blob["k"], blob["x_prev"].to(device), blob["y"].to(device), blob["t"], hist, blob["k_d"],
+                     blob["k_r"], None if yt is None else yt.to(device))
+
+
 def fista(level: Level, x0, n_iter: int, momentum: bool = True, prox_iter: int = 20,
-          eps_d: Optional[float] = None, callback=None):
+          eps_d: Optional[float] = None, callback=None, state: Optional[IterState] = None, on_state=None):
     """Alg. FISTA (Alg. ISTA without momentum); returns (x, [F(x_k)]).
-    ``callback(k, x_k, F(x_k))`` runs after every iteration."""
-    x_prev = x0.clone()
-    y = x0.clone()
-    t = 1.0
-    hist: List[float] = []
-    for _ in range(n_iter):
+    ``callback(k, x_k, F(x_k))`` runs after every iteration.  `n_iter`
+    counts every iteration of the run; with `state` (an ``IterState`` from
+    an earlier call's ``on_state``, or ``load_state``) the run resumes after
+    its iteration ``state.k`` (x0 is then unused).  ``on_state(IterState)``
+    runs after every iteration (its tensors are the run's own: save or copy
+    them there)."""
+    if state is None:
+        x_prev, y, t, hist, k0 = x0.clone(), x0.clone(), 1.0, [], 0
+    else:
+        x_prev, y, t, hist, k0 = state.x_prev.clone(), state.y.clone(), state.t, list(state.hist), state.k
+    for _ in range(k0, n_iter):
+        if eps_d is not None and len(hist) > 1 and hist[-2] - hist[-1] < eps_d * max(hist[-2], hist[-1]):
+            break
         x = _direct(level, y, prox_iter)
         hist.append(level.objective(x))
         if callback is not None:
@@ -119,8 +165,8 @@ def fista(level: Level, x0, n_iter: int, momentum: bool = True, prox_iter: int =
         theta = (t - 1.0) / tn if momentum else 0.0
         y = axpby(1.0 + theta, x, -theta, x_prev)
         x_prev, t = x, tn
-        if eps_d is not None and len(hist) > 1 and hist[-2] - hist[-1] < eps_d * max(hist[-2], hist[-1]):
-            break
+        if on_state is not None:
+            on_state(IterState(len(hist), x_prev, y, t, list(hist)))
     return x_prev, hist
 
 
@@ -326,30 +372,37 @@ def coarse_mg(levels, i: int, x0, v, lower, p: MGParams, pairs=None):
     return x_prev, k, depth
 
 
-def mg_fista(fine: Level, coarse, x0, n_iter: int, params: MGParams = MGParams(), callback=None):
+def mg_fista(fine: Level, coarse, x0, n_iter: int, params: MGParams = MGParams(), callback=None,
+             state: Optional[IterState] = None, on_state=None):
     """Alg. FISTAMG; ``coarse`` is the next coarse level, or a list of levels
     from the next coarse one down (more than two levels).  Returns (x,
-    [MGRecord]); ``callback(k, x_k, record)`` runs after every iteration."""
+    [MGRecord]); ``callback(k, x_k, record)`` runs after every iteration.
+    `n_iter`, `state` and `on_state` as in ``fista`` (the state carries the
+    decision rule's K_d, K_r and y-tilde as well)."""
     levels = [fine] + (list(coarse) if isinstance(coarse, (list, tuple)) else [coarse])
     p = params
     pairs = {}
     try:
-        return _mg_fista(levels, x0, n_iter, p, callback, pairs)
+        return _mg_fista(levels, x0, n_iter, p, callback, pairs, state, on_state)
     finally:
         for pr in pairs.values():
             if pr is not None:
                 pr.close()
 
 
-def _mg_fista(levels, x0, n_iter: int, p: MGParams, callback, pairs):
+def _mg_fista(levels, x0, n_iter: int, p: MGParams, callback, pairs, state=None, on_state=None):
     fine = levels[0]
-    x_prev = x0.clone()
-    y = x0.clone()
-    t = 1.0
-    k_d = k_r = 0
-    y_tilde = None
-    hist: List[MGRecord] = []
-    for k in range(1, n_iter + 1):
+    if state is None:
+        x_prev, y, t, k_d, k_r, y_tilde, k0 = x0.clone(), x0.clone(), 1.0, 0, 0, None, 0
+        hist: List[MGRecord] = []
+    else:
+        x_prev, y, t, k_d, k_r, k0 = state.x_prev.clone(), state.y.clone(), state.t, state.k_d, state.k_r, state.k
+        y_tilde = None if state.y_tilde is None else state.y_tilde.clone()
+        hist = list(state.hist)
+    for k in range(k0 + 1, n_iter + 1):
+        if p.eps_d is not None and len(hist) > 1 and \
+                hist[-2].F - hist[-1].F < p.eps_d * max(hist[-2].F, hist[-1].F):
+            break
         recursive = False
         ratio = 0.0
         rg = gf = None
@@ -390,7 +443,6 @@ def _mg_fista(levels, x0, n_iter: int, p: MGParams, callback, pairs):
         theta = (t - 1.0) / tn if p.momentum else 0.0
         y = axpby(1.0 + theta, x, -theta, x_prev)
         x_prev, t = x, tn
-        if p.eps_d is not None and len(hist) > 1 and \
-                hist[-2].F - hist[-1].F < p.eps_d * max(hist[-2].F, hist[-1].F):
-            break
+        if on_state is not None:
+            on_state(IterState(k, x_prev, y, t, list(hist), k_d, k_r, y_tilde))
     return x_prev, hist
