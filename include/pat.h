@@ -307,11 +307,14 @@ int pat_adjoint_batched(pat_plan* const* plans, int32_t nb, const float* const* 
  * device buffers and timed with HIP events.  A batch of several groups
  * then runs its groups at the same time, where a variant that wins alone can
  * lose (a wide workgroup needs a whole CU's worth of LDS), so a second phase
- * times width policies in context: each policy (the fastest variant; the
- * fastest of width <= 8; of width <= 4; of width 8) is applied to every
- * tuned pass and timed on a short concurrent run of forward steps of all
- * groups (the longest time axis 4 x chunk steps, the others in proportion);
- * the fastest policy is used from then on.  Results stay bitwise equal to
+ * times width policies in context: each policy (width 8 with one field per
+ * workgroup; the fastest variant; the fastest of width <= 8; of width <= 4;
+ * of width 8) is applied to every tuned pass and timed on a short concurrent
+ * run of forward steps of all groups (the longest time axis 4 x chunk steps,
+ * the others in proportion), the policies taking turns over three rounds,
+ * the best run of each counting.  The first policy is kept unless another
+ * runs at least 0.5 % faster; the policy kept is used from then on.
+ * Results stay bitwise equal to
  * pat_forward / pat_adjoint: a variant only changes how columns and fields
  * are grouped into workgroups.
  *
