@@ -47,6 +47,37 @@ def test_batch_matches_eager_bitwise(chunk, parts, lanes):
     b.close()
 
 
+def test_batches_sharing_lanes_match_eager_bitwise():
+    """Batches alive at the same time share the device's lane streams: a
+    one-lane, a two-lane and a three-lane batch (the pool grows to three),
+    each over plans of its own, called on two caller streams so that their
+    work interleaves on the shared lanes, each keep their results bitwise
+    those of the eager path."""
+    insts = _instances()
+    sets = [[pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=DEV) for i in insts] for _ in range(3)]
+    p0 = [torch.from_numpy(i.p0).to(DEV) for i in insts]
+    ref_d = [p.forward(x).clone() for p, x in zip(sets[0], p0)]
+    rng = np.random.default_rng(5)
+    hs = [torch.from_numpy(rng.standard_normal((i.desc.nt, i.ns)).astype(np.float32)).to(DEV) for i in insts]
+    ref_i = [p.adjoint(h).clone() for p, h in zip(sets[0], hs)]
+    batches = [pat.Batch(sets[0], chunk=4, parts=1, lanes=1), pat.Batch(sets[1], chunk=4, parts=2, lanes=2),
+               pat.Batch(sets[2], chunk=3, parts=3, lanes=3)]
+    main, side = torch.cuda.current_stream(), torch.cuda.Stream()
+    side.wait_stream(main)
+    for rep in range(2):
+        outs = []
+        for j, b in enumerate(batches):
+            with torch.cuda.stream(side if j % 2 else main):
+                outs.append((b.forward(p0), b.adjoint(hs)))
+        torch.cuda.synchronize()
+        for j, (d, im) in enumerate(outs):
+            for k in range(len(insts)):
+                assert torch.equal(d[k], ref_d[k]), (rep, j, k)
+                assert torch.equal(im[k], ref_i[k]), (rep, j, k)
+    for b in batches:
+        b.close()
+
+
 def _fused_instances(lossy):
     """2D size classes with axes of 128, 256 and 512 points (fused into
     shared launches), different time axes, non-square grids, and a class of
