@@ -252,7 +252,11 @@ int pat_batch_create(pat_batch** out, pat_plan* const* plans, int32_t nb, int32_
  *   tables, and the groups run on `lanes` streams (0: one per group; with
  *   fewer streams than groups, the groups are placed heaviest first, by grid
  *   points x time steps, on the least-loaded stream).  Groups on different
- *   streams overlap on the GPU.
+ *   streams overlap on the GPU.  The streams come from a per-device pool
+ *   that every batch shares (created by the first batch, two at a time, and
+ *   kept until the process ends), so batches created later do not add
+ *   hardware-queue mappings of their own; the work of batches called on
+ *   different caller streams may interleave on them.
  *   Fusion (default; flags PAT_BATCH_NO_FUSE turns it off): 2D size classes
  *   whose axes are 128, 256 or 512 points long, with the same physics and
  *   nt >= 2, share their launches -- part k of each such class joins fused
