@@ -61,6 +61,63 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def scaling_probe(insts, pat, torch, dev):
+    """Fixed and marginal cost of the batched step.  (1) Forward + adjoint of
+    the first k instances of every size class, k = 2, 4, 8, 16, each batch
+    with the default grouping (two groups on two streams), autotuned, the
+    best of three timed calls.  (2) The launch time of every pass against the
+    number of 512^2 instances in the launch: a one-stream batch of one group
+    over the first 1, 2, 4, 8, 16 of them, each pass launched back to back
+    (10 untimed, then 50 timed with HIP events)."""
+    by = {}
+    for i in insts:
+        by.setdefault(tuple(i.desc.n), []).append(i)
+    print("instances per class, ms per forward + adjoint (best of 3), G grid-point-steps/s")
+    for k in (2, 4, 8, 16):
+        sel = [i for n in sorted(by) for i in by[n][:k]]
+        plans = [pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=dev) for i in sel]
+        p0 = [torch.from_numpy(i.p0).to(dev) for i in sel]
+        gps = sum(2.0 * p.npoints * p.nt for p in plans)
+        b = pat.Batch(plans)
+        d = b.forward(p0)
+        b.autotune(reps=10)
+        d = b.forward(p0)
+        b.adjoint(d)
+        best = float("inf")
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            d = b.forward(p0)
+            b.adjoint(d)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        print(f"{k:3d}  {best:8.1f}  {gps / best / 1e6:6.2f}", flush=True)
+        b.close()
+        del b, plans, p0, d
+    big = by[max(by)]
+    names = ["c-grad", "r-vel", "c-div", "r-dens", "c-abs", "r-state", "c-aabs", "r-adens", "c-adiv", "r-avel",
+             "c-agrad"]
+    keys = [(0, 0), (0, 1), (0, 2), (0, 3), (0, 4), (0, 5), (1, 1), (1, 2), (1, 3), (1, 4), (1, 5)]
+    n = big[0].desc.n[0]
+    print(f"\n{n}^2 instances per launch, us per launch (one stream, back-to-back launches)")
+    print("  k " + " ".join(f"{x:>8s}" for x in names))
+    for k in (1, 2, 4, 8, 16):
+        sel = big[:k]
+        plans = [pat.Plan(i.desc, i.c0, i.rho0, i.alpha0_db, i.sensors, device=dev) for i in sel]
+        p0 = [torch.from_numpy(i.p0).to(dev) for i in sel]
+        b = pat.Batch(plans, chunk=1, parts=1, lanes=1)
+        b.adjoint(b.forward(p0))
+        b.autotune(reps=10)
+        row = []
+        for d_, i_ in keys:
+            b.time_pass(d_, i_, n, 10)
+            row.append(b.time_pass(d_, i_, n, 50)[0])
+        print(f"{k:3d} " + " ".join(f"{u:8.2f}" for u in row), flush=True)
+        b.close()
+        del b, plans, p0
+
+
 def fused_batch(plans) -> bool:
     """Whether the library's batch of these plans fuses its size classes
     into shared launches (2D, both axes 128/256/512, nt >= 2, more than one
@@ -193,6 +250,11 @@ def main():
     ap.add_argument("--sync-probe", action="store_true",
                     help="diagnostic: cost of a grid-wide barrier in a cooperative launch against a kernel "
                          "boundary (stream and graph), for several grid sizes and amounts of work; no JSON line")
+    ap.add_argument("--scaling-probe", action="store_true",
+                    help="diagnostic (2D): forward + adjoint time of the first k instances of every size class "
+                         "(k = 2, 4, 8, 16; two groups on two streams), and the launch time of every pass "
+                         "against the number of 512^2 instances in the launch (1 to 16; one stream); no JSON "
+                         "line")
     ap.add_argument("--pmc-step", action="store_true",
                     help="counter probe of a whole step: the calibration copy, then one forward and one "
                          "adjoint of the workload with the time axes cut to a tenth, every pass launched "
@@ -226,6 +288,9 @@ def main():
                       flush=True)
         return
     insts, wl_name = workload(args.workload)
+    if args.scaling_probe:
+        scaling_probe(insts, pat, torch, dev)
+        return
     if args.pmc_step:
         # the same instances with a tenth of their time axes: the size
         # classes keep their step ratios, so each step of a fused group
