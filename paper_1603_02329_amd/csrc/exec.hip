@@ -548,10 +548,9 @@ struct BatchClass {
 
 }  // namespace
 
-// Width policies of the autotuner's second phase: how a pass's variant is
-// chosen from its isolated timings.
-// Width policies of the in-context phase.  The first is the incumbent: 8
-// columns, one field per block (the fused passes' untuned default).
+// Width policies of the autotuner's second (in-context) phase: how a pass's
+// variant is chosen from its isolated timings.  The first is the incumbent:
+// 8 columns, one field per block (the fused passes' untuned default).
 enum TunePolicy : int { TP_EXACT8_F1 = 0, TP_FASTEST, TP_MAX8, TP_MAX4, TP_EXACT8, TP_COUNT };
 const char* const kPolicyName[TP_COUNT] = {"width=8,fpb=1", "fastest", "width<=8", "width<=4", "width=8"};
 // a policy replaces the incumbent only when it runs this much faster
