@@ -209,17 +209,21 @@ struct SyncOf<true> {
   using type = WaveSync;
 };
 
-// Fields a column pass transforms side by side (FftStageK): the forward
-// transforms of mode 1 (FPB fields) and of a two-input mode 2, the inverse
-// transforms of mode 1 and of a two-output mode 0.  Three-field passes (3D)
-// take their fields one at a time.
+// Fields a column pass transforms side by side (FftStageK): the forward and
+// inverse transforms of mode 1 (FPB fields) and the inverse transforms of a
+// two-output mode 0.  Mode 2 takes its inputs one at a time: with one set of
+// LDS regions (45 KB instead of 82 KB for a 512-point tile of 8 columns) its
+// blocks fit beside the other group's, which outweighs the pairing (the
+// 48-instance batch's adjoint 1.7 % faster, same-box A/B); the gradient keeps
+// its pair, whose sequential form holds 137 instead of 102 VGPRs.
+// Three-field passes (3D) take their fields one at a time.
 // Tiles whose two sets of regions would take more than 80 KB of LDS (512
 // points, 16 columns) transform one field at a time.
 template <int NA, int TW>
 constexpr bool col_pair_fits() { return ColGeo<NA, TW>::TILE * (NA + NA / 8 - 1) * 16 <= 81920; }
 template <int NA, int TW, int MODE, int NF, int FPB>
 constexpr int col_kf() {
-  return !col_pair_fits<NA, TW>() ? 1 : MODE == 1 ? FPB : (MODE == 2 && NF == 2 ? 2 : 1);
+  return !col_pair_fits<NA, TW>() ? 1 : MODE == 1 ? FPB : 1;
 }
 template <int NA, int TW, int MODE, int NF, int FPB>
 constexpr int col_ki() {
