@@ -210,13 +210,17 @@ struct SyncOf<true> {
 };
 
 // Fields a column pass transforms side by side (FftStageK): the forward and
-// inverse transforms of mode 1 (FPB fields) and the inverse transforms of a
-// two-output mode 0.  Mode 2 takes its inputs one at a time: with one set of
-// LDS regions (45 KB instead of 82 KB for a 512-point tile of 8 columns) its
-// blocks fit beside the other group's, which outweighs the pairing (the
-// 48-instance batch's adjoint 1.7 % faster, same-box A/B); the gradient keeps
-// its pair, whose sequential form holds 137 instead of 102 VGPRs.
-// Three-field passes (3D) take their fields one at a time.
+// inverse transforms of mode 1 (FPB fields).  Modes 0 and 2 take their
+// outputs / inputs one at a time: with one set of LDS regions (45 KB instead
+// of 82 KB for a 512-point tile of 8 columns) their blocks fit beside the
+// other group's in a batch, which outweighs the pairing (same-box A/B on the
+// 48-instance batch: the adjoint 1.7 % faster with mode 2 sequential, then
+// the forward 1.5 % faster with mode 0 sequential).  A two-output mode 0
+// applies both multipliers before its first inverse transform, so that only
+// the second product, not the spectrum and the multiplier operands, waits
+// in registers through it (109 VGPRs; 137 when each output was formed just
+// before its transform).  Three-field passes (3D) take their fields one at
+// a time.
 // Tiles whose two sets of regions would take more than 80 KB of LDS (512
 // points, 16 columns) transform one field at a time.
 template <int NA, int TW>
@@ -227,7 +231,7 @@ constexpr int col_kf() {
 }
 template <int NA, int TW, int MODE, int NF, int FPB>
 constexpr int col_ki() {
-  return !col_pair_fits<NA, TW>() ? 1 : MODE == 1 ? FPB : (MODE == 0 && NF == 2 ? 2 : 1);
+  return !col_pair_fits<NA, TW>() ? 1 : MODE == 1 ? FPB : 1;
 }
 template <int NA, int TW, int MODE, int NF, int FPB>
 constexpr int col_k() {
@@ -238,9 +242,10 @@ constexpr int col_k() {
 // The spectrum of packed column 0 (the source of its mirror bins) is kept in
 // that column's own region of each set, free between the forward and the
 // inverse transforms, unless a mode-0 pass needs it across several groups of
-// inverse transforms: then in an array of its own.
+// inverse transforms (the three-output 3D gradient, which forms each product
+// just before its transform): then in an array of its own.
 template <int NA, int TW, int MODE, int NF, int FPB>
-constexpr bool col_sep_mirror() { return MODE == 0 && NF > col_ki<NA, TW, MODE, NF, FPB>(); }
+constexpr bool col_sep_mirror() { return MODE == 0 && NF > 2 && NF > col_ki<NA, TW, MODE, NF, FPB>(); }
 
 // LDS of one column-pass block: K sets of the tile's column regions (padded
 // exchange; the odd stride spreads the columns over the banks), the mirror
@@ -491,6 +496,18 @@ __device__ __forceinline__ void colm_pass(const DevPlan& P, int tile_index, cons
     float2 v[1][E], s[1][E];
     take(0, v);
     forward(v, s, true);
+    if constexpr (NF == 2 && KI == 1) {  // both products first, then the two inverse transforms
+      float2 acc[2][1][E];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) acc[i][0][m] = f2(0.f, 0.f);
+        apply(which_of(i), s[0], acc[i][0], 0);
+      }
+      inverse_store(acc[0], [&](int) { return out_ptr(0); }, false);
+      inverse_store(acc[1], [&](int) { return out_ptr(1); }, true);
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < NF; i += KI) {
       float2 acc[KI][E];
