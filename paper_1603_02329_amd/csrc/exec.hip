@@ -169,6 +169,35 @@ __global__ void k_set_io_many(DevPlan* recs, int nb, IoArgs a) {
     recs[i].out = a.out[i];
   }
 }
+// W^T h of every sample, one sum per node group of the scatter operator (a
+// grid node that sensor taps land on), for the adjoint state passes: their
+// step's sums are then two independent loads per lane, issued before the
+// step's transform, instead of a chain of four dependent loads after it.
+// The sums run over a group's taps in the order the passes used (bitwise
+// the same values).  Block row y: plan y of `plans`.
+constexpr int kScatterThreads = 256;
+__global__ void __launch_bounds__(kScatterThreads) k_scatter_sums(const DevPlan* __restrict__ plans) {
+  const DevPlan& P = plans[blockIdx.y];
+  const long total = (long)P.nt * P.ngroups;
+  for (long i = (long)blockIdx.x * kScatterThreads + threadIdx.x; i < total; i += (long)gridDim.x * kScatterThreads) {
+    const int n = (int)(i / P.ngroups), g = (int)(i - (long)n * P.ngroups);
+    const SGroup grp = P.s_grp[g];
+    const float* h = P.in + (long)n * P.ns;
+    float acc = 0.f;
+    for (int e = grp.beg; e < grp.end; ++e) {
+      const STap tp = P.s_tap[e];
+      acc = fmaf(tp.w, h[tp.s], acc);
+    }
+    P.sc[i] = acc;
+  }
+}
+int scatter_sums(const DevPlan* recs, int nplans, long max_total, hipStream_t st) {
+  if (nplans < 1 || max_total < 1) return PAT_OK;
+  const int nb = (int)std::min<long>(1024, (max_total + kScatterThreads - 1) / kScatterThreads);
+  hipLaunchKernelGGL(k_scatter_sums, dim3(nb, nplans), dim3(kScatterThreads), 0, st, recs);
+  return hipGetLastError() == hipSuccess ? PAT_OK : PAT_EHIP;
+}
+
 __global__ void k_set_ctr(int32_t* c, int v) { *c = v; }
 __global__ void k_add_ctr(int32_t* c, int v) { *c += v; }
 
@@ -395,7 +424,8 @@ extern "C" int pat_adjoint(pat_plan* p, const float* data, float* img, void* str
   if (p->desc.nt == 1) {
     rc = R.row(R_ADJ_SCATTER_ONLY, StepArg{nullptr, 0}, st);
   } else {
-    rc = R.steps(1, 0, p->desc.nt - 1, st);
+    rc = scatter_sums(p->dp, 1, (long)p->desc.nt * p->hp.ngroups, st);
+    if (!rc) rc = R.steps(1, 0, p->desc.nt - 1, st);
     if (!rc) rc = R.adj_final(eos_init(p), st);
   }
   if (!rc) rc = R.smooth_out(smooths_p0(p), st);
@@ -719,7 +749,10 @@ int batch_run(pat_batch* b, int dir, const float* const* in, float* const* out, 
       rc = R.row(R_ADJ_SCATTER_ONLY, StepArg{nullptr, 0}, c.st);
       if (!rc) rc = R.smooth_out(c.smooth_p0, c.st);
     } else {
-      if (follow && hipStreamWaitEvent(c.st, b->lead, 0) != hipSuccess) rc = PAT_EHIP;
+      long most = 0;
+      for (auto* pl : c.plans) most = std::max(most, (long)pl->desc.nt * pl->hp.ngroups);
+      rc = scatter_sums(c.recs, (int)c.plans.size(), most, c.st);
+      if (!rc && follow && hipStreamWaitEvent(c.st, b->lead, 0) != hipSuccess) rc = PAT_EHIP;
       if (!rc) rc = run_steps(b, c, 1, c.nt - 1, lead);
       if (!rc) rc = R.adj_final(c.eos, c.st);
       if (!rc) rc = R.smooth_out(c.smooth_p0, c.st);

@@ -424,12 +424,33 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
         if (first) io.zero(rb[j]); else io.ld(P.r[j], rb[j]);
       }
     }
+    // W^T h[nsamp] for this row: the sums of the row's node groups, formed
+    // before the time loop (k_scatter_sums).  The group range is loaded with
+    // the pass's inputs, this lane's first group and its sum once they have
+    // arrived, so that those loads complete during the transform.
+    int sp0 = 0, sp1 = 0;
+    if (valid) {
+      sp0 = gld(P.s_ptr, rowc) + t;
+      sp1 = gld(P.s_ptr, rowc + 1);
+    }
     load_row_twiddles<N, ROWS * T>(tws, g_tw);  // after the pass's own loads
     __syncthreads();
+    const float* sc = P.sc + (long)nsamp * P.ngroups;
+    int sx = -1;
+    float sv = 0.f;
+    if (valid && sp0 < sp1) {
+      sx = gld(P.s_grp, sp0).x;
+      sv = gld(sc, sp0);
+    }
     if (!first) c2r<N>(v, L, t, tws);
 #pragma unroll
     for (int m = 0; m < E; ++m) L[t + T * m] = v[m];
-    scatter_row<N>(P, nsamp, Lf, rowc, t, valid);
+    WaveSync::sync();
+    if (sx >= 0) {
+      Lf[sx] += sv;
+      for (int g = sp0 + T; g < sp1; g += T) Lf[gld(P.s_grp, g).x] += gld(sc, g);
+    }
+    WaveSync::sync();
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = L[t + T * m];
     WaveSync::sync();

@@ -77,6 +77,8 @@ struct DevPlan {
   const int32_t* s_ptr;   // [nrows + 1]
   const SGroup* s_grp;
   const STap* s_tap;
+  float* sc;                // [nt][ngroups]: W^T h of every sample per node group (adjoint, formed per call)
+  int32_t ngroups;          // node groups of the scatter operator
   const int32_t* slot_ptr;  // [ns + 1]
   float* partial;           // [nt][nslots]
   int32_t* bad;             // non-finite flag (PAT_CHECK_FINITE)

@@ -156,6 +156,7 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
   const size_t o_gptr = cv.take<int32_t>(so.g_ptr.size()), o_gtap = cv.take<GTap>(std::max<size_t>(1, so.g_tap.size()));
   const size_t o_sptr = cv.take<int32_t>(so.s_ptr.size()), o_sgrp = cv.take<SGroup>(std::max<size_t>(1, so.s_grp.size()));
   const size_t o_stap = cv.take<STap>(std::max<size_t>(1, so.s_tap.size()));
+  const size_t o_sc = cv.take<float>(std::max<size_t>(1, (size_t)d.nt * so.s_grp.size()));
   const size_t o_slot = cv.take<int32_t>(so.slot_ptr.size());
   const size_t o_part = cv.take<float>((size_t)d.nt * so.nslots);
   const size_t o_bad = cv.take<int32_t>(1);
@@ -306,6 +307,8 @@ extern "C" int pat_plan_create(pat_plan** out, const pat_desc* desc, const float
   h.s_ptr = (const int32_t*)(A + o_sptr);
   h.s_grp = (const SGroup*)(A + o_sgrp);
   h.s_tap = (const STap*)(A + o_stap);
+  h.sc = (float*)(A + o_sc);
+  h.ngroups = (int32_t)so.s_grp.size();
   h.slot_ptr = (const int32_t*)(A + o_slot);
   h.partial = (float*)(A + o_part);
   h.bad = (int32_t*)(A + o_bad);
