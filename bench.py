@@ -163,10 +163,12 @@ def counter_traffic(kernel: str):
     return float(fields[key]) if fields and key in fields else None
 
 
-def step_traffic():
+def step_traffic(workload: str):
     """Measured HBM bytes per grid-point-step of a whole forward + adjoint of
-    the 48-instance workload (committed counter summary), or None."""
-    fields = _summary_fields("cfg4_step_counters_fetch_write.md")
+    the workload (committed counter summary: the 48-instance 2D batch or the
+    128^3 instance), or None."""
+    name = {"cfg4": "cfg4_step_counters_fetch_write.md", "cfg5": "cfg5_step_counters_fetch_write.md"}.get(workload)
+    fields = _summary_fields(name) if name else None
     return float(fields["traffic_bytes_per_gps"]) if fields and "traffic_bytes_per_gps" in fields else None
 
 
@@ -468,7 +470,7 @@ def main():
     if ndim == 3:
         names = {(0, 3): "row velocity", (0, 7): "row density", (0, 11): "row state+gather"}
     step_bytes = value * b_alg / 1e9  # algorithmic GB/s of the whole step
-    st_bpg = step_traffic() if args.workload == "cfg4" else None
+    st_bpg = step_traffic(args.workload)
     dom_name = names.get((tdir, tidx), f"{tdir}:{tidx}")
     dominant = {
         "kernel": dom_name,
