@@ -51,6 +51,27 @@ def test_small_parity(case):
     assert rel(img, ri) <= 1e-5
 
 
+@pytest.mark.parametrize("n", [(64, 32), (512, 16)], ids=["64x32", "512x16"])
+def test_line_array_parity(n):
+    """A line of sensors along x, one grid spacing apart: each row it crosses
+    carries more node groups of the adjoint's scatter than the row has lanes
+    (4 at 64 points, 32 at 512), so a lane adds several of the step's sums;
+    forward and adjoint against the oracle, eager and batched."""
+    inst = synth.small_instance(140 + n[0], n, nt=12, ns=4, pml=2, lossy=True)
+    dx = inst.desc.dx[0]
+    k = min(n[0] - 8, 40)
+    xs = 3.3 + np.arange(k, dtype=np.float64)
+    inst = replace(inst, sensors=np.stack([xs * dx, np.full(k, 7.6 * dx)], axis=1))
+    print("line array", n, k, flush=True)
+    plan, d, img, rd, ri, h = run_pair(inst)
+    assert rel(d, rd) <= 1e-5
+    assert rel(img, ri) <= 1e-5
+    b = pat.Batch([plan], chunk=4)
+    hb = torch.from_numpy(h).to(DEV)
+    assert torch.equal(b.adjoint([hb])[0].cpu(), torch.from_numpy(img))
+    b.close()
+
+
 def test_config1_parity_and_dot():
     inst = synth.config1()
     plan, d, img, rd, ri, h = run_pair(inst)
