@@ -142,9 +142,20 @@ __device__ __forceinline__ void gather_row(const DevPlan& P, int n, const float*
   if (valid) {
     const int e1 = gld(P.g_ptr, row + 1);
     float* out = P.partial + (long)n * P.nslots;
-    for (int e = gld(P.g_ptr, row) + t; e < e1; e += G::T) {
+    const int e = gld(P.g_ptr, row) + t;
+    if (e < e1) {
       const GTap tap = gld(P.g_tap, e);
       gst(out, tap.slot, fmaf(tap.w0, Lf[tap.x0], tap.w1 * Lf[tap.x0 + 1]));
+    }
+    // further taps four per round, their loads issued together (a row of a
+    // planar sensor holds a tap at every node: 16 per lane at 128 points)
+    for (int e0 = e + G::T; e0 < e1; e0 += 4 * G::T) {
+      GTap tp[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) tp[u] = gld(P.g_tap, e0 + u * G::T < e1 ? e0 + u * G::T : e0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u * G::T < e1) gst(out, tp[u].slot, fmaf(tp[u].w0, Lf[tp[u].x0], tp[u].w1 * Lf[tp[u].x0 + 1]));
     }
   }
   WaveSync::sync();
@@ -448,7 +459,20 @@ __device__ __forceinline__ void row_pass(const DevPlan& P, int tile, int it, flo
     WaveSync::sync();
     if (sx >= 0) {
       Lf[sx] += sv;
-      for (int g = sp0 + T; g < sp1; g += T) Lf[gld(P.s_grp, g).x] += gld(sc, g);
+      // the remaining groups four per round, their loads issued together
+      for (int g0 = sp0 + T; g0 < sp1; g0 += 4 * T) {
+        int gx[4];
+        float gs[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int g = g0 + u * T < sp1 ? g0 + u * T : sp0;
+          gx[u] = gld(P.s_grp, g).x;
+          gs[u] = gld(sc, g);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (g0 + u * T < sp1) Lf[gx[u]] += gs[u];
+      }
     }
     WaveSync::sync();
 #pragma unroll
